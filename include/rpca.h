@@ -1,0 +1,221 @@
+/*
+ * rpca.h -- C ABI of the MI355X (gfx950) randomized block-Lanczos PCA library.
+ *
+ * The method is the six-step algorithm of Halko, Martinsson, Shkolnisky and
+ * Tygert, "An algorithm for the principal component analysis of large data
+ * sets", Section 3 ("Summary of the algorithm"), run out-of-core the way
+ * Section 4 describes, with the data matrix A touched only by streaming
+ * products with tall, skinny blocks:
+ *
+ *   Step 1   H^(0) = A G,  H^(j) = A (A^T H^(j-1)), j = 1..i      (eqs. first_prod..last_prod)
+ *            H = [H^(0) | ... | H^(i)]                            (eq. product23)
+ *   Step 2   H = Q R, Q with (i+1) l orthonormal columns           (eq. good_approx23)
+ *   Step 3   T = A^T Q                                             (eq. product_t3)
+ *   Step 4   T = V~ S~ W^T, S~ non-increasing                      (eq. svd_small3)
+ *   Step 5   U~ = Q W                                              (eq. product33)
+ *   Step 6   U, S, V = leading k columns / k x k block
+ *
+ * so that ||A - U S V^T||_2 is close to sigma_{k+1} (eq. sort_of_svd).
+ *
+ * Conventions for every entry point:
+ *   - No call throws, aborts or exits; each returns an rpca_status.
+ *   - Matrices are row-major with an explicit leading dimension (elements).
+ *   - "device" pointers are HIP device memory of the plan's device;
+ *     "pinned host" pointers come from hipHostMalloc (or equivalent).
+ *   - The caller owns every pointer it passes; the plan owns its workspace
+ *     and frees it in rpca_destroy.  A plan is bound to one HIP stream and
+ *     must not be used from two threads at once.
+ *   - Calls that produce results block until those results are complete on
+ *     the plan's stream.
+ */
+#ifndef RPCA_H
+#define RPCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPCA_OK = 0,
+  RPCA_ERR_INVALID_ARG = 1,   /* a precondition below is violated */
+  RPCA_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+  RPCA_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed */
+  RPCA_ERR_HIP = 4,           /* a HIP runtime call failed; code in rpca_stats.hip_error */
+  RPCA_ERR_CALLBACK = 5,      /* the panel callback returned non-zero */
+  RPCA_ERR_NONFINITE = 6,     /* NaN or Inf met in the data or the iterates */
+  RPCA_ERR_QR_BREAKDOWN = 7,  /* H (or T) numerically rank deficient beyond the fallback */
+  RPCA_ERR_NO_STATE = 8       /* rpca_backward / rpca_get_state without a kept forward */
+} rpca_status;
+
+/* How A is stored.  Every format is row-major m x n with leading dimension lda.
+ *   F32        float
+ *   BF16       bfloat16 bit patterns (uint16_t)
+ *   FP8_E4M3   OCP e4m3 bytes (uint8_t); entry (r, c) is q(r, c) * col_scale[c]
+ *   BF16_HILO  two bfloat16 planes: hi at A, lo at A + m*lda; entry = hi + lo     */
+typedef enum {
+  RPCA_A_F32 = 0,
+  RPCA_A_BF16 = 1,
+  RPCA_A_FP8_E4M3 = 2,
+  RPCA_A_BF16_HILO = 3
+} rpca_storage;
+
+/* Where A lives (Section 4: storage on disk vs. on-the-fly evaluation).
+ *   DEVICE       A resident in HBM
+ *   HOST_PINNED  A in pinned host memory, streamed by row panels
+ *   CALLBACK     rows produced on demand by an rpca_panel_cb (Section 4.1)  */
+typedef enum {
+  RPCA_SRC_DEVICE = 0,
+  RPCA_SRC_HOST_PINNED = 1,
+  RPCA_SRC_CALLBACK = 2
+} rpca_source;
+
+enum {
+  RPCA_FLAG_KEEP_STATE = 1u << 0,  /* keep H, Q, R, T, W, ... for rpca_backward / rpca_get_state */
+  RPCA_FLAG_PROFILE = 1u << 1,     /* time every stage with HIP events (rpca_stats.ms_*) */
+  RPCA_FLAG_FORCE_FALLBACK = 1u << 2, /* take the shifted Cholesky-QR fallback for Step 2 */
+  RPCA_FLAG_NO_RESCALE = 1u << 3   /* do not rescale the power iterates (Section 3, overflow remark) */
+};
+
+typedef struct {
+  int64_t m, n;        /* A is m x n; this build requires m >= n (Section 3 assumes n <= m) */
+  int32_t k;           /* rank of the approximation, 1 <= k < n */
+  int32_t l;           /* block width, l >= k */
+  int32_t i;           /* power steps, i >= 0, with (i+1) l <= n - k (Section 3) */
+  int32_t storage;     /* rpca_storage */
+  int32_t source;      /* rpca_source */
+  int32_t center;      /* 1: factor A - 1 mu^T with mu the column means of A (Introduction) */
+  int64_t panel_rows;  /* rows per streamed panel for HOST_PINNED / CALLBACK; 0 = automatic */
+  uint64_t seed;       /* G from Philox4x32-10 + Box-Muller when rpca_factor gets G == NULL */
+  uint32_t flags;      /* RPCA_FLAG_* */
+  int32_t device;      /* HIP device ordinal the plan runs on */
+} rpca_desc;
+
+/* Fills rows [row0, row0+nrows) of A into dst (pinned host memory owned by the
+ * plan, leading dimension ld elements, in the plan's storage format).  For
+ * FP8_E4M3 the callback also writes the n column scales into col_scale on its
+ * first call (col_scale is NULL on later calls).  Returns 0 on success; any
+ * other value aborts rpca_factor with RPCA_ERR_CALLBACK.  Section 4.1: rows
+ * are evaluated on demand and every contribution of a row is made at once.  */
+typedef int (*rpca_panel_cb)(void* user, int64_t row0, int64_t nrows, void* dst, int64_t ld,
+                             float* col_scale);
+
+typedef struct rpca_plan_s* rpca_plan_t;
+
+/* Timing and counters of the last rpca_factor call (PROFILE adds the ms_* stages). */
+typedef struct {
+  double ms_total;       /* entry to results ready, host clock */
+  double ms_colmean;     /* column-mean pass (centering) */
+  double ms_power;       /* Step 1: all power passes */
+  double ms_qr;          /* Step 2 */
+  double ms_tpass;       /* Step 3 */
+  double ms_small_svd;   /* Step 4 */
+  double ms_assemble;    /* Steps 5-6 */
+  double ms_fwd_kernel;  /* summed duration of the A X panel kernels (event timed) */
+  double ms_adj_kernel;  /* summed duration of the A^T Z panel kernels (event timed) */
+  int64_t fwd_launches;  /* number of A X kernel launches timed above */
+  int64_t adj_launches;  /* number of A^T Z kernel launches timed above */
+  int64_t a_bytes_read;  /* bytes of A read by the panel kernels (algorithmic) */
+  int64_t h2d_bytes;     /* bytes of A moved host -> device (streamed sources) */
+  int32_t qr_fallback;   /* 1 when Step 2 took the shifted Cholesky-QR path */
+  int32_t jacobi_sweeps; /* sweeps the small eigensolver used */
+  int32_t hip_error;     /* raw hipError_t of the last RPCA_ERR_HIP */
+  int32_t passes;        /* full passes over A performed */
+} rpca_stats;
+
+/* Creates a plan for the problem in *desc, bound to hip_stream (a hipStream_t,
+ * NULL = the null stream) on desc->device, and allocates its workspace
+ * (O((i+1) l (m+n)) entries, Section 4: only Steps 1 and 3 touch A).
+ * Errors: INVALID_ARG when desc is NULL, out is NULL, m < n, or the Section 3
+ * parameter rules fail (1 <= k < n, l >= k, (i+1) l <= n - k, i >= 0);
+ * UNSUPPORTED for (i+1) l > 1024 or an unknown storage/source;
+ * OUT_OF_MEMORY / HIP when allocation fails.  On error *out is NULL.      */
+rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out);
+
+/* Computes U (m x k), S (k, non-increasing, >= 0) and V (n x k) of Steps 1-6.
+ *   A          DEVICE: device pointer; HOST_PINNED: pinned host pointer;
+ *              CALLBACK: ignored (may be NULL).  Format per desc->storage.
+ *   lda        leading dimension of A in elements (>= n).
+ *   col_scale  FP8_E4M3 only: n device floats (DEVICE) or host floats
+ *              (HOST_PINNED); NULL otherwise.
+ *   cb, user   CALLBACK source only.
+ *   G          n x l device floats (row-major, leading dimension l), the
+ *              Gaussian test matrix of Step 1; NULL = generate from desc->seed
+ *              with Philox4x32-10 (counter = element index r*l+c >> 1, stream 1,
+ *              key = seed) and Box-Muller, rounded to float.
+ *   U, ldu     device, m x k floats, ldu >= k.
+ *   S          device, k floats.
+ *   V, ldv     device, n x k floats, ldv >= k.
+ * Column j of U and V is signed so that the largest-magnitude entry of v_j is
+ * positive.  A is read (i+2) times (one fused pass A^T(A X) per power step,
+ * one A X pass, one A^T Q pass), plus one column-mean pass when centering.
+ * Errors: INVALID_ARG for NULL or misaligned pointers or short leading
+ * dimensions; CALLBACK; NONFINITE; QR_BREAKDOWN; HIP.                      */
+rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
+                        rpca_panel_cb cb, void* user, const float* G,
+                        float* U, int64_t ldu, float* S, float* V, int64_t ldv);
+
+/* Reverse-mode derivative of rpca_factor with G held fixed (the paper has no
+ * derivative; this is the exact adjoint of Steps 1-6 as computed).  Needs a
+ * preceding rpca_factor with RPCA_FLAG_KEEP_STATE and the same A still valid.
+ *   gS  (k), gU (m x k, ldgu), gV (n x k, ldgv): device cotangents of S, U, V
+ *       (any may be NULL = zero).
+ *   dA  (m x n, ldda): device floats receiving dL/dA.
+ * Errors: NO_STATE, INVALID_ARG, UNSUPPORTED (storage other than F32), HIP. */
+rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, int64_t ldgu,
+                          const float* gV, int64_t ldgv, float* dA, int64_t ldda);
+
+/* Appendix estimator p_{j,q}(D) of ||D||_2 for D = A~ - U S V^T (A~ = A, or
+ * A - 1 mu^T when the plan centres), with q start vectors of iid N(0,1)
+ * entries (Philox stream 9 under `seed`) and j power steps (the paper uses
+ * j = 6 and q = k).  U (m x k), S (k), V (n x k) are device floats as
+ * rpca_factor returns them; A as in rpca_factor (DEVICE source only).
+ * *estimate receives the estimate (host double).                          */
+rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
+                          const float* U, int64_t ldu, const float* S, const float* V, int64_t ldv,
+                          int32_t j, int32_t q, uint64_t seed, double* estimate);
+
+/* Quantises a device float matrix into the stored formats of rpca_storage:
+ *   BF16 / BF16_HILO: round-to-nearest-even; lo = bf16(a - hi).
+ *   FP8_E4M3: per-column scale c_j = max_r |a_rj| / 448 (1 when the column is
+ *   zero), q = e4m3(a / c_j) with round-to-nearest-even and saturation.
+ * out has m*ldo elements (2*m*ldo for BF16_HILO); col_scale n floats.      */
+rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda,
+                          void* out, int64_t ldo, float* col_scale, void* hip_stream);
+
+/* Intermediate results kept by KEEP_STATE (device copies into dst):
+ *   RPCA_STATE_H      m x L floats, the blocks H^(j) each multiplied by a
+ *                     positive scalar (rpca_get_state(RPCA_STATE_HSCALE))
+ *   RPCA_STATE_HSCALE i+1 doubles: the block scalars
+ *   RPCA_STATE_Q      m x L doubles (Step 2)
+ *   RPCA_STATE_T      n x L doubles (Step 3)
+ *   RPCA_STATE_SIGMA  L doubles, S~ of Step 4
+ *   RPCA_STATE_W      L x L doubles, W of Step 4 (columns in S~ order)
+ *   RPCA_STATE_MU     n doubles, column means (centering)
+ * ld is the destination leading dimension in elements (>= column count).   */
+enum {
+  RPCA_STATE_H = 0,
+  RPCA_STATE_HSCALE = 1,
+  RPCA_STATE_Q = 2,
+  RPCA_STATE_T = 3,
+  RPCA_STATE_SIGMA = 4,
+  RPCA_STATE_W = 5,
+  RPCA_STATE_MU = 6
+};
+rpca_status rpca_get_state(rpca_plan_t plan, int32_t which, void* dst, int64_t ld);
+
+/* Copies the statistics of the last call into *out. */
+rpca_status rpca_get_stats(rpca_plan_t plan, rpca_stats* out);
+
+/* Static description of a status code (never NULL). */
+const char* rpca_status_str(rpca_status s);
+
+/* Frees the plan and its workspace; NULL is ignored. */
+void rpca_destroy(rpca_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCA_H */

@@ -1,0 +1,125 @@
+// Host-side launch interface of the library's kernels (internal, not ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpca {
+
+// ---------------------------------------------------------------- panel products
+struct FwdArgs {              // Z = alpha ((A - 1 s^T) Xt^T - 1 corr^T)
+  const void* A = nullptr;    // m x n row-major, storage per kernel family
+  int64_t lda = 0, m = 0, n = 0;
+  const float* shift = nullptr;   // n (padded to x4, zero tail) or null
+  const float* Xt = nullptr;      // ncols x ldx (padded rows zero beyond n)
+  int64_t ldx = 0;
+  int ncols = 0;
+  const float* corr = nullptr;    // ncols or null
+  const double* alpha = nullptr;  // device scalar or null
+  float* Z = nullptr;
+  int64_t ldz = 0;
+  bool vec = false;               // A 16-byte aligned and lda % 4 == 0
+  // low-precision storage extras
+  const float* col_scale = nullptr;  // FP8: n scales (padded)
+  int64_t plane = 0;                 // BF16_HILO: elements between hi and lo planes
+};
+
+struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
+  const void* A = nullptr;
+  int64_t lda = 0, m = 0, n = 0;
+  const float* shift = nullptr;
+  const float* Z = nullptr;       // m x ncols (ldz)
+  int64_t ldz = 0;
+  int ncols = 0;
+  int64_t rows_per_split = 0;     // multiple of 4
+  int nsplit = 0;
+  float* P = nullptr;             // [nsplit][ncols][ldp]
+  int64_t ldp = 0, split_stride = 0;
+  bool vec = false;
+  const float* col_scale = nullptr;
+  int64_t plane = 0;
+};
+
+hipError_t launch_fwd_f32(const FwdArgs& a, hipStream_t st);
+int adj_nt_for(int ncols);  // 16-column tiles per wave used by the adjoint kernels
+hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st);
+hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st);
+hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st);
+
+// ---------------------------------------------------------------- auxiliary
+// FP64 column sums of a row-major matrix in a given storage: part[s][c] over row splits.
+hipError_t launch_colsum(int storage, const void* X, int64_t ld, int64_t rows, int64_t cols,
+                         const float* col_scale, int64_t plane, int64_t rows_per_split, int nsplit,
+                         double* part, hipStream_t st);
+// out[c] = scale * sum_s part[s][c]; optional fl32 copy and residual d = out - fl32(out).
+hipError_t launch_colsum_reduce(const double* part, int nsplit, int64_t cols, double scale, double* out,
+                                float* out_f32, double* resid, hipStream_t st);
+// Xt[c][r] = normal(seed, stream 1, r*l + c) rounded to float (G of Step 1).
+hipError_t launch_gen_G(uint64_t seed, int64_t n, int l, float* Xt, int64_t ldx, hipStream_t st);
+// Xt[c][r] = G[r][c]
+hipError_t launch_transpose_G(const float* G, int64_t ldg, int64_t n, int l, float* Xt, int64_t ldx,
+                              hipStream_t st);
+// corr[j] = sum_c d[c] Xt[j][c]
+hipError_t launch_dot_rows(const double* d, const float* Xt, int64_t ldx, int64_t n, int ncols, float* corr,
+                           hipStream_t st);
+// Xt[j][c] = sum_s P[s][j][c] - d[c] zsum[j]; per-block sums of squares into sq_part
+hipError_t launch_reduce_y(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
+                           const double* d, const double* zsum, float* Xt, int64_t ldx, double* sq_part,
+                           int* n_sq_part, hipStream_t st);
+// alpha = 1/sqrt(sum of sq_part) (1 when zero or rescaling is off); nonfinite flag
+hipError_t launch_finish_scale(const double* sq_part, int n_part, bool rescale, double* alpha, int* flag,
+                               hipStream_t st);
+// T[c][j] = sum_s P[s][j][c] - d[c] qsum[j]  (T row-major n x ncols, FP64)
+hipError_t launch_reduce_t(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
+                           const double* d, const double* qsum, double* T, int64_t ldt, hipStream_t st);
+// flag |= nonfinite(x) over a float matrix
+hipError_t launch_check_finite_f32(const float* X, int64_t rows, int64_t cols, int64_t ld, int* flag,
+                                   hipStream_t st);
+hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t st);
+// out[r][c] = X[r][c] - colsum[c] * inv_rows, float64 (projects the column sums out)
+hipError_t launch_center_cols(const float* X, int64_t ldx, int64_t rows, int64_t cols, const double* colsum,
+                              double inv_rows, double* out, int64_t ldo, hipStream_t st);
+
+// ---------------------------------------------------------------- small FP64 algebra
+// part[s][i][j] = sum over rows of split s of X[r][i] X[r][j]
+hipError_t launch_gram(bool x_is_f64, const void* X, int64_t ldx, int64_t rows, int L, int64_t rows_per_split,
+                       int nsplit, double* part, hipStream_t st);
+// W = sum_s part[s] (+ shift * I when shift_from_trace: shift = coef * trace)
+hipError_t launch_gram_reduce(const double* part, int nsplit, int L, double* W, double shift_coef,
+                              hipStream_t st);
+// per-workgroup LDS limit used to pick LDS-resident variants of the single-workgroup kernels
+void set_max_lds(size_t bytes);
+// W (L x L) -> upper R with W = R^T R in place; flag set on breakdown
+hipError_t launch_cholesky(double* W, int L, double rel_tol, int* flag, hipStream_t st);
+// Rinv = R^-1 (upper)
+hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st);
+// C = A B (A: M x K float or double, B: K x N double), optional upper-triangular B,
+// column scale, FP64 and/or FP32 outputs
+hipError_t launch_gemm64(bool a_is_f64, const void* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                         int N, int K, bool b_upper, const double* colscale, double* C, int64_t ldc, float* C32,
+                         int64_t ldc32, hipStream_t st);
+// C (L x L) = A (L x L upper) * B (L x L upper)
+hipError_t launch_trmm_upper(const double* A, const double* B, int L, double* C, hipStream_t st);
+
+// symmetric eigen-decomposition by one-sided block Jacobi on M (L x L): on exit
+// B holds M V (columns), V the eigenvectors; rot_count[sweep] the rotations done
+struct JacobiPlan {
+  int L = 0, nb = 0, nblk = 0;  // block width and (even) block count
+  size_t lds_bytes = 0;
+};
+JacobiPlan jacobi_plan(int L);
+hipError_t launch_jacobi_init(const double* M, int L, double* B, double* V, int* rot_count, int max_sweeps,
+                              hipStream_t st);
+hipError_t launch_jacobi_round(const JacobiPlan& jp, double* B, double* V, int sweep, int round, int* rot_count,
+                               double tol, hipStream_t st);
+// lam[j] = ||B[:,j]||, order = permutation sorting lam descending (ties by index)
+hipError_t launch_jacobi_finish(const double* B, const double* V, int L, double* lam, int* order, double* Wsorted,
+                                double* sig_sorted, hipStream_t st);
+// V[:, j] /= ||V[:, j]|| and sign so the largest |entry| is positive; sig[j] = norm; sgn[j] = sign
+hipError_t launch_normalize_sign(double* V, int64_t rows, int k, int64_t ldv, double* sig, double* sgn,
+                                 hipStream_t st);
+// out32[r][j] = (float) (X[r][j] * colscale[j])
+hipError_t launch_to_f32(const double* X, int64_t rows, int cols, int64_t ldx, const double* colscale,
+                         float* out, int64_t ldo, hipStream_t st);
+
+}  // namespace rpca

@@ -1,0 +1,676 @@
+// C ABI and host orchestration of the randomized block-Lanczos PCA
+// (Section 3, Steps 1-6; Section 4 out-of-core structure).  Every arithmetic
+// step runs in the library's HIP kernels; the host only validates, sizes the
+// workspace, launches, and makes the one decision that needs a value from
+// the device (whether Step 2 must take its fallback).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rpca.h"
+#include "kernels.h"
+#include "storage.h"
+
+using namespace rpca;
+
+namespace {
+
+struct DevGuard {
+  int prev = -1;
+  explicit DevGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DevGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct rpca_plan_s {
+  rpca_desc d{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t m = 0, n = 0;
+  int k = 0, l = 0, i = 0, L = 0;
+  int64_t ldx = 0;  // row stride of transposed blocks (n rounded up to 4)
+  int64_t ldp = 0;  // row stride of split partials
+  size_t max_lds = 65536;
+
+  // split configuration of the adjoint products
+  int ns_y = 1, ns_t = 1;
+  int64_t rps_y = 0, rps_t = 0;
+  int ns_cs = 1;  // column-sum splits over A
+  int64_t rps_cs = 0;
+  int ns_g = 1;   // Gram splits over H / Q rows
+  int64_t rps_g = 0;
+  int ns_gt = 1;  // Gram splits over T rows
+  int64_t rps_gt = 0;
+  JacobiPlan jp;
+  int max_sweeps = 40;
+
+  std::vector<void*> allocs;
+  // device buffers
+  float* X = nullptr;       // (i+1) blocks of l x ldx (transposed X_j, X_0 = G)
+  float* shift = nullptr;   // ldx
+  double* mu = nullptr;     // n
+  double* dres = nullptr;   // n: mu - fl32(mu)
+  float* H = nullptr;       // m x L
+  double* Q1 = nullptr;     // m x L
+  double* Q = nullptr;      // m x L
+  float* Q32 = nullptr;     // m x L
+  float* P = nullptr;       // partials
+  double* T = nullptr;      // n x L
+  double* csp = nullptr;    // column-sum partials
+  double* gp = nullptr;     // Gram partials
+  double* Wg = nullptr;     // L x L Gram
+  double* R1 = nullptr;     // L x L
+  double* R2 = nullptr;
+  double* R3 = nullptr;
+  double* Rtmp = nullptr;
+  double* Rfull = nullptr;
+  double* Rinv = nullptr;
+  double* Mg = nullptr;     // T^T T
+  double* JB = nullptr;     // Jacobi columns
+  double* JV = nullptr;     // Jacobi vectors
+  double* lam = nullptr;
+  int* order = nullptr;
+  double* Wsorted = nullptr;
+  double* sigL = nullptr;   // eigenvalue order
+  double* Vk = nullptr;     // n x k
+  double* sig = nullptr;    // k
+  double* sgn = nullptr;    // k
+  double* alpha = nullptr;  // i+1
+  double* zsum = nullptr;   // L
+  double* sqp = nullptr;    // sum of squares partials
+  float* corr = nullptr;    // L
+  int* flags = nullptr;     // [0] nonfinite, [1] chol breakdown round 1, [2] round 2, [3] round 3
+  int* rot = nullptr;       // max_sweeps
+  int64_t sqp_cap = 0;
+
+  bool have_state = false;
+  bool Qfinal_is_Q1 = false;
+  rpca_stats stats{};
+  std::vector<EventPair> ev_fwd, ev_adj;
+  int nev_fwd = 0, nev_adj = 0;
+
+  ~rpca_plan_s() {
+    DevGuard g(device);
+    for (void* p : allocs) (void)hipFree(p);
+    for (auto& e : ev_fwd) {
+      if (e.a) (void)hipEventDestroy(e.a);
+      if (e.b) (void)hipEventDestroy(e.b);
+    }
+    for (auto& e : ev_adj) {
+      if (e.a) (void)hipEventDestroy(e.a);
+      if (e.b) (void)hipEventDestroy(e.b);
+    }
+  }
+
+  template <typename T>
+  hipError_t alloc(T** p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    *p = reinterpret_cast<T*>(q);
+    return hipSuccess;
+  }
+};
+
+#define RPCA_TRY(expr)                                  \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) {                             \
+      plan->stats.hip_error = (int32_t)e_;              \
+      (void)hipGetLastError();                          \
+      return e_ == hipErrorOutOfMemory ? RPCA_ERR_OUT_OF_MEMORY : RPCA_ERR_HIP; \
+    }                                                   \
+  } while (0)
+
+namespace {
+
+// Section 3 parameter rules (reading: enforce l >= k and (i+1) l <= n - k).
+rpca_status validate_desc(const rpca_desc* d) {
+  if (d == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (d->m <= 0 || d->n <= 0 || d->m < d->n) return RPCA_ERR_INVALID_ARG;
+  if (d->k < 1 || (int64_t)d->k >= d->n) return RPCA_ERR_INVALID_ARG;
+  if (d->l < d->k || d->i < 0) return RPCA_ERR_INVALID_ARG;
+  if ((int64_t)(d->i + 1) * d->l > d->n - d->k) return RPCA_ERR_INVALID_ARG;
+  if (d->storage < RPCA_A_F32 || d->storage > RPCA_A_BF16_HILO) return RPCA_ERR_UNSUPPORTED;
+  if (d->source < RPCA_SRC_DEVICE || d->source > RPCA_SRC_CALLBACK) return RPCA_ERR_UNSUPPORTED;
+  if ((int64_t)(d->i + 1) * d->l > 1024) return RPCA_ERR_UNSUPPORTED;
+  return RPCA_OK;
+}
+
+// Choose the row splits of an adjoint product so that the grid holds about
+// `target` blocks, with at least 64 rows per split.
+void choose_splits(int64_t m, int64_t n, int ncols, int64_t target, int* ns, int64_t* rps) {
+  const int nt = adj_nt_for(ncols);
+  const int64_t jtiles = (ncols + 16 * nt - 1) / (16 * nt);
+  const int64_t ctiles = (n + 255) / 256;
+  int64_t s = (target + jtiles * ctiles - 1) / (jtiles * ctiles);
+  const int64_t smax = std::max<int64_t>(1, m / 64);
+  s = std::max<int64_t>(1, std::min(s, smax));
+  int64_t r = round_up((m + s - 1) / s, 4);
+  s = (m + r - 1) / r;
+  *ns = (int)s;
+  *rps = r;
+}
+
+void choose_rows(int64_t rows, int64_t per, int maxs, int* ns, int64_t* rps) {
+  int64_t s = std::max<int64_t>(1, std::min<int64_t>(maxs, (rows + per - 1) / per));
+  int64_t r = round_up((rows + s - 1) / s, 16);
+  s = (rows + r - 1) / r;
+  *ns = (int)std::max<int64_t>(1, s);
+  *rps = std::max<int64_t>(r, 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rpca_status_str(rpca_status s) {
+  switch (s) {
+    case RPCA_OK: return "ok";
+    case RPCA_ERR_INVALID_ARG: return "invalid argument";
+    case RPCA_ERR_UNSUPPORTED: return "unsupported";
+    case RPCA_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RPCA_ERR_HIP: return "HIP runtime error";
+    case RPCA_ERR_CALLBACK: return "panel callback failed";
+    case RPCA_ERR_NONFINITE: return "non-finite value in data or iterates";
+    case RPCA_ERR_QR_BREAKDOWN: return "QR breakdown (numerically rank-deficient block)";
+    case RPCA_ERR_NO_STATE: return "no kept forward state";
+  }
+  return "unknown status";
+}
+
+void rpca_destroy(rpca_plan_t plan) { delete plan; }
+
+rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out) {
+  if (out == nullptr) return RPCA_ERR_INVALID_ARG;
+  *out = nullptr;
+  rpca_status vs = validate_desc(desc);
+  if (vs != RPCA_OK) return vs;
+  if (desc->source != RPCA_SRC_DEVICE) return RPCA_ERR_UNSUPPORTED;
+  if (desc->storage != RPCA_A_F32) return RPCA_ERR_UNSUPPORTED;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev) {
+    (void)hipGetLastError();
+    return RPCA_ERR_INVALID_ARG;
+  }
+  rpca_plan_s* plan = new (std::nothrow) rpca_plan_s();
+  if (plan == nullptr) return RPCA_ERR_OUT_OF_MEMORY;
+  plan->d = *desc;
+  plan->device = desc->device;
+  plan->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  DevGuard g(plan->device);
+  auto fail = [&](rpca_status s) {
+    delete plan;
+    return s;
+  };
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, plan->device) != hipSuccess) return fail(RPCA_ERR_HIP);
+  plan->max_lds = prop.sharedMemPerBlock;
+  set_max_lds(plan->max_lds);
+
+  const int64_t m = desc->m, n = desc->n;
+  const int k = desc->k, l = desc->l, i = desc->i, L = (i + 1) * l;
+  plan->m = m;
+  plan->n = n;
+  plan->k = k;
+  plan->l = l;
+  plan->i = i;
+  plan->L = L;
+  plan->ldx = round_up(n, 4);
+  plan->ldp = round_up(n, 4);
+
+  const int64_t target = 2048;
+  choose_splits(m, n, l, target, &plan->ns_y, &plan->rps_y);
+  choose_splits(m, n, L, target, &plan->ns_t, &plan->rps_t);
+  choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
+  choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
+  choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
+  plan->jp = jacobi_plan(L);
+  while (plan->jp.lds_bytes > plan->max_lds && plan->jp.nb > 1) {
+    // shrink the column blocks until a block pair fits the workgroup's LDS
+    JacobiPlan jp = plan->jp;
+    jp.nb = jp.nb - 1;
+    int nblk = (L + jp.nb - 1) / jp.nb;
+    if (nblk < 2) nblk = 2;
+    if (nblk & 1) ++nblk;
+    jp.nblk = nblk;
+    jp.lds_bytes = (size_t)2 * jp.nb * L * 2 * sizeof(double);
+    plan->jp = jp;
+  }
+  if (plan->jp.lds_bytes > plan->max_lds) return fail(RPCA_ERR_UNSUPPORTED);
+
+  const int64_t ldx = plan->ldx;
+  const int64_t pcount =
+      std::max<int64_t>((int64_t)plan->ns_y * l, (int64_t)plan->ns_t * L) * plan->ldp;
+  const int64_t LL = (int64_t)L * L;
+  plan->sqp_cap = ((n + 255) / 256) * (int64_t)std::max(l, 1) + 16;
+  hipError_t e = hipSuccess;
+#define ALLOC(ptr, cnt)                                                    \
+  do {                                                                     \
+    e = plan->alloc(&plan->ptr, (cnt));                                    \
+    if (e != hipSuccess)                                                   \
+      return fail(e == hipErrorOutOfMemory ? RPCA_ERR_OUT_OF_MEMORY : RPCA_ERR_HIP); \
+  } while (0)
+  ALLOC(X, (int64_t)(i + 1) * l * ldx);
+  ALLOC(shift, ldx);
+  ALLOC(mu, n);
+  ALLOC(dres, n);
+  ALLOC(H, m * L);
+  ALLOC(Q1, m * L);
+  ALLOC(Q, m * L);
+  ALLOC(Q32, m * L);
+  ALLOC(P, pcount);
+  ALLOC(T, n * L);
+  ALLOC(csp, (int64_t)plan->ns_cs * ldx + (int64_t)plan->ns_cs * L);
+  ALLOC(gp, (int64_t)std::max(plan->ns_g, plan->ns_gt) * LL);
+  ALLOC(Wg, LL);
+  ALLOC(R1, LL);
+  ALLOC(R2, LL);
+  ALLOC(R3, LL);
+  ALLOC(Rtmp, LL);
+  ALLOC(Rfull, LL);
+  ALLOC(Rinv, LL);
+  ALLOC(Mg, LL);
+  ALLOC(JB, LL);
+  ALLOC(JV, LL);
+  ALLOC(lam, L);
+  ALLOC(order, L);
+  ALLOC(Wsorted, LL);
+  ALLOC(sigL, L);
+  ALLOC(Vk, n * k);
+  ALLOC(sig, k);
+  ALLOC(sgn, k);
+  ALLOC(alpha, i + 1);
+  ALLOC(zsum, L);
+  ALLOC(sqp, plan->sqp_cap);
+  ALLOC(corr, L);
+  ALLOC(flags, 8);
+  ALLOC(rot, plan->max_sweeps);
+#undef ALLOC
+  // zero the padded transposed blocks and the shift once (padding must stay 0)
+  if (hipMemset(plan->X, 0, sizeof(float) * (size_t)(i + 1) * l * ldx) != hipSuccess ||
+      hipMemset(plan->shift, 0, sizeof(float) * (size_t)ldx) != hipSuccess ||
+      hipMemset(plan->P, 0, sizeof(float) * (size_t)pcount) != hipSuccess)
+    return fail(RPCA_ERR_HIP);
+  if (hipDeviceSynchronize() != hipSuccess) return fail(RPCA_ERR_HIP);
+  plan->ev_fwd.resize(16);
+  plan->ev_adj.resize(16);
+  for (auto* vec : {&plan->ev_fwd, &plan->ev_adj})
+    for (auto& ev : *vec)
+      if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return fail(RPCA_ERR_HIP);
+  *out = plan;
+  return RPCA_OK;
+}
+
+rpca_status rpca_get_stats(rpca_plan_t plan, rpca_stats* out) {
+  if (plan == nullptr || out == nullptr) return RPCA_ERR_INVALID_ARG;
+  *out = plan->stats;
+  return RPCA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipError_t record_fwd(rpca_plan_s* plan, bool begin) {
+  if (!(plan->d.flags & RPCA_FLAG_PROFILE)) return hipSuccess;
+  if (plan->nev_fwd >= (int)plan->ev_fwd.size()) return hipSuccess;
+  EventPair& p = plan->ev_fwd[plan->nev_fwd];
+  if (begin) return hipEventRecord(p.a, plan->stream);
+  hipError_t e = hipEventRecord(p.b, plan->stream);
+  ++plan->nev_fwd;
+  return e;
+}
+
+hipError_t record_adj(rpca_plan_s* plan, bool begin) {
+  if (!(plan->d.flags & RPCA_FLAG_PROFILE)) return hipSuccess;
+  if (plan->nev_adj >= (int)plan->ev_adj.size()) return hipSuccess;
+  EventPair& p = plan->ev_adj[plan->nev_adj];
+  if (begin) return hipEventRecord(p.a, plan->stream);
+  hipError_t e = hipEventRecord(p.b, plan->stream);
+  ++plan->nev_adj;
+  return e;
+}
+
+// One CholQR round: W = X^T X (+ shift), R = chol(W), Xout = X R^-1.
+rpca_status cholqr_round(rpca_plan_s* plan, bool x_f64, const void* X, double* Xout, float* Xout32, double* R,
+                         double shift_coef, int* flag) {
+  const int L = plan->L;
+  const int64_t m = plan->m;
+  hipStream_t st = plan->stream;
+  RPCA_TRY(launch_gram(x_f64, X, L, m, L, plan->rps_g, plan->ns_g, plan->gp, st));
+  RPCA_TRY(launch_gram_reduce(plan->gp, plan->ns_g, L, R, shift_coef, st));
+  RPCA_TRY(launch_cholesky(R, L, 1e-14, flag, st));
+  RPCA_TRY(launch_triinv(R, L, plan->Rinv, st));
+  RPCA_TRY(launch_gemm64(x_f64, X, L, plan->Rinv, L, m, L, L, true, nullptr, Xout, L, Xout32, L, st));
+  return RPCA_OK;
+}
+
+}  // namespace
+
+extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
+                                   rpca_panel_cb cb, void* user, const float* G, float* U, int64_t ldu, float* S,
+                                   float* V, int64_t ldv) {
+  (void)col_scale;
+  (void)cb;
+  (void)user;
+  if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
+  const int64_t m = plan->m, n = plan->n;
+  const int k = plan->k, l = plan->l, i = plan->i, L = plan->L;
+  if (A == nullptr || U == nullptr || S == nullptr || V == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (lda < n || ldu < k || ldv < k) return RPCA_ERR_INVALID_ARG;
+  DevGuard g(plan->device);
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t st = plan->stream;
+  rpca_stats& sx = plan->stats;
+  sx = rpca_stats{};
+  plan->have_state = false;
+  plan->nev_fwd = plan->nev_adj = 0;
+  const bool center = plan->d.center != 0;
+  const bool rescale = !(plan->d.flags & RPCA_FLAG_NO_RESCALE);
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0);
+  const int64_t ldx = plan->ldx;
+  const int64_t bpe = 4;  // bytes per stored element (F32)
+
+  RPCA_TRY(hipMemsetAsync(plan->flags, 0, 8 * sizeof(int), st));
+
+  // centring: mu = column means (FP64), shift = fl32(mu), d = mu - shift.
+  // The panel kernels always read a shift vector: without centring it is the
+  // plan's zero-filled buffer (never written for such a plan).
+  const float* shift = plan->shift;
+  const double* dres = nullptr;
+  if (center) {
+    RPCA_TRY(launch_colsum(ST_F32, A, lda, m, n, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
+    RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, n, 1.0 / (double)m, plan->mu, plan->shift, plan->dres,
+                                  st));
+    dres = plan->dres;
+    sx.passes += 1;
+    sx.a_bytes_read += m * n * bpe;
+  }
+
+  // Step 1: X_0 = G
+  float* X0 = plan->X;
+  if (G != nullptr)
+    RPCA_TRY(launch_transpose_G(G, l, n, l, X0, ldx, st));
+  else
+    RPCA_TRY(launch_gen_G(plan->d.seed, n, l, X0, ldx, st));
+  RPCA_TRY(launch_fill_f64(plan->alpha, i + 1, 1.0, st));
+
+  for (int j = 0; j <= i; ++j) {
+    float* Xj = plan->X + (int64_t)j * l * ldx;
+    if (center) RPCA_TRY(launch_dot_rows(dres, Xj, ldx, n, l, plan->corr, st));
+    FwdArgs fa;
+    fa.A = A;
+    fa.lda = lda;
+    fa.m = m;
+    fa.n = n;
+    fa.shift = shift;
+    fa.Xt = Xj;
+    fa.ldx = ldx;
+    fa.ncols = l;
+    fa.corr = center ? plan->corr : nullptr;
+    fa.alpha = plan->alpha + j;
+    fa.Z = plan->H + (int64_t)j * l;
+    fa.ldz = L;
+    fa.vec = vec;
+    RPCA_TRY(record_fwd(plan, true));
+    RPCA_TRY(launch_fwd_f32(fa, st));
+    RPCA_TRY(record_fwd(plan, false));
+    sx.passes += 1;
+    sx.a_bytes_read += m * n * bpe;
+    if (j == i) break;
+    // fused half of the pass: X_{j+1} = A~^T H^(j)
+    if (center)
+      RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cs, plan->ns_cs,
+                             plan->csp, st));
+    if (center) RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, l, 1.0, plan->zsum, nullptr, nullptr, st));
+    AdjArgs aa;
+    aa.A = A;
+    aa.lda = lda;
+    aa.m = m;
+    aa.n = n;
+    aa.shift = shift;
+    aa.Z = plan->H + (int64_t)j * l;
+    aa.ldz = L;
+    aa.ncols = l;
+    aa.rows_per_split = plan->rps_y;
+    aa.nsplit = plan->ns_y;
+    aa.P = plan->P;
+    aa.ldp = plan->ldp;
+    aa.split_stride = (int64_t)l * plan->ldp;
+    aa.vec = vec;
+    RPCA_TRY(record_adj(plan, true));
+    RPCA_TRY(launch_adj_f32(aa, st));
+    RPCA_TRY(record_adj(plan, false));
+    float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
+    int npart = 0;
+    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, dres,
+                             center ? plan->zsum : nullptr, Xn, ldx, plan->sqp, &npart, st));
+    RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
+  }
+  RPCA_TRY(launch_check_finite_f32(plan->H, m, L, L, plan->flags, st));
+  const auto t_power = std::chrono::steady_clock::now();
+
+  // Step 2: Cholesky QR twice (shifted Cholesky QR three times as fallback)
+  bool fallback = (plan->d.flags & RPCA_FLAG_FORCE_FALLBACK) != 0;
+  double* Qfinal = nullptr;
+  // With centring every exact block A~ X_j has zero column sums; the float32
+  // rounding of H leaves a component along 1 that the conditioning of H would
+  // amplify inside span(Q), so it is removed in float64 before the QR (a no-op
+  // in exact arithmetic).
+  const bool x_f64 = center;
+  const void* Hqr = center ? static_cast<const void*>(plan->Q) : static_cast<const void*>(plan->H);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 3 * sizeof(int), st));
+    if (center) {
+      RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, L, 1.0, plan->zsum, nullptr, nullptr, st));
+      RPCA_TRY(launch_center_cols(plan->H, L, m, L, plan->zsum, 1.0 / (double)m, plan->Q, L, st));
+    }
+    rpca_status s;
+    if (!fallback) {
+      s = cholqr_round(plan, x_f64, Hqr, plan->Q1, nullptr, plan->R1, 0.0, plan->flags + 1);
+      if (s != RPCA_OK) return s;
+      s = cholqr_round(plan, true, plan->Q1, plan->Q, plan->Q32, plan->R2, 0.0, plan->flags + 2);
+      if (s != RPCA_OK) return s;
+      Qfinal = plan->Q;
+    } else {
+      // shift = 11 (m L + L (L+1)) u ||H||_F^2 (shifted Cholesky QR)
+      const double u = 1.1102230246251565e-16;
+      const double coef = 11.0 * ((double)m * L + (double)L * (L + 1)) * u;
+      s = cholqr_round(plan, x_f64, Hqr, plan->Q1, nullptr, plan->R1, coef, plan->flags + 1);
+      if (s != RPCA_OK) return s;
+      s = cholqr_round(plan, true, plan->Q1, plan->Q, nullptr, plan->R2, 0.0, plan->flags + 2);
+      if (s != RPCA_OK) return s;
+      s = cholqr_round(plan, true, plan->Q, plan->Q1, plan->Q32, plan->R3, 0.0, plan->flags + 3);
+      if (s != RPCA_OK) return s;
+      Qfinal = plan->Q1;
+    }
+    int hf[4] = {0, 0, 0, 0};
+    RPCA_TRY(hipMemcpyAsync(hf, plan->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    RPCA_TRY(hipStreamSynchronize(st));
+    if (hf[0] != 0) return RPCA_ERR_NONFINITE;
+    const bool broke = hf[1] != 0 || hf[2] != 0 || hf[3] != 0;
+    if (!broke) break;
+    if (fallback) return RPCA_ERR_QR_BREAKDOWN;
+    fallback = true;
+  }
+  sx.qr_fallback = fallback ? 1 : 0;
+  const auto t_qr = std::chrono::steady_clock::now();
+
+  // Step 3: T = A~^T Q  (n x L, FP64 after the ordered split reduction)
+  if (center) {
+    RPCA_TRY(launch_colsum(ST_F32, plan->Q32, L, m, L, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
+    RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, L, 1.0, plan->zsum, nullptr, nullptr, st));
+  }
+  {
+    AdjArgs aa;
+    aa.A = A;
+    aa.lda = lda;
+    aa.m = m;
+    aa.n = n;
+    aa.shift = shift;
+    aa.Z = plan->Q32;
+    aa.ldz = L;
+    aa.ncols = L;
+    aa.rows_per_split = plan->rps_t;
+    aa.nsplit = plan->ns_t;
+    aa.P = plan->P;
+    aa.ldp = plan->ldp;
+    aa.split_stride = (int64_t)L * plan->ldp;
+    aa.vec = vec;
+    RPCA_TRY(record_adj(plan, true));
+    RPCA_TRY(launch_adj_f32(aa, st));
+    RPCA_TRY(record_adj(plan, false));
+    RPCA_TRY(launch_reduce_t(plan->P, plan->ns_t, aa.split_stride, plan->ldp, L, n, dres,
+                             center ? plan->zsum : nullptr, plan->T, L, st));
+    sx.passes += 1;
+    sx.a_bytes_read += m * n * bpe;
+  }
+  RPCA_TRY(hipStreamSynchronize(st));
+  const auto t_tpass = std::chrono::steady_clock::now();
+
+  // Step 4: T^T T = W diag(S~^2) W^T by block Jacobi
+  RPCA_TRY(launch_gram(true, plan->T, L, n, L, plan->rps_gt, plan->ns_gt, plan->gp, st));
+  RPCA_TRY(launch_gram_reduce(plan->gp, plan->ns_gt, L, plan->Mg, 0.0, st));
+  RPCA_TRY(launch_jacobi_init(plan->Mg, L, plan->JB, plan->JV, plan->rot, plan->max_sweeps, st));
+  const double tol = (double)L * 2.220446049250313e-16;
+  int sweeps_done = 0;
+  {
+    std::vector<int> hrot(plan->max_sweeps, 0);
+    int next_check = 6;
+    for (int sw = 0; sw < plan->max_sweeps; ++sw) {
+      for (int r = 0; r < plan->jp.nblk - 1; ++r)
+        RPCA_TRY(launch_jacobi_round(plan->jp, plan->JB, plan->JV, sw, r, plan->rot, tol, st));
+      sweeps_done = sw + 1;
+      if (sweeps_done == next_check || sweeps_done == plan->max_sweeps) {
+        RPCA_TRY(hipMemcpyAsync(hrot.data(), plan->rot, sizeof(int) * sweeps_done, hipMemcpyDeviceToHost, st));
+        RPCA_TRY(hipStreamSynchronize(st));
+        bool conv = false;
+        for (int q = 0; q < sweeps_done; ++q)
+          if (hrot[q] == 0) {
+            conv = true;
+            sweeps_done = q + 1;
+            break;
+          }
+        if (conv) break;
+        next_check += 2;
+      }
+    }
+  }
+  sx.jacobi_sweeps = sweeps_done;
+  RPCA_TRY(launch_jacobi_finish(plan->JB, plan->JV, L, plan->lam, plan->order, plan->Wsorted, plan->sigL, st));
+  RPCA_TRY(hipStreamSynchronize(st));
+  const auto t_svd = std::chrono::steady_clock::now();
+
+  // Steps 5-6: V = T W_k / ||T W_k|| (signed), S = ||T W_k||, U = Q W_k (signed)
+  RPCA_TRY(launch_gemm64(true, plan->T, L, plan->Wsorted, L, n, k, L, false, nullptr, plan->Vk, k, nullptr, 0, st));
+  RPCA_TRY(launch_normalize_sign(plan->Vk, n, k, k, plan->sig, plan->sgn, st));
+  RPCA_TRY(launch_gemm64(true, Qfinal, L, plan->Wsorted, L, m, k, L, false, plan->sgn, nullptr, 0, U, ldu, st));
+  RPCA_TRY(launch_to_f32(plan->Vk, n, k, k, nullptr, V, ldv, st));
+  RPCA_TRY(launch_to_f32(plan->sig, 1, k, k, nullptr, S, k, st));
+  RPCA_TRY(hipStreamSynchronize(st));
+  const auto t_end = std::chrono::steady_clock::now();
+
+  auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+  };
+  sx.ms_total = ms(t0, t_end);
+  sx.ms_power = ms(t0, t_power);
+  sx.ms_qr = ms(t_power, t_qr);
+  sx.ms_tpass = ms(t_qr, t_tpass);
+  sx.ms_small_svd = ms(t_tpass, t_svd);
+  sx.ms_assemble = ms(t_svd, t_end);
+  if (plan->d.flags & RPCA_FLAG_PROFILE) {
+    for (int q = 0; q < plan->nev_fwd; ++q) {
+      float t = 0.f;
+      RPCA_TRY(hipEventElapsedTime(&t, plan->ev_fwd[q].a, plan->ev_fwd[q].b));
+      sx.ms_fwd_kernel += t;
+    }
+    for (int q = 0; q < plan->nev_adj; ++q) {
+      float t = 0.f;
+      RPCA_TRY(hipEventElapsedTime(&t, plan->ev_adj[q].a, plan->ev_adj[q].b));
+      sx.ms_adj_kernel += t;
+    }
+    sx.fwd_launches = plan->nev_fwd;
+    sx.adj_launches = plan->nev_adj;
+  }
+  plan->have_state = true;
+  plan->Qfinal_is_Q1 = (Qfinal == plan->Q1);
+  return RPCA_OK;
+}
+
+extern "C" rpca_status rpca_get_state(rpca_plan_t plan, int32_t which, void* dst, int64_t ld) {
+  if (plan == nullptr || dst == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (!plan->have_state) return RPCA_ERR_NO_STATE;
+  DevGuard g(plan->device);
+  const int64_t m = plan->m, n = plan->n;
+  const int L = plan->L;
+  const void* src = nullptr;
+  int64_t rows = 0, cols = 0, lds = 0, esz = 0;
+  switch (which) {
+    case RPCA_STATE_H: src = plan->H; rows = m; cols = L; lds = L; esz = 4; break;
+    case RPCA_STATE_HSCALE: src = plan->alpha; rows = 1; cols = plan->i + 1; lds = cols; esz = 8; break;
+    case RPCA_STATE_Q: src = plan->Qfinal_is_Q1 ? plan->Q1 : plan->Q; rows = m; cols = L; lds = L; esz = 8; break;
+    case RPCA_STATE_T: src = plan->T; rows = n; cols = L; lds = L; esz = 8; break;
+    case RPCA_STATE_SIGMA: src = plan->sigL; rows = 1; cols = L; lds = L; esz = 8; break;
+    case RPCA_STATE_W: src = plan->Wsorted; rows = L; cols = L; lds = L; esz = 8; break;
+    case RPCA_STATE_MU:
+      if (!plan->d.center) return RPCA_ERR_NO_STATE;
+      src = plan->mu; rows = 1; cols = n; lds = n; esz = 8; break;
+    default: return RPCA_ERR_INVALID_ARG;
+  }
+  if (ld < cols) return RPCA_ERR_INVALID_ARG;
+  hipError_t e = hipMemcpy2DAsync(dst, (size_t)(ld * esz), src, (size_t)(lds * esz), (size_t)(cols * esz),
+                                  (size_t)rows, hipMemcpyDeviceToDevice, plan->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+  if (e != hipSuccess) {
+    plan->stats.hip_error = (int32_t)e;
+    (void)hipGetLastError();
+    return RPCA_ERR_HIP;
+  }
+  return RPCA_OK;
+}
+
+extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, int64_t ldgu,
+                                     const float* gV, int64_t ldgv, float* dA, int64_t ldda) {
+  (void)gS; (void)gU; (void)ldgu; (void)gV; (void)ldgv; (void)dA; (void)ldda;
+  if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
+  return RPCA_ERR_UNSUPPORTED;
+}
+
+extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
+                                     const float* U, int64_t ldu, const float* S, const float* V, int64_t ldv,
+                                     int32_t j, int32_t q, uint64_t seed, double* estimate) {
+  (void)A; (void)lda; (void)col_scale; (void)U; (void)ldu; (void)S; (void)V; (void)ldv; (void)j; (void)q;
+  (void)seed; (void)estimate;
+  if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
+  return RPCA_ERR_UNSUPPORTED;
+}
+
+extern "C" rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out,
+                                     int64_t ldo, float* col_scale, void* hip_stream) {
+  (void)storage; (void)m; (void)n; (void)A; (void)lda; (void)out; (void)ldo; (void)col_scale; (void)hip_stream;
+  return RPCA_ERR_UNSUPPORTED;
+}

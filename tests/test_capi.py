@@ -1,0 +1,79 @@
+"""The C-ABI library loads on a CPU-only host, exports every declared entry point,
+and rejects invalid parameters before touching a device (Section 3 rules)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rpca.h")
+LIB = os.path.join(ROOT, "paper_1007_5510_amd", "librpca.so")
+
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="librpca.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(rpca_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n != "rpca_panel_cb"))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rpca_plan", "rpca_factor", "rpca_backward", "rpca_residual", "rpca_quantize",
+                     "rpca_get_state", "rpca_get_stats", "rpca_status_str", "rpca_destroy"):
+        assert required in names
+
+
+@needs_lib
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], stdout=subprocess.PIPE, check=True).stdout.decode()
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(lib, n)
+
+
+@needs_lib
+def test_parameter_validation_without_device():
+    from paper_1007_5510_amd import _lib as L
+    lib = L.load()
+    h = ctypes.c_void_p(0)
+
+    def plan(**kw):
+        base = dict(m=1000, n=400, k=10, l=12, i=1, device=0)
+        base.update(kw)
+        d = L.Desc(**base)
+        return lib.rpca_plan(ctypes.byref(d), None, ctypes.byref(h))
+
+    assert plan(l=8) == 1                  # l < k
+    assert plan(i=40) == 1                 # (i+1) l > n - k
+    assert plan(k=400) == 1                # k >= n
+    assert plan(k=0) == 1
+    assert plan(m=300) == 1                # m < n
+    assert plan(storage=9) == 2            # unknown storage
+    assert plan(l=1100, k=10, i=0, n=4000, m=8000) == 2  # (i+1) l > 1024 unsupported
+    assert lib.rpca_plan(None, None, ctypes.byref(h)) == 1
+    assert h.value is None
+    for code in range(9):
+        assert lib.rpca_status_str(code)
+    assert lib.rpca_status_str(99) == b"unknown status"
+    lib.rpca_destroy(None)
+    st = L.Stats()
+    assert lib.rpca_get_stats(None, ctypes.byref(st)) == 1
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1007_5510_amd import _lib as L
+    saved = L._lib
+    try:
+        L._lib = None
+        with pytest.raises(RuntimeError):
+            L.load(str(tmp_path / "missing.so"))
+    finally:
+        L._lib = saved
