@@ -186,6 +186,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
+    st_last = plan.stats()
+    log(f"[bench] eig vectors {st_last['eig_vectors']} qr_fallback {st_last['qr_fallback']} passes {st_last['passes']}")
     log(f"[bench] timed {args.steps} steps: {ms:.2f} ms/step  stages " +
         " ".join(f"{key}={v / args.steps:.2f}" for key, v in stage.items()))
     a_bytes = (i + 2) * m * n * 4

@@ -119,7 +119,7 @@ typedef struct {
   int64_t a_bytes_read;  /* bytes of A read by the panel kernels (algorithmic) */
   int64_t h2d_bytes;     /* bytes of A moved host -> device (streamed sources) */
   int32_t qr_fallback;   /* 1 when Step 2 took the shifted Cholesky-QR path */
-  int32_t jacobi_sweeps; /* sweeps the small eigensolver used */
+  int32_t eig_vectors;   /* eigenvectors computed in Step 4 (k, or L when state is kept) */
   int32_t hip_error;     /* raw hipError_t of the last RPCA_ERR_HIP */
   int32_t passes;        /* full passes over A performed */
 } rpca_stats;
@@ -191,7 +191,8 @@ rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A,
  *   RPCA_STATE_Q      m x L doubles (Step 2)
  *   RPCA_STATE_T      n x L doubles (Step 3)
  *   RPCA_STATE_SIGMA  L doubles, S~ of Step 4
- *   RPCA_STATE_W      L x L doubles, W of Step 4 (columns in S~ order)
+ *   RPCA_STATE_W      L x L doubles, W of Step 4 (columns in S~ order; only the
+ *                     first k columns are computed unless KEEP_STATE was set)
  *   RPCA_STATE_MU     n doubles, column means (centering)
  * ld is the destination leading dimension in elements (>= column count).   */
 enum {

@@ -43,7 +43,7 @@ class Stats(ctypes.Structure):
         ("ms_qr", ctypes.c_double), ("ms_tpass", ctypes.c_double), ("ms_small_svd", ctypes.c_double),
         ("ms_assemble", ctypes.c_double), ("ms_fwd_kernel", ctypes.c_double), ("ms_adj_kernel", ctypes.c_double),
         ("fwd_launches", ctypes.c_int64), ("adj_launches", ctypes.c_int64), ("a_bytes_read", ctypes.c_int64),
-        ("h2d_bytes", ctypes.c_int64), ("qr_fallback", ctypes.c_int32), ("jacobi_sweeps", ctypes.c_int32),
+        ("h2d_bytes", ctypes.c_int64), ("qr_fallback", ctypes.c_int32), ("eig_vectors", ctypes.c_int32),
         ("hip_error", ctypes.c_int32), ("passes", ctypes.c_int32),
     ]
 

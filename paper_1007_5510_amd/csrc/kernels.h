@@ -101,20 +101,11 @@ hipError_t launch_gemm64(bool a_is_f64, const void* A, int64_t lda, const double
 // C (L x L) = A (L x L upper) * B (L x L upper)
 hipError_t launch_trmm_upper(const double* A, const double* B, int L, double* C, hipStream_t st);
 
-// symmetric eigen-decomposition by one-sided block Jacobi on M (L x L): on exit
-// B holds M V (columns), V the eigenvectors; rot_count[sweep] the rotations done
-struct JacobiPlan {
-  int L = 0, nb = 0, nblk = 0;  // block width and (even) block count
-  size_t lds_bytes = 0;
-};
-JacobiPlan jacobi_plan(int L);
-hipError_t launch_jacobi_init(const double* M, int L, double* B, double* V, int* rot_count, int max_sweeps,
-                              hipStream_t st);
-hipError_t launch_jacobi_round(const JacobiPlan& jp, double* B, double* V, int sweep, int round, int* rot_count,
-                               double tol, hipStream_t st);
-// lam[j] = ||B[:,j]||, order = permutation sorting lam descending (ties by index)
-hipError_t launch_jacobi_finish(const double* B, const double* V, int L, double* lam, int* order, double* Wsorted,
-                                double* sig_sorted, hipStream_t st);
+// Step 4 eigensolver (small_eig.hip): M (L x L) = W diag(lam) W^T; lam_desc all L
+// eigenvalues descending, sig_desc = sqrt(max(lam, 0)), W[:, 0:kk] the leading eigenvectors
+size_t syev_small_work(int L, int kk);
+hipError_t launch_syev_small(const double* M, int L, int kk, double* work, double* lam_desc, double* sig_desc,
+                             double* W, int ldw, size_t max_lds, hipStream_t st);
 // V[:, j] /= ||V[:, j]|| and sign so the largest |entry| is positive; sig[j] = norm; sgn[j] = sign
 hipError_t launch_normalize_sign(double* V, int64_t rows, int k, int64_t ldv, double* sig, double* sgn,
                                  hipStream_t st);

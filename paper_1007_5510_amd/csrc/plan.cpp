@@ -59,8 +59,6 @@ struct rpca_plan_s {
   int64_t rps_g = 0;
   int ns_gt = 1;  // Gram splits over T rows
   int64_t rps_gt = 0;
-  JacobiPlan jp;
-  int max_sweeps = 40;
 
   std::vector<void*> allocs;
   // device buffers
@@ -84,12 +82,10 @@ struct rpca_plan_s {
   double* Rfull = nullptr;
   double* Rinv = nullptr;
   double* Mg = nullptr;     // T^T T
-  double* JB = nullptr;     // Jacobi columns
-  double* JV = nullptr;     // Jacobi vectors
-  double* lam = nullptr;
-  int* order = nullptr;
-  double* Wsorted = nullptr;
-  double* sigL = nullptr;   // eigenvalue order
+  double* eigwork = nullptr;  // Step 4 eigensolver scratch
+  double* lam = nullptr;      // eigenvalues of T^T T, descending
+  double* Wsorted = nullptr;  // eigenvectors (columns), same order
+  double* sigL = nullptr;     // S~ = sqrt(lam)
   double* Vk = nullptr;     // n x k
   double* sig = nullptr;    // k
   double* sgn = nullptr;    // k
@@ -98,7 +94,6 @@ struct rpca_plan_s {
   double* sqp = nullptr;    // sum of squares partials
   float* corr = nullptr;    // L
   int* flags = nullptr;     // [0] nonfinite, [1] chol breakdown round 1, [2] round 2, [3] round 3
-  int* rot = nullptr;       // max_sweeps
   int64_t sqp_cap = 0;
 
   bool have_state = false;
@@ -246,19 +241,6 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
   choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
   choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
-  plan->jp = jacobi_plan(L);
-  while (plan->jp.lds_bytes > plan->max_lds && plan->jp.nb > 1) {
-    // shrink the column blocks until a block pair fits the workgroup's LDS
-    JacobiPlan jp = plan->jp;
-    jp.nb = jp.nb - 1;
-    int nblk = (L + jp.nb - 1) / jp.nb;
-    if (nblk < 2) nblk = 2;
-    if (nblk & 1) ++nblk;
-    jp.nblk = nblk;
-    jp.lds_bytes = (size_t)2 * jp.nb * L * 2 * sizeof(double);
-    plan->jp = jp;
-  }
-  if (plan->jp.lds_bytes > plan->max_lds) return fail(RPCA_ERR_UNSUPPORTED);
 
   const int64_t ldx = plan->ldx;
   const int64_t pcount =
@@ -292,10 +274,8 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(Rfull, LL);
   ALLOC(Rinv, LL);
   ALLOC(Mg, LL);
-  ALLOC(JB, LL);
-  ALLOC(JV, LL);
+  ALLOC(eigwork, (int64_t)syev_small_work(L, L));
   ALLOC(lam, L);
-  ALLOC(order, L);
   ALLOC(Wsorted, LL);
   ALLOC(sigL, L);
   ALLOC(Vk, n * k);
@@ -306,7 +286,6 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(sqp, plan->sqp_cap);
   ALLOC(corr, L);
   ALLOC(flags, 8);
-  ALLOC(rot, plan->max_sweeps);
 #undef ALLOC
   // zero the padded transposed blocks and the shift once (padding must stay 0)
   if (hipMemset(plan->X, 0, sizeof(float) * (size_t)(i + 1) * l * ldx) != hipSuccess ||
@@ -551,36 +530,13 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   RPCA_TRY(hipStreamSynchronize(st));
   const auto t_tpass = std::chrono::steady_clock::now();
 
-  // Step 4: T^T T = W diag(S~^2) W^T by block Jacobi
+  // Step 4: T^T T = W diag(S~^2) W^T (tridiagonal reduction, bisection, inverse iteration)
   RPCA_TRY(launch_gram(true, plan->T, L, n, L, plan->rps_gt, plan->ns_gt, plan->gp, st));
   RPCA_TRY(launch_gram_reduce(plan->gp, plan->ns_gt, L, plan->Mg, 0.0, st));
-  RPCA_TRY(launch_jacobi_init(plan->Mg, L, plan->JB, plan->JV, plan->rot, plan->max_sweeps, st));
-  const double tol = (double)L * 2.220446049250313e-16;
-  int sweeps_done = 0;
-  {
-    std::vector<int> hrot(plan->max_sweeps, 0);
-    int next_check = 6;
-    for (int sw = 0; sw < plan->max_sweeps; ++sw) {
-      for (int r = 0; r < plan->jp.nblk - 1; ++r)
-        RPCA_TRY(launch_jacobi_round(plan->jp, plan->JB, plan->JV, sw, r, plan->rot, tol, st));
-      sweeps_done = sw + 1;
-      if (sweeps_done == next_check || sweeps_done == plan->max_sweeps) {
-        RPCA_TRY(hipMemcpyAsync(hrot.data(), plan->rot, sizeof(int) * sweeps_done, hipMemcpyDeviceToHost, st));
-        RPCA_TRY(hipStreamSynchronize(st));
-        bool conv = false;
-        for (int q = 0; q < sweeps_done; ++q)
-          if (hrot[q] == 0) {
-            conv = true;
-            sweeps_done = q + 1;
-            break;
-          }
-        if (conv) break;
-        next_check += 2;
-      }
-    }
-  }
-  sx.jacobi_sweeps = sweeps_done;
-  RPCA_TRY(launch_jacobi_finish(plan->JB, plan->JV, L, plan->lam, plan->order, plan->Wsorted, plan->sigL, st));
+  const int kvec = (plan->d.flags & RPCA_FLAG_KEEP_STATE) ? L : k;
+  RPCA_TRY(launch_syev_small(plan->Mg, L, kvec, plan->eigwork, plan->lam, plan->sigL, plan->Wsorted, L, plan->max_lds,
+                             st));
+  sx.eig_vectors = kvec;
   RPCA_TRY(hipStreamSynchronize(st));
   const auto t_svd = std::chrono::steady_clock::now();
 

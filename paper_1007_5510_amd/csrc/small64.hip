@@ -2,9 +2,8 @@
 // Steps 2, 4, 5 and 6 run "in RAM"):
 //   Step 2  H = Q R by Cholesky QR applied twice (Gram, Cholesky, Q = H R^-1),
 //           with a shifted first round as the fallback for ill-conditioned H;
-//   Step 4  the SVD of T through the symmetric eigenproblem of T^T T, solved
-//           by a one-sided block Jacobi method (each workgroup orthogonalises
-//           a pair of column blocks held in LDS);
+//   Step 4  the SVD of T through the symmetric eigenproblem of T^T T (the
+//           eigensolver itself is in small_eig.hip);
 //   Step 5/6 U = Q W_k and V = T W_k / ||T W_k|| with the sign convention.
 #include "common.h"
 #include "kernels.h"
@@ -190,39 +189,41 @@ hipError_t launch_cholesky(double* W, int L, double rel_tol, int* flag, hipStrea
 }
 
 // ---------------------------------------------------------------- R^-1
-// Column j of the inverse of an upper triangular R depends only on R and on
-// itself: X[j][j] = 1/R[j][j], X[i][j] = -(sum_{p=i+1..j} R[i][p] X[p][j]) / R[i][i].
-// One thread per column; R read from LDS (packed) when it fits.
-template <bool PACKED>
-__global__ __launch_bounds__(1024) void triinv_kernel(const double* __restrict__ R, int L,
-                                                      double* __restrict__ X) {
-  extern __shared__ double smem[];
-  TriAcc a{PACKED ? smem : const_cast<double*>(R), L, PACKED};
-  if (PACKED) {
-    for (int64_t e = threadIdx.x; e < (int64_t)L * L; e += blockDim.x) {
-      const int i = (int)(e / L), j = (int)(e % L);
-      if (j >= i) a.at(i, j) = R[e];
-    }
-    __syncthreads();
+// Rows of X = R^-1 (upper triangular) are produced from the bottom up:
+// X[i][i] = 1/R[i][i] and X[i][j] = -(sum_{p=i+1..j} R[i][p] X[p][j]) / R[i][i]
+// only needs rows below i, so every column j of row i is computed in
+// parallel, with a power-of-two group of threads splitting each dot product.
+__global__ __launch_bounds__(1024) void triinv_kernel(const double* __restrict__ R, int L, double* __restrict__ X) {
+  extern __shared__ double rrow[];  // row i of R
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int64_t t = tid; t < (int64_t)L * L; t += nt) {
+    const int i = (int)(t / L), j = (int)(t % L);
+    if (j < i) X[t] = 0.0;
   }
-  for (int j = threadIdx.x; j < L; j += blockDim.x) {
-    for (int i = j + 1; i < L; ++i) X[(int64_t)i * L + j] = 0.0;
-    X[(int64_t)j * L + j] = 1.0 / a.at(j, j);
-    for (int i = j - 1; i >= 0; --i) {
+  for (int i = L - 1; i >= 0; --i) {
+    __syncthreads();
+    for (int j = i + tid; j < L; j += nt) rrow[j] = R[(int64_t)i * L + j];
+    __syncthreads();
+    const int ncol = L - i;
+    int G = 1;
+    while (G * 2 * ncol <= nt && G < 64) G *= 2;
+    const double inv = 1.0 / rrow[i];
+    for (int base = 0; base < ncol * G; base += nt) {
+      const int t = base + tid;
+      const int c = t / G, part = t % G;
+      const int j = i + c;
       double s = 0.0;
-      for (int p = i + 1; p <= j; ++p) s = fma(a.at(i, p), X[(int64_t)p * L + j], s);
-      X[(int64_t)i * L + j] = -s / a.at(i, i);
+      if (c < ncol) {
+        for (int p = i + 1 + part; p <= j; p += G) s = fma(rrow[p], X[(int64_t)p * L + j], s);
+      }
+      for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+      if (c < ncol && part == 0) X[(int64_t)i * L + j] = (j == i) ? inv : -s * inv;
     }
   }
 }
 
 hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st) {
-  const size_t bytes = (size_t)L * (L + 1) / 2 * sizeof(double);
-  if (bytes <= g_max_lds) {
-    hipLaunchKernelGGL(triinv_kernel<true>, dim3(1), dim3(1024), bytes, st, R, L, Rinv);
-  } else {
-    hipLaunchKernelGGL(triinv_kernel<false>, dim3(1), dim3(1024), 0, st, R, L, Rinv);
-  }
+  hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(1024), (size_t)L * sizeof(double), st, R, L, Rinv);
   return hipGetLastError();
 }
 
@@ -313,176 +314,6 @@ hipError_t launch_gemm64(bool a_is_f64, const void* A, int64_t lda, const double
   else
     hipLaunchKernelGGL(gemm64_kernel<float>, grid, dim3(256), 0, st, (const float*)A, lda, B, ldb, M, N, K,
                        b_upper ? 1 : 0, colscale, C, ldc, C32, ldc32);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------- Jacobi
-// Round-robin ("circle") schedule: for an even count N, round r in [0, N-1)
-// pairs t = 0 .. N/2-1 as (N-1, r) for t = 0 and ((r+t) mod (N-1),
-// (r-t) mod (N-1)) otherwise; every pair meets exactly once per N-1 rounds.
-RPCA_DEV void circle_pair(int r, int t, int N, int& a, int& b) {
-  if (t == 0) {
-    a = N - 1;
-    b = r;
-  } else {
-    a = (r + t) % (N - 1);
-    b = (r - t + (N - 1)) % (N - 1);
-  }
-}
-
-JacobiPlan jacobi_plan(int L) {
-  JacobiPlan jp;
-  jp.L = L;
-  int nb = 4608 / (L > 0 ? L : 1);  // 2 blocks x nb columns x L rows x (B, V) doubles <= 144 KiB
-  if (nb > 32) nb = 32;
-  if (nb < 1) nb = 1;
-  if (2 * nb >= L) nb = (L + 1) / 2;  // one block pair covers every column
-  jp.nb = nb;
-  int nblk = (L + nb - 1) / nb;
-  if (nblk < 2) nblk = 2;
-  if (nblk & 1) ++nblk;
-  jp.nblk = nblk;
-  jp.lds_bytes = (size_t)2 * nb * L * 2 * sizeof(double);
-  return jp;
-}
-
-__global__ void jacobi_init_kernel(const double* __restrict__ M, int L, double* __restrict__ B,
-                                   double* __restrict__ V, int* __restrict__ rot_count, int max_sweeps) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t LL = (int64_t)L * L;
-  if (e < LL) {
-    const int c = (int)(e / L), r = (int)(e % L);  // column-major B, V
-    B[e] = M[(int64_t)r * L + c];
-    V[e] = (r == c) ? 1.0 : 0.0;
-  }
-  if (e < max_sweeps) rot_count[e] = 0;
-}
-
-hipError_t launch_jacobi_init(const double* M, int L, double* B, double* V, int* rot_count, int max_sweeps,
-                              hipStream_t st) {
-  int64_t tot = (int64_t)L * L;
-  if (tot < max_sweeps) tot = max_sweeps;
-  hipLaunchKernelGGL(jacobi_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, M, L, B, V,
-                     rot_count, max_sweeps);
-  return hipGetLastError();
-}
-
-// One round of the block schedule: workgroup w orthogonalises (one inner
-// sweep over all column pairs) the union of its two column blocks, held in LDS.
-__global__ __launch_bounds__(1024) void jacobi_round_kernel(double* __restrict__ B, double* __restrict__ V, int L,
-                                                            int nb, int nblk, int sweep, int round,
-                                                            int* __restrict__ rot_count, double tol) {
-  if (sweep > 0 && rot_count[sweep - 1] == 0) return;  // previous sweep rotated nothing: converged
-  extern __shared__ double smem[];
-  int ba, bb;
-  circle_pair(round, blockIdx.x, nblk, ba, bb);
-  const int a0 = ba * nb, b0 = bb * nb;
-  const int na = a0 < L ? (a0 + nb <= L ? nb : L - a0) : 0;
-  const int nbb = b0 < L ? (b0 + nb <= L ? nb : L - b0) : 0;
-  const int ncl = na + nbb;
-  auto gcol = [&](int lc) { return lc < na ? a0 + lc : b0 + (lc - na); };
-  if (ncl < 2) return;
-  double* Bs = smem;                  // ncl columns of L
-  double* Vs = smem + (int64_t)ncl * L;
-  for (int64_t e = threadIdx.x; e < (int64_t)ncl * L; e += blockDim.x) {
-    const int lc = (int)(e / L), r = (int)(e % L);
-    Bs[e] = B[(int64_t)gcol(lc) * L + r];
-    Vs[e] = V[(int64_t)gcol(lc) * L + r];
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  const int NI = (ncl + 1) & ~1;
-  int rotations = 0;
-  for (int ir = 0; ir < NI - 1; ++ir) {
-    for (int t = wave; t < NI / 2; t += nwave) {
-      int p, q;
-      circle_pair(ir, t, NI, p, q);
-      if (p >= ncl || q >= ncl) continue;
-      double* bp = Bs + (int64_t)p * L;
-      double* bq = Bs + (int64_t)q * L;
-      double al = 0.0, be = 0.0, ga = 0.0;
-      for (int r = lane; r < L; r += 64) {
-        const double x = bp[r], y = bq[r];
-        al = fma(x, x, al);
-        be = fma(y, y, be);
-        ga = fma(x, y, ga);
-      }
-      al = wave_sum(al);
-      be = wave_sum(be);
-      ga = wave_sum(ga);
-      if (!(fabs(ga) > tol * sqrt(al) * sqrt(be)) || al == 0.0 || be == 0.0) continue;
-      const double zeta = (be - al) / (2.0 * ga);
-      const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + hypot(1.0, zeta));
-      const double cs = 1.0 / sqrt(1.0 + tt * tt);
-      const double sn = cs * tt;
-      double* vp = Vs + (int64_t)p * L;
-      double* vq = Vs + (int64_t)q * L;
-      for (int r = lane; r < L; r += 64) {
-        const double x = bp[r], y = bq[r];
-        bp[r] = cs * x - sn * y;
-        bq[r] = sn * x + cs * y;
-        const double u = vp[r], w = vq[r];
-        vp[r] = cs * u - sn * w;
-        vq[r] = sn * u + cs * w;
-      }
-      ++rotations;
-    }
-    __syncthreads();
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)ncl * L; e += blockDim.x) {
-    const int lc = (int)(e / L), r = (int)(e % L);
-    B[(int64_t)gcol(lc) * L + r] = Bs[e];
-    V[(int64_t)gcol(lc) * L + r] = Vs[e];
-  }
-  if (lane == 0 && rotations > 0) atomicAdd(rot_count + sweep, rotations);
-}
-
-hipError_t launch_jacobi_round(const JacobiPlan& jp, double* B, double* V, int sweep, int round, int* rot_count,
-                               double tol, hipStream_t st) {
-  hipLaunchKernelGGL(jacobi_round_kernel, dim3((unsigned)(jp.nblk / 2)), dim3(1024), jp.lds_bytes, st, B, V, jp.L,
-                     jp.nb, jp.nblk, sweep, round, rot_count, tol);
-  return hipGetLastError();
-}
-
-// lam[j] = ||B[:, j]||; order sorts lam descending (ties by column index);
-// Wsorted[i][r] = V[i][order[r]] row-major, sig_sorted[r] = sqrt(lam[order[r]]) (lam are
-// eigenvalues of T^T T, so these are the singular values of T).
-__global__ __launch_bounds__(1024) void jacobi_finish_kernel(const double* __restrict__ B,
-                                                             const double* __restrict__ V, int L,
-                                                             double* __restrict__ lam, int* __restrict__ order,
-                                                             double* __restrict__ Wsorted,
-                                                             double* __restrict__ sig_sorted) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-  for (int j = wave; j < L; j += nwave) {
-    double s = 0.0;
-    for (int r = lane; r < L; r += 64) {
-      const double x = B[(int64_t)j * L + r];
-      s = fma(x, x, s);
-    }
-    s = wave_sum(s);
-    if (lane == 0) lam[j] = sqrt(s);
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < L; j += blockDim.x) {
-    const double v = lam[j];
-    int rank = 0;
-    for (int i = 0; i < L; ++i) {
-      const double w = lam[i];
-      rank += (w > v || (w == v && i < j)) ? 1 : 0;
-    }
-    order[rank] = j;
-  }
-  __syncthreads();
-  for (int64_t e = threadIdx.x; e < (int64_t)L * L; e += blockDim.x) {
-    const int i = (int)(e / L), r = (int)(e % L);
-    Wsorted[e] = V[(int64_t)order[r] * L + i];
-  }
-  for (int r = threadIdx.x; r < L; r += blockDim.x) sig_sorted[r] = sqrt(lam[order[r]]);
-}
-
-hipError_t launch_jacobi_finish(const double* B, const double* V, int L, double* lam, int* order, double* Wsorted,
-                                double* sig_sorted, hipStream_t st) {
-  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, st, B, V, L, lam, order, Wsorted, sig_sorted);
   return hipGetLastError();
 }
 

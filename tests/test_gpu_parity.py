@@ -102,6 +102,15 @@ def test_intermediates_match_oracle():
     T = plan.state("T").cpu().numpy()
     st = np.linalg.svd(T, compute_uv=False)
     assert np.abs(st[:k] - orc.Stilde[:k]).max() / orc.Stilde[0] < 1e-5
+    # Step 4 on the device's own T: every eigenpair of T^T T (state keeps all L)
+    L = (i + 1) * l
+    Mg = T.T @ T
+    ev = np.sort(np.linalg.eigvalsh(Mg))[::-1]
+    sig_all = plan.state("SIGMA").cpu().numpy()
+    assert np.abs(sig_all ** 2 - ev).max() < 1e-12 * ev[0]
+    Wg = plan.state("W").cpu().numpy()
+    assert np.abs(Wg.T @ Wg - np.eye(L)).max() < 1e-10
+    assert np.linalg.norm(Mg @ Wg - Wg * ev) < 1e-11 * ev[0]
 
 
 @pytest.mark.parametrize("m,n,k,l,i,lda,v_tol", [
