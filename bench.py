@@ -203,7 +203,7 @@ def main():
     if adj_ms >= fwd_ms:
         dom = {"kernel": "adj_f32_kernel", "achieved": adj_tf, "avg_ms": adj_avg}
     else:
-        dom = {"kernel": "fwd_f32_kernel", "achieved": fwd_tf, "avg_ms": fwd_avg}
+        dom = {"kernel": "fwd32_kernel", "achieved": fwd_tf, "avg_ms": fwd_avg}
     roof = {"bound": "mfma", "achieved": round(dom["achieved"], 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(dom["achieved"] / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": dom["kernel"],
             "avg_launch_ms": round(dom["avg_ms"], 4)}

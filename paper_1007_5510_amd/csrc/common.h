@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 #define RPCA_DEV __device__ __forceinline__
 

@@ -19,6 +19,14 @@ struct FwdArgs {              // Z = alpha ((A - 1 s^T) Xt^T - 1 corr^T)
   float* Z = nullptr;
   int64_t ldz = 0;
   bool vec = false;               // A 16-byte aligned and lda % 4 == 0
+  // K split: ksplit > 1 writes partial sums P[s][r][c] (ldp >= ncols rounded up to
+  // 64, split_stride >= m * ldp) and reduces them into Z; kchunk per split
+  int ksplit = 1;
+  int64_t kchunk = 0;
+  float* P = nullptr;
+  int64_t ldp = 0, split_stride = 0;
+  // optional events recorded around the main product kernel only
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
   // low-precision storage extras
   const float* col_scale = nullptr;  // FP8: n scales (padded)
   int64_t plane = 0;                 // BF16_HILO: elements between hi and lo planes
@@ -36,11 +44,14 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
   float* P = nullptr;             // [nsplit][ncols][ldp]
   int64_t ldp = 0, split_stride = 0;
   bool vec = false;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
   const float* col_scale = nullptr;
   int64_t plane = 0;
 };
 
 hipError_t launch_fwd_f32(const FwdArgs& a, hipStream_t st);
+// K split for the forward product over `slots` concurrent blocks
+void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);
 int adj_nt_for(int ncols);  // 16-column tiles per wave used by the adjoint kernels
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st);
 hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st);

@@ -13,13 +13,14 @@
 // partial sums in the same transposed layout, so one pass's output is the
 // next pass's input without a transpose.
 //
-// MFMA operand layout for 16x16x4 f32 (wave64):
+// MFMA operand layout for 16x16x4 f32 (wave64, adjoint kernel):
 //   A operand: lane = i + 16*kk holds A[i][kk]   (i: M index, kk: K index)
 //   B operand: lane = j + 16*kk holds B[kk][j]
 //   D:         lane = j + 16*g holds D[4g + v][j] in register v
-// The forward kernel gives each lane a float4 along K of its own row, so four
-// MFMAs consume one coalesced 16-byte load (the K order inside a 16-wide
-// step is permuted identically for A and X, which leaves the sum unchanged).
+// Both kernels give each lane a float4 of A, so four MFMAs consume one
+// 16-byte load; in the forward product the float4 runs along K and the K
+// order inside a step is permuted identically for A and X, which leaves the
+// sum unchanged.
 //
 // Accuracy: each float32 accumulation chain is limited to 64 MFMA K-steps and
 // then folded into an outer accumulator (float64 in the forward product,
@@ -59,121 +60,175 @@ RPCA_DEV floatx4 mfma4(float a, float b, floatx4 c) {
 }
 
 // ---------------------------------------------------------------------------
-// forward: each wave owns 16 rows x (16*NT) output columns; 4 waves per block.
-// shift is always a valid n-vector (zeros when not centring).
-// K is walked in steps of 16 (one float4 per lane), STAGE steps per register
-// stage, with the next stage's loads issued before the current MFMAs.
+// forward (v_mfma_f32_32x32x2_f32): each wave owns 32 rows x
+// (32*NT2) columns, a block of 4 waves 128 rows.  X and the shift are staged
+// once per block in LDS (32 columns of K per stage, double buffered, rows
+// padded to 36 floats so the 32 lanes of a ds_read_b128 hit distinct banks);
+// A goes straight to registers, one float4 along K per lane, two register
+// stages in flight.  The K range is split over blockIdx.y so that the grid
+// has enough blocks to fill every CU evenly; the split partial sums go to a
+// buffer reduced in float64 by fwd_reduce_kernel (or straight to Z with the
+// epilogue when there is a single split).
+//   A operand: lane = i + 32*kk holds A[i][kk]; B operand: lane = j + 32*kk
+//   holds B[kk][j]; D: lane l, register v holds D[8(v/4) + 4(l/32) + v%4][l%32].
 // ---------------------------------------------------------------------------
-template <int NT, bool VEC, int STAGE>
-__global__ __launch_bounds__(256, 2) void fwd_f32_kernel(
-    const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
-    const float* __restrict__ Xt, int64_t ldx, int ncols, const float* __restrict__ corr,
-    const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int ii = lane & 15;
-  const int kk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int c0 = blockIdx.y * (16 * NT);
-  const int64_t row = r0 + ii;
-  const float* __restrict__ arow = A + (row < m ? row : m - 1) * lda;
-  const float* __restrict__ xrow[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int c = c0 + 16 * t + ii;
-    xrow[t] = Xt + (int64_t)(c < ncols ? c : ncols - 1) * ldx;
-  }
+RPCA_DEV floatx16 mfma32(float a, float b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
 
-  floatx4 acc[NT];
-  double accd[NT][4];
+constexpr int F3_KST = 32;           // K per LDS stage
+constexpr int F3_XP = F3_KST + 4;    // padded LDS row (floats)
+
+template <int NT2, bool VEC>
+__global__ __launch_bounds__(256, 2) void fwd32_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
+    const float* __restrict__ Xt, int64_t ldx, int ncols, int64_t kchunk, const float* __restrict__ corr,
+    const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz, int64_t split_stride, int direct) {
+  __shared__ float Xs[2][64][F3_XP];
+  __shared__ float Ss[2][F3_KST];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, kh = lane >> 5;
+  const int64_t r0 = (int64_t)blockIdx.x * 128 + wave * 32;
+  const int sk = blockIdx.y;
+  const int c0 = blockIdx.z * 64;
+  const int64_t kbeg = (int64_t)sk * kchunk;
+  const int64_t kend = kbeg + kchunk < n ? kbeg + kchunk : n;
+  const int64_t row = r0 + li;
+  const float* __restrict__ arow = A + (row < m ? row : m - 1) * lda;
+  // cooperative stage loader: thread -> (X row xc, 8-float slice xq)
+  const int xc = tid >> 2, xq = tid & 3;
+  const float* __restrict__ xsrc = Xt + (int64_t)(c0 + xc < ncols ? c0 + xc : ncols - 1) * ldx;
+
+  floatx16 acc[NT2];
+  double accd[NT2][16];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < NT2; ++t) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) accd[t][v] = 0.0;
+    for (int v = 0; v < 16; ++v) {
+      acc[t][v] = 0.f;
+      accd[t][v] = 0.0;
+    }
   }
   auto fold = [&]() {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+    for (int t = 0; t < NT2; ++t) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) accd[t][v] += (double)acc[t][v];
-      acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int v = 0; v < 16; ++v) {
+        accd[t][v] += (double)acc[t][v];
+        acc[t][v] = 0.f;
+      }
     }
   };
-  auto mma = [&](const floatx4& a, const floatx4 (&x)[NT]) {
+  struct AStage {
+    floatx4 a[F3_KST / 8];
+  };
+  struct XStage {
+    floatx4 x0, x1, s;
+  };
+  auto load_a = [&](AStage& b, int64_t kb) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int q = 0; q < F3_KST / 8; ++q) b.a[q] = ld4<VEC>(arow + kb + 8 * q + 4 * kh);
+  };
+  auto load_x = [&](XStage& b, int64_t kb) {
+    b.x0 = ld4<true>(xsrc + kb + 8 * xq);
+    b.x1 = ld4<true>(xsrc + kb + 8 * xq + 4);
+    b.s = ld4<true>(shift + kb + 4 * (tid & 7));
+  };
+  auto store_x = [&](const XStage& b, int buf) {
+    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq]) = b.x0;
+    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq + 4]) = b.x1;
+    if (tid < 8) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = b.s;
+  };
+  auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = mfma4(a[e], x[t][e], acc[t]);
+    for (int q = 0; q < F3_KST / 8; ++q) {
+      const floatx4 sv = *reinterpret_cast<const floatx4*>(&Ss[buf][8 * q + 4 * kh]);
+      const floatx4 a = b.a[q] - sv;
+      floatx4 x[NT2];
+#pragma unroll
+      for (int t = 0; t < NT2; ++t) x[t] = *reinterpret_cast<const floatx4*>(&Xs[buf][32 * t + li][8 * q + 4 * kh]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int t = 0; t < NT2; ++t) acc[t] = mfma32(a[e], x[t][e], acc[t]);
+      }
     }
   };
 
-  // main part: whole stages, unconditional loads, two register buffers
-  // (the loads of one stage are in flight while the other stage's MFMAs run)
-  constexpr int KS = 16 * STAGE;
-  constexpr int FOLD = 8 / STAGE > 0 ? 8 / STAGE : 1;  // fold every ~64 MFMA K-steps
-  const int64_t nmain = (n / (2 * KS)) * (2 * KS);
-  const int koff = 4 * kk;
-  struct Stage {
-    floatx4 a[STAGE], s[STAGE], x[STAGE][NT];
-  };
-  auto load_stage = [&](Stage& b, int64_t kb) {
-#pragma unroll
-    for (int q = 0; q < STAGE; ++q) {
-      const int64_t k = kb + 16 * q + koff;
-      b.a[q] = ld4<VEC>(arow + k);
-      b.s[q] = ld4<true>(shift + k);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b.x[q][t] = ld4<true>(xrow[t] + k);
-    }
-  };
+  // whole stages: straight-line body, the prefetch after the last one re-reads it
+  const int64_t nfull = (kend - kbeg) / F3_KST;
   int it = 0;
-  auto run_stage = [&](const Stage& b) {
-#pragma unroll
-    for (int q = 0; q < STAGE; ++q) mma(b.a[q] - b.s[q], b.x[q]);
-    if (++it == 2 * FOLD) {
-      it = 0;
-      fold();
-    }
-  };
-  // The loop body is straight-line (every load unconditional; the prefetch
-  // after the last pair re-reads the current stage), so the wait counters
-  // only ever wait for the stage about to be consumed.
-  if (nmain > 0) {
-    Stage b0, b1;
-    load_stage(b0, 0);
-    for (int64_t kb = 0; kb < nmain; kb += 2 * KS) {
-      load_stage(b1, kb + KS);
-      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
-      run_stage(b0);
-      load_stage(b0, kb + 2 * KS < nmain ? kb + 2 * KS : kb);
+  if (nfull > 0) {
+    AStage ac, an;
+    XStage xr;
+    load_x(xr, kbeg);
+    load_a(ac, kbeg);
+    store_x(xr, 0);
+    __syncthreads();
+    for (int64_t st = 0; st < nfull; ++st) {
+      const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * F3_KST;
+      load_x(xr, kn);
+      load_a(an, kn);
       __builtin_amdgcn_sched_barrier(0);
-      run_stage(b1);
+      compute(ac, (int)(st & 1));
+      store_x(xr, (int)((st + 1) & 1));
+      __syncthreads();
+      ac = an;
+      if (++it == 4) {  // fold every 4 stages (64 MFMA K-steps)
+        it = 0;
+        fold();
+      }
     }
   }
-  // tail: fewer than 2 KS columns, masked loads one 16-wide step at a time
-  for (int64_t kb = nmain; kb < n; kb += 16) {
-    const int64_t k = kb + koff;
-    const floatx4 a = ld4_masked(arow, k, n) - ld4_masked(shift, k, n);
-    floatx4 x[NT];
+  // tail stage (fewer than F3_KST columns left): masked loads
+  const int64_t kt = kbeg + nfull * F3_KST;
+  if (kt < kend) {
+    AStage at;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) x[t] = ld4_masked(xrow[t], k, n);
-    mma(a, x);
+    for (int q = 0; q < F3_KST / 8; ++q) at.a[q] = ld4_masked(arow, kt + 8 * q + 4 * kh, kend);
+    const int buf = (int)(nfull & 1);
+    const floatx4 x0 = ld4_masked(xsrc, kt + 8 * xq, kend);
+    const floatx4 x1 = ld4_masked(xsrc, kt + 8 * xq + 4, kend);
+    const floatx4 sv = ld4_masked(shift, kt + 4 * (tid & 7), kend);
+    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq]) = x0;
+    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq + 4]) = x1;
+    if (tid < 8) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = sv;
+    __syncthreads();
+    compute(at, buf);
   }
   fold();
 
-  const double alpha = alpha_ptr != nullptr ? *alpha_ptr : 1.0;
+  const double alpha = (direct && alpha_ptr != nullptr) ? *alpha_ptr : 1.0;
+  float* __restrict__ Zs = Z + (direct ? 0 : (int64_t)sk * split_stride);
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int c = c0 + 16 * t + ii;
+  for (int t = 0; t < NT2; ++t) {
+    const int c = c0 + 32 * t + li;
     if (c >= ncols) continue;
-    const double cr = corr != nullptr ? (double)corr[c] : 0.0;
+    const double cr = (direct && corr != nullptr) ? (double)corr[c] : 0.0;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = r0 + 4 * kk + v;
-      if (r < m) Z[r * ldz + c] = (float)(alpha * (accd[t][v] - cr));
+    for (int v = 0; v < 16; ++v) {
+      const int64_t r = r0 + 8 * (v >> 2) + 4 * kh + (v & 3);
+      if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * (accd[t][v] - cr)) : (float)accd[t][v];
     }
   }
+}
+
+// Z[r][c] = alpha (sum_s P[s][r][c] - corr[c]) in float64, s in split order
+__global__ __launch_bounds__(256) void fwd_reduce_kernel(const float* __restrict__ P, int nsplit,
+                                                         int64_t split_stride, int64_t ldp, int64_t m, int ncols,
+                                                         const float* __restrict__ corr,
+                                                         const double* __restrict__ alpha_ptr,
+                                                         float* __restrict__ Z, int64_t ldz) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= m * ncols) return;
+  const int64_t r = e / ncols;
+  const int c = (int)(e % ncols);
+  double v = 0.0;
+  for (int s = 0; s < nsplit; ++s) v += (double)P[(int64_t)s * split_stride + r * ldp + c];
+  const double alpha = alpha_ptr != nullptr ? *alpha_ptr : 1.0;
+  const double cr = corr != nullptr ? (double)corr[c] : 0.0;
+  Z[r * ldz + c] = (float)(alpha * (v - cr));
 }
 
 // ---------------------------------------------------------------------------
@@ -327,15 +382,29 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int NT>
-static hipError_t launch_fwd_nt(const FwdArgs& a, hipStream_t st) {
-  dim3 grid((unsigned)((a.m + 63) / 64), (unsigned)((a.ncols + 16 * NT - 1) / (16 * NT)));
+template <int NT2>
+static hipError_t launch_fwd32(const FwdArgs& a, hipStream_t st) {
+  const int ctiles = (a.ncols + 63) / 64;
+  const int ns = a.ksplit > 0 ? a.ksplit : 1;
+  const int64_t kchunk = ns > 1 ? a.kchunk : a.n;
+  dim3 grid((unsigned)((a.m + 127) / 128), (unsigned)ns, (unsigned)ctiles);
+  const bool direct = ns == 1;
+  float* out = direct ? a.Z : a.P;
+  const int64_t ldo = direct ? a.ldz : a.ldp;
+  if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
   if (a.vec)
-    hipLaunchKernelGGL((fwd_f32_kernel<NT, true, 3>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
-                       a.shift, a.Xt, a.ldx, a.ncols, a.corr, a.alpha, a.Z, a.ldz);
+    hipLaunchKernelGGL((fwd32_kernel<NT2, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
+                       a.Xt, a.ldx, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
   else
-    hipLaunchKernelGGL((fwd_f32_kernel<NT, false, 3>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
-                       a.shift, a.Xt, a.ldx, a.ncols, a.corr, a.alpha, a.Z, a.ldz);
+    hipLaunchKernelGGL((fwd32_kernel<NT2, false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+                       a.shift, a.Xt, a.ldx, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride,
+                       direct ? 1 : 0);
+  hipError_t e = hipGetLastError();
+  if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
+  if (e != hipSuccess || direct) return e;
+  const int64_t tot = a.m * a.ncols;
+  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a.P, ns,
+                     a.split_stride, a.ldp, a.m, a.ncols, a.corr, a.alpha, a.Z, a.ldz);
   return hipGetLastError();
 }
 
@@ -343,11 +412,37 @@ hipError_t launch_fwd_f32(const FwdArgs& a, hipStream_t st) {
   if (a.m <= 0 || a.ncols <= 0) return hipSuccess;
   if (a.A == nullptr || a.shift == nullptr || a.Xt == nullptr || a.Z == nullptr) return hipErrorInvalidValue;
   if (a.ldx < a.n || a.lda < a.n) return hipErrorInvalidValue;
-  const int tiles = (a.ncols + 15) / 16;
-  if (tiles <= 1) return launch_fwd_nt<1>(a, st);
-  if (tiles <= 2) return launch_fwd_nt<2>(a, st);
-  if (tiles <= 3) return launch_fwd_nt<3>(a, st);
-  return launch_fwd_nt<4>(a, st);
+  if (a.ksplit > 1) {
+    if (a.P == nullptr || a.ldp < ((a.ncols + 63) / 64) * 64 || a.kchunk % F3_KST != 0 ||
+        (int64_t)a.ksplit * a.kchunk < a.n || a.split_stride < a.m * a.ldp)
+      return hipErrorInvalidValue;
+  }
+  if (a.ncols <= 32) return launch_fwd32<1>(a, st);
+  return launch_fwd32<2>(a, st);
+}
+
+// K split of the forward product: the smallest split count (at most 8) whose
+// grid of 128-row blocks fills `slots` concurrent blocks with < 6% idle in the
+// last round; kchunk is a multiple of the LDS stage.
+void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk) {
+  const int64_t rt = (m + 127) / 128;
+  int best = 1;
+  double best_eff = 0.0;
+  for (int s = 1; s <= 8; ++s) {
+    const int64_t chunk = ((n + s - 1) / s + F3_KST - 1) / F3_KST * F3_KST;
+    const int64_t ns = (n + chunk - 1) / chunk;
+    const int64_t blocks = rt * ns;
+    const int64_t rounds = (blocks + slots - 1) / slots;
+    const double eff = (double)blocks / (double)(rounds * slots);
+    if (eff > best_eff + 1e-9) {
+      best_eff = eff;
+      best = (int)ns;
+    }
+    if (eff >= 0.94) break;
+  }
+  const int64_t chunk = ((n + best - 1) / best + F3_KST - 1) / F3_KST * F3_KST;
+  *ksplit = (int)((n + chunk - 1) / chunk);
+  *kchunk = chunk;
 }
 
 // rows / 4 per register stage of the adjoint kernel (two stages are in flight)
@@ -365,6 +460,7 @@ static hipError_t launch_adj_nt(const AdjArgs& a, hipStream_t st) {
   const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
   dim3 grid((unsigned)total);
   const bool vec = a.vec && (a.n % 4 == 0);
+  if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
   if (vec)
     hipLaunchKernelGGL((adj_f32_kernel<NT, true, ADJ_STAGE>), grid, dim3(256), 0, st, (const float*)a.A, a.lda,
                        a.m, a.n, a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P,
@@ -373,7 +469,9 @@ static hipError_t launch_adj_nt(const AdjArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((adj_f32_kernel<NT, false, ADJ_STAGE>), grid, dim3(256), 0, st, (const float*)a.A, a.lda,
                        a.m, a.n, a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P,
                        a.ldp, a.split_stride);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
+  return e;
 }
 
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {

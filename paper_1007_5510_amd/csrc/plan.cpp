@@ -59,6 +59,9 @@ struct rpca_plan_s {
   int64_t rps_g = 0;
   int ns_gt = 1;  // Gram splits over T rows
   int64_t rps_gt = 0;
+  int fwd_ks = 1;  // K split of the forward product
+  int64_t fwd_kchunk = 0;
+  int64_t ldpf = 0;  // row stride of the forward split partials
 
   std::vector<void*> allocs;
   // device buffers
@@ -70,7 +73,8 @@ struct rpca_plan_s {
   double* Q1 = nullptr;     // m x L
   double* Q = nullptr;      // m x L
   float* Q32 = nullptr;     // m x L
-  float* P = nullptr;       // partials
+  float* P = nullptr;       // adjoint split partials
+  float* Pf = nullptr;      // forward split partials
   double* T = nullptr;      // n x L
   double* csp = nullptr;    // column-sum partials
   double* gp = nullptr;     // Gram partials
@@ -241,6 +245,8 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
   choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
   choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
+  fwd_split(m, n, (int64_t)prop.multiProcessorCount * 2, &plan->fwd_ks, &plan->fwd_kchunk);
+  plan->ldpf = ((int64_t)l + 63) / 64 * 64;
 
   const int64_t ldx = plan->ldx;
   const int64_t pcount =
@@ -263,6 +269,7 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(Q, m * L);
   ALLOC(Q32, m * L);
   ALLOC(P, pcount);
+  ALLOC(Pf, plan->fwd_ks > 1 ? (int64_t)plan->fwd_ks * m * plan->ldpf : 1);
   ALLOC(T, n * L);
   ALLOC(csp, (int64_t)plan->ns_cs * ldx + (int64_t)plan->ns_cs * L);
   ALLOC(gp, (int64_t)std::max(plan->ns_g, plan->ns_gt) * LL);
@@ -312,24 +319,15 @@ rpca_status rpca_get_stats(rpca_plan_t plan, rpca_stats* out) {
 
 namespace {
 
-hipError_t record_fwd(rpca_plan_s* plan, bool begin) {
-  if (!(plan->d.flags & RPCA_FLAG_PROFILE)) return hipSuccess;
-  if (plan->nev_fwd >= (int)plan->ev_fwd.size()) return hipSuccess;
-  EventPair& p = plan->ev_fwd[plan->nev_fwd];
-  if (begin) return hipEventRecord(p.a, plan->stream);
-  hipError_t e = hipEventRecord(p.b, plan->stream);
-  ++plan->nev_fwd;
-  return e;
+// Event pair for the next timed panel kernel (null when not profiling or out of pairs).
+EventPair* next_fwd_events(rpca_plan_s* plan) {
+  if (!(plan->d.flags & RPCA_FLAG_PROFILE) || plan->nev_fwd >= (int)plan->ev_fwd.size()) return nullptr;
+  return &plan->ev_fwd[plan->nev_fwd++];
 }
 
-hipError_t record_adj(rpca_plan_s* plan, bool begin) {
-  if (!(plan->d.flags & RPCA_FLAG_PROFILE)) return hipSuccess;
-  if (plan->nev_adj >= (int)plan->ev_adj.size()) return hipSuccess;
-  EventPair& p = plan->ev_adj[plan->nev_adj];
-  if (begin) return hipEventRecord(p.a, plan->stream);
-  hipError_t e = hipEventRecord(p.b, plan->stream);
-  ++plan->nev_adj;
-  return e;
+EventPair* next_adj_events(rpca_plan_s* plan) {
+  if (!(plan->d.flags & RPCA_FLAG_PROFILE) || plan->nev_adj >= (int)plan->ev_adj.size()) return nullptr;
+  return &plan->ev_adj[plan->nev_adj++];
 }
 
 // One CholQR round: W = X^T X (+ shift), R = chol(W), Xout = X R^-1.
@@ -413,9 +411,16 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     fa.Z = plan->H + (int64_t)j * l;
     fa.ldz = L;
     fa.vec = vec;
-    RPCA_TRY(record_fwd(plan, true));
+    fa.ksplit = plan->fwd_ks;
+    fa.kchunk = plan->fwd_kchunk;
+    fa.P = plan->Pf;
+    fa.ldp = plan->ldpf;
+    fa.split_stride = m * plan->ldpf;
+    if (EventPair* ev = next_fwd_events(plan)) {
+      fa.ev_begin = ev->a;
+      fa.ev_end = ev->b;
+    }
     RPCA_TRY(launch_fwd_f32(fa, st));
-    RPCA_TRY(record_fwd(plan, false));
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
     if (j == i) break;
@@ -439,9 +444,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     aa.ldp = plan->ldp;
     aa.split_stride = (int64_t)l * plan->ldp;
     aa.vec = vec;
-    RPCA_TRY(record_adj(plan, true));
+    if (EventPair* ev = next_adj_events(plan)) {
+      aa.ev_begin = ev->a;
+      aa.ev_end = ev->b;
+    }
     RPCA_TRY(launch_adj_f32(aa, st));
-    RPCA_TRY(record_adj(plan, false));
     float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
     int npart = 0;
     RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, dres,
@@ -519,9 +526,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     aa.ldp = plan->ldp;
     aa.split_stride = (int64_t)L * plan->ldp;
     aa.vec = vec;
-    RPCA_TRY(record_adj(plan, true));
+    if (EventPair* ev = next_adj_events(plan)) {
+      aa.ev_begin = ev->a;
+      aa.ev_end = ev->b;
+    }
     RPCA_TRY(launch_adj_f32(aa, st));
-    RPCA_TRY(record_adj(plan, false));
     RPCA_TRY(launch_reduce_t(plan->P, plan->ns_t, aa.split_stride, plan->ldp, L, n, dres,
                              center ? plan->zsum : nullptr, plan->T, L, st));
     sx.passes += 1;
