@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=40000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed steps, copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -207,6 +209,14 @@ def main():
     roof = {"bound": "mfma", "achieved": round(dom["achieved"], 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(dom["achieved"] / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": dom["kernel"],
             "avg_launch_ms": round(dom["avg_ms"], 4)}
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 1 GiB device-to-device copy done")
+        del src, dst
     gate = None
     if not args.no_gate:
         t = time.perf_counter()

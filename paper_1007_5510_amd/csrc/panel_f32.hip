@@ -246,11 +246,16 @@ RPCA_DEV int64_t xcd_remap(int64_t b, int64_t total) {
   return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
-template <int NT, bool VEC, int STAGE>
+constexpr int ADJ_RS = 16;  // rows of A per LDS stage of the adjoint kernel
+
+template <int NT, bool VEC>
 __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
     const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
     const float* __restrict__ Z, int64_t ldz, int ncols, int64_t rows_per_split, int nsplit,
     int jtiles, int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride) {
+  // Z rows staged per block, interleaved so that lane (p, kk) finds its NT
+  // B-operand values (columns p, 16+p, 32+p, 48+p) in one 16-byte word.
+  __shared__ float Zs[2][ADJ_RS][16][4];
   const int64_t total = (int64_t)jtiles * ctiles * nsplit;
   const int64_t logical = xcd_remap(blockIdx.x, total);
   const int jt = (int)(logical % jtiles);
@@ -258,27 +263,30 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
   const int ct = (int)(rest % ctiles);
   const int sp = (int)(rest / ctiles);
 
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int p = lane & 15;
   const int kk = lane >> 4;
   const int64_t c0 = (int64_t)ct * 256 + wave * 64;
   const int64_t cl = c0 + 4 * p;
   const int64_t clc = cl < n ? cl : 0;  // clamped column for the unmasked path
-  const int j0 = jt * 16 * NT;
+  const int j0 = jt * 64;
   const int64_t rbeg = (int64_t)sp * rows_per_split;
   const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
-
-  int zc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int c = j0 + 16 * t + p;
-    zc[t] = c < ncols ? c : ncols - 1;
-  }
   const floatx4 sh = VEC ? ld4<true>(shift + clc) : ld4_masked(shift, cl, n);
+  // cooperative Z loader: 4 elements per thread per stage, element e = tid + 256 q
+  // -> row e / 64, column e % 64 (clamped to the last real column)
+  int zcol[4], zrow[4], zslot[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    const int cc = e & 63;
+    zrow[q] = e >> 6;
+    zcol[q] = j0 + cc < ncols ? j0 + cc : ncols - 1;
+    zslot[q] = (cc & 15) * 4 + (cc >> 4);  // [p][t] with column 16 t + p
+  }
 
-  // two float32 levels: acc takes 64 MFMA K-steps (256 rows), then is added
-  // into acc2; the split partial sums are reduced in float64 afterwards
   floatx4 acc[4][NT], acc2[4][NT];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -296,65 +304,89 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
         acc[v][t] = floatx4{0.f, 0.f, 0.f, 0.f};
       }
   };
-  auto mma = [&](const floatx4& a, const float (&z)[NT]) {
+  struct AStage {
+    floatx4 a[ADJ_RS / 4];
+  };
+  struct ZStage {
+    float z[4];
+  };
+  auto load_a = [&](AStage& b, int64_t rb) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[v][t] = mfma4(a[v], z[t], acc[v][t]);
+    for (int q = 0; q < ADJ_RS / 4; ++q) {
+      const float* arow = A + (rb + 4 * q + kk) * lda;
+      b.a[q] = VEC ? ld4<true>(arow + clc) : ld4_masked(arow, cl, n);
     }
   };
-  auto load_row = [&](int64_t r, floatx4& a, float (&z)[NT]) {
-    const float* arow = A + r * lda;
-    a = VEC ? ld4<true>(arow + clc) : ld4_masked(arow, cl, n);
+  auto load_z = [&](ZStage& b, int64_t rb) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t) z[t] = Z[r * ldz + zc[t]];
+    for (int q = 0; q < 4; ++q) b.z[q] = Z[(rb + zrow[q]) * ldz + zcol[q]];
+  };
+  auto store_z = [&](const ZStage& b, int buf) {
+    float* base = &Zs[buf][0][0][0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) base[zrow[q] * 64 + zslot[q]] = b.z[q];
+  };
+  auto compute = [&](const AStage& b, int buf) {
+#pragma unroll
+    for (int q = 0; q < ADJ_RS / 4; ++q) {
+      const floatx4 zz = *reinterpret_cast<const floatx4*>(&Zs[buf][4 * q + kk][p][0]);
+      const floatx4 a = b.a[q] - sh;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[v][t] = mfma4(a[v], zz[t], acc[v][t]);
+      }
+    }
   };
 
-  constexpr int RS = 4 * STAGE;
-  constexpr int FOLD = 64 / STAGE;  // fold every ~64 MFMA K-steps (~256 rows)
-  const int64_t nmain = rbeg + ((rend - rbeg) / (2 * RS)) * (2 * RS);
-  struct Stage {
-    floatx4 a[STAGE];
-    float z[STAGE][NT];
-  };
-  auto load_stage = [&](Stage& b, int64_t rb) {
-#pragma unroll
-    for (int q = 0; q < STAGE; ++q) load_row(rb + 4 * q + kk, b.a[q], b.z[q]);
-  };
+  const int64_t nfull = (rend - rbeg) / ADJ_RS;
   int it = 0;
-  auto run_stage = [&](const Stage& b) {
-#pragma unroll
-    for (int q = 0; q < STAGE; ++q) mma(b.a[q] - sh, b.z[q]);
-    if (++it == FOLD) {
-      it = 0;
-      fold();
-    }
-  };
-  // straight-line body as in the forward kernel
-  if (nmain > rbeg) {
-    Stage b0, b1;
-    load_stage(b0, rbeg);
-    for (int64_t rb = rbeg; rb < nmain; rb += 2 * RS) {
-      load_stage(b1, rb + RS);
-      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
-      run_stage(b0);
-      load_stage(b0, rb + 2 * RS < nmain ? rb + 2 * RS : rb);
+  if (nfull > 0) {
+    AStage ac, an;
+    ZStage zr;
+    load_z(zr, rbeg);
+    load_a(ac, rbeg);
+    store_z(zr, 0);
+    __syncthreads();
+    for (int64_t st = 0; st < nfull; ++st) {
+      const int64_t rn = rbeg + (st + 1 < nfull ? st + 1 : st) * ADJ_RS;
+      load_z(zr, rn);
+      load_a(an, rn);
       __builtin_amdgcn_sched_barrier(0);
-      run_stage(b1);
+      compute(ac, (int)(st & 1));
+      store_z(zr, (int)((st + 1) & 1));
+      __syncthreads();
+      ac = an;
+      if (++it == 16) {  // fold every 16 stages (64 MFMA K-steps, 256 rows)
+        it = 0;
+        fold();
+      }
     }
   }
-  // tail rows: fewer than 2 RS, masked by row
-  for (int64_t rb = nmain; rb < rend; rb += 4) {
-    const int64_t r = rb + kk;
-    floatx4 a = {0.f, 0.f, 0.f, 0.f};
-    float z[NT];
+  // tail rows (fewer than a stage): masked by row, zeros beyond rend
+  const int64_t rt = rbeg + nfull * ADJ_RS;
+  if (rt < rend) {
+    const int buf = (int)(nfull & 1);
+    float* base = &Zs[buf][0][0][0];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) z[t] = 0.f;
-    if (r < rend) {
-      load_row(r, a, z);
-      a -= sh;
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = rt + zrow[q];
+      base[zrow[q] * 64 + zslot[q]] = r < rend ? Z[r * ldz + zcol[q]] : 0.f;
     }
-    mma(a, z);
+    AStage at;
+#pragma unroll
+    for (int q = 0; q < ADJ_RS / 4; ++q) {
+      const int64_t r = rt + 4 * q + kk;
+      at.a[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+      if (r < rend) {
+        const float* arow = A + r * lda;
+        at.a[q] = VEC ? ld4<true>(arow + clc) : ld4_masked(arow, cl, n);
+      } else {
+        at.a[q] = sh;  // (a - sh) = 0 for rows past the end
+      }
+    }
+    __syncthreads();
+    compute(at, buf);
   }
   fold();
 
@@ -445,33 +477,39 @@ void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk
   *kchunk = chunk;
 }
 
-// rows / 4 per register stage of the adjoint kernel (two stages are in flight)
-constexpr int ADJ_STAGE = 3;
-
 int adj_nt_for(int ncols) {
-  const int tiles = (ncols + 15) / 16;
-  return tiles <= 1 ? 1 : tiles <= 2 ? 2 : tiles <= 3 ? 3 : 4;
+  (void)ncols;
+  return 4;  // 64 Z columns per block (j tile)
 }
 
-template <int NT>
-static hipError_t launch_adj_nt(const AdjArgs& a, hipStream_t st) {
-  const int jtiles = (a.ncols + 16 * NT - 1) / (16 * NT);
-  const int ctiles = (int)((a.n + 255) / 256);
-  const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
-  dim3 grid((unsigned)total);
-  const bool vec = a.vec && (a.n % 4 == 0);
-  if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
-  if (vec)
-    hipLaunchKernelGGL((adj_f32_kernel<NT, true, ADJ_STAGE>), grid, dim3(256), 0, st, (const float*)a.A, a.lda,
-                       a.m, a.n, a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P,
-                       a.ldp, a.split_stride);
-  else
-    hipLaunchKernelGGL((adj_f32_kernel<NT, false, ADJ_STAGE>), grid, dim3(256), 0, st, (const float*)a.A, a.lda,
-                       a.m, a.n, a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P,
-                       a.ldp, a.split_stride);
-  hipError_t e = hipGetLastError();
-  if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
-  return e;
+// Row split of the adjoint product: among split counts giving at least two
+// rounds of `slots` concurrent blocks, the one whose last round is fullest
+// (ties to fewer splits, i.e. less partial-sum traffic); rows per split are a
+// multiple of the LDS stage.
+void adj_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split) {
+  const int64_t per = (int64_t)((ncols + 63) / 64) * ((n + 255) / 256);
+  int64_t lo = (2 * slots + per - 1) / per;
+  int64_t hi = lo * 4 + 8;
+  const int64_t maxs = m / 64 > 0 ? m / 64 : 1;
+  if (lo > maxs) lo = maxs;
+  if (hi > maxs) hi = maxs;
+  if (lo < 1) lo = 1;
+  double best = -1.0;
+  int64_t bs = 1, br = ((m + ADJ_RS - 1) / ADJ_RS) * ADJ_RS;
+  for (int64_t s = lo; s <= hi; ++s) {
+    const int64_t r = ((m + s - 1) / s + ADJ_RS - 1) / ADJ_RS * ADJ_RS;
+    const int64_t ns = (m + r - 1) / r;
+    const int64_t blocks = per * ns;
+    const int64_t rounds = (blocks + slots - 1) / slots;
+    const double eff = (double)blocks / (double)(rounds * slots);
+    if (eff > best + 1e-3) {
+      best = eff;
+      bs = ns;
+      br = r;
+    }
+  }
+  *nsplit = (int)bs;
+  *rows_per_split = br;
 }
 
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
@@ -479,12 +517,23 @@ hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
   if (a.A == nullptr || a.shift == nullptr || a.Z == nullptr || a.P == nullptr) return hipErrorInvalidValue;
   if (a.lda < a.n || a.ldp < a.n || a.rows_per_split % 4 != 0) return hipErrorInvalidValue;
   if ((int64_t)a.nsplit * a.rows_per_split < a.m) return hipErrorInvalidValue;
-  switch (adj_nt_for(a.ncols)) {
-    case 1: return launch_adj_nt<1>(a, st);
-    case 2: return launch_adj_nt<2>(a, st);
-    case 3: return launch_adj_nt<3>(a, st);
-    default: return launch_adj_nt<4>(a, st);
-  }
+  const int jtiles = (a.ncols + 63) / 64;
+  const int ctiles = (int)((a.n + 255) / 256);
+  const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
+  dim3 grid((unsigned)total);
+  const bool vec = a.vec && (a.n % 4 == 0);
+  if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
+  if (vec)
+    hipLaunchKernelGGL((adj_f32_kernel<4, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+                       a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P, a.ldp,
+                       a.split_stride);
+  else
+    hipLaunchKernelGGL((adj_f32_kernel<4, false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+                       a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P, a.ldp,
+                       a.split_stride);
+  hipError_t e = hipGetLastError();
+  if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
+  return e;
 }
 
 }  // namespace rpca

@@ -157,21 +157,6 @@ rpca_status validate_desc(const rpca_desc* d) {
   return RPCA_OK;
 }
 
-// Choose the row splits of an adjoint product so that the grid holds about
-// `target` blocks, with at least 64 rows per split.
-void choose_splits(int64_t m, int64_t n, int ncols, int64_t target, int* ns, int64_t* rps) {
-  const int nt = adj_nt_for(ncols);
-  const int64_t jtiles = (ncols + 16 * nt - 1) / (16 * nt);
-  const int64_t ctiles = (n + 255) / 256;
-  int64_t s = (target + jtiles * ctiles - 1) / (jtiles * ctiles);
-  const int64_t smax = std::max<int64_t>(1, m / 64);
-  s = std::max<int64_t>(1, std::min(s, smax));
-  int64_t r = round_up((m + s - 1) / s, 4);
-  s = (m + r - 1) / r;
-  *ns = (int)s;
-  *rps = r;
-}
-
 void choose_rows(int64_t rows, int64_t per, int maxs, int* ns, int64_t* rps) {
   int64_t s = std::max<int64_t>(1, std::min<int64_t>(maxs, (rows + per - 1) / per));
   int64_t r = round_up((rows + s - 1) / s, 16);
@@ -239,13 +224,13 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   plan->ldx = round_up(n, 4);
   plan->ldp = round_up(n, 4);
 
-  const int64_t target = 2048;
-  choose_splits(m, n, l, target, &plan->ns_y, &plan->rps_y);
-  choose_splits(m, n, L, target, &plan->ns_t, &plan->rps_t);
+  const int64_t slots = (int64_t)prop.multiProcessorCount * 2;  // two 256-thread blocks per CU
+  adj_split(m, n, l, slots, &plan->ns_y, &plan->rps_y);
+  adj_split(m, n, L, slots, &plan->ns_t, &plan->rps_t);
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
   choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
   choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
-  fwd_split(m, n, (int64_t)prop.multiProcessorCount * 2, &plan->fwd_ks, &plan->fwd_kchunk);
+  fwd_split(m, n, slots, &plan->fwd_ks, &plan->fwd_kchunk);
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
 
   const int64_t ldx = plan->ldx;
