@@ -32,6 +32,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None.
+
+    The summary lists calibrated FETCH_SIZE / WRITE_SIZE averages together with
+    the sha256 prefix of the panel-kernel source they were taken on; a source
+    change since then makes the numbers stale and they are not reported.
+    """
+    import hashlib
+    src = os.path.join(ROOT, "paper_1007_5510_amd", "csrc", "panel_f32.hip")
+    summary = os.path.join(ROOT, "profiles", "incore_f32_hbm_counters.md")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        for line in open(summary):
+            f = line.split()
+            if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[2] == sha:
+                return {"fetch": float(f[3]), "write": float(f[4])}
+    except OSError:
+        pass
+    return None
+
+
 def make_incore(m, n, r, seed, device):
     import numpy as np
     import torch
@@ -206,9 +227,13 @@ def main():
         dom = {"kernel": "adj_f32_kernel", "achieved": adj_tf, "avg_ms": adj_avg}
     else:
         dom = {"kernel": "fwd32_kernel", "achieved": fwd_tf, "avg_ms": fwd_avg}
+    tr = measured_traffic(dom["kernel"])
     roof = {"bound": "mfma", "achieved": round(dom["achieved"], 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(dom["achieved"] / PEAK_FP32_TFLOPS, 4), "traffic": None, "kernel": dom["kernel"],
-            "avg_launch_ms": round(dom["avg_ms"], 4)}
+            "frac": round(dom["achieved"] / PEAK_FP32_TFLOPS, 4),
+            "traffic": round(tr["fetch"] + tr["write"]) if tr else None,
+            "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+            "algorithmic_bytes": m * n * 4,
+            "kernel": dom["kernel"], "avg_launch_ms": round(dom["avg_ms"], 4)}
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
