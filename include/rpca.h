@@ -53,7 +53,12 @@ typedef enum {
  *   F32        float
  *   BF16       bfloat16 bit patterns (uint16_t)
  *   FP8_E4M3   OCP e4m3 bytes (uint8_t); entry (r, c) is q(r, c) * col_scale[c]
- *   BF16_HILO  two bfloat16 planes: hi at A, lo at A + m*lda; entry = hi + lo     */
+ *   BF16_HILO  two bfloat16 planes: hi at A, lo at A + m*lda; entry = hi + lo
+ * The three low-precision formats (not part of the paper, which stores
+ * float32; they trade accuracy of the stored A for bytes moved) need A 16-byte
+ * aligned and lda a multiple of 16; entries between n and lda are ignored.
+ * Their products run on bfloat16 matrix cores with float accumulation, the
+ * float operand carried as a bfloat16 hi + lo pair (16 significant bits).   */
 typedef enum {
   RPCA_A_F32 = 0,
   RPCA_A_BF16 = 1,
@@ -150,8 +155,12 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
  * Column j of U and V is signed so that the largest-magnitude entry of v_j is
  * positive.  A is read (i+2) times (one fused pass A^T(A X) per power step,
  * one A X pass, one A^T Q pass), plus one column-mean pass when centering.
+ * Low-precision storage: with centring the column means come from the
+ * stored values (times col_scale for FP8) and enter only through the exact
+ * rank-one correction.
  * Errors: INVALID_ARG for NULL or misaligned pointers or short leading
- * dimensions; CALLBACK; NONFINITE; QR_BREAKDOWN; HIP.                      */
+ * dimensions (low-precision formats: A not 16-byte aligned or lda % 16 != 0,
+ * FP8_E4M3 without col_scale); CALLBACK; NONFINITE; QR_BREAKDOWN; HIP.     */
 rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
                         rpca_panel_cb cb, void* user, const float* G,
                         float* U, int64_t ldu, float* S, float* V, int64_t ldv);
@@ -176,13 +185,30 @@ rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const fl
                           const float* U, int64_t ldu, const float* S, const float* V, int64_t ldv,
                           int32_t j, int32_t q, uint64_t seed, double* estimate);
 
-/* Quantises a device float matrix into the stored formats of rpca_storage:
- *   BF16 / BF16_HILO: round-to-nearest-even; lo = bf16(a - hi).
- *   FP8_E4M3: per-column scale c_j = max_r |a_rj| / 448 (1 when the column is
- *   zero), q = e4m3(a / c_j) with round-to-nearest-even and saturation.
- * out has m*ldo elements (2*m*ldo for BF16_HILO); col_scale n floats.      */
+/* Converts a device float matrix A (m x n, lda) into a stored format of
+ * rpca_storage (BF16, FP8_E4M3 or BF16_HILO), writing out (device, m x ldo
+ * elements, 2 m ldo for BF16_HILO; 16-byte aligned, ldo >= n, ldo % 16 == 0;
+ * columns n .. ldo-1 are written as zero).  With a shift, a = A[r][c] - shift[c]
+ * (float32) is stored instead of A[r][c]:
+ *   shift_mode 0: no shift (shift may be NULL);
+ *   shift_mode 1: shift is n device floats given by the caller;
+ *   shift_mode 2: shift (n device floats) receives fl32 of the column means of
+ *                 A (float64 sums) and is then used.
+ * Column-mean centring of the stored matrix removes any shift, so a shifted
+ * copy factored with desc.center = 1 gives the centred PCA of the data while
+ * the stored bits carry the spread instead of the mean.
+ * Rounding (the definitions the library's tests check bit for bit):
+ *   BF16 / BF16_HILO: round to nearest, ties to even; lo = bf16(a - hi).
+ *   FP8_E4M3: per-column scale c_j = fl32(max_r |a_rj| / 448) (1 when the
+ *   column is zero) written to col_scale (n device floats); code =
+ *   e4m3(fl32(a / c_j)) rounded to nearest, ties to the even code, saturated
+ *   at +-448 (never NaN).
+ * Blocks the calling thread until done (allocates small scratch).
+ * Errors: INVALID_ARG (F32 or unknown storage, NULL pointers, short or
+ * unaligned leading dimensions, bad shift_mode); OUT_OF_MEMORY; HIP.        */
 rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda,
-                          void* out, int64_t ldo, float* col_scale, void* hip_stream);
+                          void* out, int64_t ldo, float* col_scale, float* shift, int32_t shift_mode,
+                          void* hip_stream);
 
 /* Intermediate results kept by KEEP_STATE (device copies into dst):
  *   RPCA_STATE_H      m x L floats, the blocks H^(j) each multiplied by a

@@ -79,7 +79,7 @@ def load(path: str = LIB_PATH):
     lib.rpca_residual.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i64, i32, i32, u64,
                                   ctypes.POINTER(ctypes.c_double)]
     lib.rpca_residual.restype = i32
-    lib.rpca_quantize.argtypes = [i32, i64, i64, vp, i64, vp, i64, vp, vp]
+    lib.rpca_quantize.argtypes = [i32, i64, i64, vp, i64, vp, i64, vp, vp, i32, vp]
     lib.rpca_quantize.restype = i32
     lib.rpca_get_state.argtypes = [vp, i32, vp, i64]
     lib.rpca_get_state.restype = i32

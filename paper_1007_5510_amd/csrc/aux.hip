@@ -148,7 +148,7 @@ hipError_t launch_dot_rows(const double* d, const float* Xt, int64_t ldx, int64_
 
 __global__ __launch_bounds__(256) void reduce_y_kernel(const float* __restrict__ P, int nsplit,
                                                        int64_t split_stride, int64_t ldp, int64_t n,
-                                                       const double* __restrict__ d,
+                                                       const float* __restrict__ cs, const double* __restrict__ d,
                                                        const double* __restrict__ zsum, float* __restrict__ Xt,
                                                        int64_t ldx, double* __restrict__ sq_part) {
   __shared__ double sh[4];
@@ -159,6 +159,7 @@ __global__ __launch_bounds__(256) void reduce_y_kernel(const float* __restrict__
     double v = 0.0;
     const float* p = P + (int64_t)j * ldp + c;
     for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+    if (cs != nullptr) v *= (double)cs[c];
     if (d != nullptr) v -= d[c] * zsum[j];
     const float f = (float)v;
     Xt[(int64_t)j * ldx + c] = f;
@@ -169,12 +170,12 @@ __global__ __launch_bounds__(256) void reduce_y_kernel(const float* __restrict__
 }
 
 hipError_t launch_reduce_y(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                           const double* d, const double* zsum, float* Xt, int64_t ldx, double* sq_part,
-                           int* n_sq_part, hipStream_t st) {
+                           const float* col_scale, const double* d, const double* zsum, float* Xt, int64_t ldx,
+                           double* sq_part, int* n_sq_part, hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
   *n_sq_part = (int)(grid.x * grid.y);
-  hipLaunchKernelGGL(reduce_y_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, n, d, zsum, Xt, ldx,
-                     sq_part);
+  hipLaunchKernelGGL(reduce_y_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, n, col_scale, d, zsum,
+                     Xt, ldx, sq_part);
   return hipGetLastError();
 }
 
@@ -204,7 +205,7 @@ hipError_t launch_finish_scale(const double* sq_part, int n_part, bool rescale, 
 
 __global__ __launch_bounds__(256) void reduce_t_kernel(const float* __restrict__ P, int nsplit,
                                                        int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                                                       const double* __restrict__ d,
+                                                       const float* __restrict__ cs, const double* __restrict__ d,
                                                        const double* __restrict__ qsum, double* __restrict__ T,
                                                        int64_t ldt) {
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -213,15 +214,17 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const float* __restrict__
   double v = 0.0;
   const float* p = P + (int64_t)j * ldp + c;
   for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  if (cs != nullptr) v *= (double)cs[c];
   if (d != nullptr) v -= d[c] * qsum[j];
   T[c * ldt + j] = v;
 }
 
 hipError_t launch_reduce_t(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                           const double* d, const double* qsum, double* T, int64_t ldt, hipStream_t st) {
+                           const float* col_scale, const double* d, const double* qsum, double* T, int64_t ldt,
+                           hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
-  hipLaunchKernelGGL(reduce_t_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, ncols, n, d, qsum, T,
-                     ldt);
+  hipLaunchKernelGGL(reduce_t_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, ncols, n, col_scale, d,
+                     qsum, T, ldt);
   return hipGetLastError();
 }
 

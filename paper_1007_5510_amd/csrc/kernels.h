@@ -27,9 +27,12 @@ struct FwdArgs {              // Z = alpha ((A - 1 s^T) Xt^T - 1 corr^T)
   int64_t ldp = 0, split_stride = 0;
   // optional events recorded around the main product kernel only
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
-  // low-precision storage extras
-  const float* col_scale = nullptr;  // FP8: n scales (padded)
-  int64_t plane = 0;                 // BF16_HILO: elements between hi and lo planes
+  // low-precision storage: X split into bfloat16 hi/lo planes (cpad x ldxs,
+  // column scales already folded in) and the hi -> lo plane distance of A
+  const uint16_t* Xh = nullptr;
+  const uint16_t* Xl = nullptr;
+  int64_t ldxs = 0;
+  int64_t plane = 0;  // BF16_HILO: elements between the hi and lo planes
 };
 
 struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
@@ -45,7 +48,11 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
   int64_t ldp = 0, split_stride = 0;
   bool vec = false;
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
-  const float* col_scale = nullptr;
+  // low-precision storage: Z split into transposed, row-permuted bfloat16
+  // hi/lo planes (cpad x ldzs)
+  const uint16_t* Zh = nullptr;
+  const uint16_t* Zl = nullptr;
+  int64_t ldzs = 0;
   int64_t plane = 0;
 };
 
@@ -58,6 +65,18 @@ void adj_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int6
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st);
 hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st);
 hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st);
+void fwd_split_lp(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);
+void adj_split_lp(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);
+// hi/lo bfloat16 planes of (col_scale o Xt): cpad x ldxs (ldxs % 64 == 0, cpad % 64 == 0)
+hipError_t launch_split_x(const float* Xt, int64_t ldx, int64_t n, int ncols, const float* col_scale,
+                          uint16_t* Xh, uint16_t* Xl, int64_t ldxs, int cpad, hipStream_t st);
+// transposed, row-permuted hi/lo bfloat16 planes of Z: cpad x ldzs (ldzs % 32 == 0)
+hipError_t launch_split_zt(const float* Z, int64_t ldz, int64_t m, int ncols, uint16_t* Zh, uint16_t* Zl,
+                           int64_t ldzs, int cpad, hipStream_t st);
+// quantisers of the stored formats (see rpca_quantize)
+hipError_t launch_quantize(int storage, int64_t m, int64_t n, const float* A, int64_t lda, const float* shift,
+                           void* out, int64_t ldo, float* col_scale, float* amax_part, int nsplit,
+                           int64_t rows_per_split, hipStream_t st);
 
 // ---------------------------------------------------------------- auxiliary
 // FP64 column sums of a row-major matrix in a given storage: part[s][c] over row splits.
@@ -77,14 +96,15 @@ hipError_t launch_dot_rows(const double* d, const float* Xt, int64_t ldx, int64_
                            hipStream_t st);
 // Xt[j][c] = sum_s P[s][j][c] - d[c] zsum[j]; per-block sums of squares into sq_part
 hipError_t launch_reduce_y(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                           const double* d, const double* zsum, float* Xt, int64_t ldx, double* sq_part,
-                           int* n_sq_part, hipStream_t st);
+                           const float* col_scale, const double* d, const double* zsum, float* Xt, int64_t ldx,
+                           double* sq_part, int* n_sq_part, hipStream_t st);
 // alpha = 1/sqrt(sum of sq_part) (1 when zero or rescaling is off); nonfinite flag
 hipError_t launch_finish_scale(const double* sq_part, int n_part, bool rescale, double* alpha, int* flag,
                                hipStream_t st);
 // T[c][j] = sum_s P[s][j][c] - d[c] qsum[j]  (T row-major n x ncols, FP64)
 hipError_t launch_reduce_t(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                           const double* d, const double* qsum, double* T, int64_t ldt, hipStream_t st);
+                           const float* col_scale, const double* d, const double* qsum, double* T, int64_t ldt,
+                           hipStream_t st);
 // flag |= nonfinite(x) over a float matrix
 hipError_t launch_check_finite_f32(const float* X, int64_t rows, int64_t cols, int64_t ld, int* flag,
                                    hipStream_t st);

@@ -62,6 +62,12 @@ struct rpca_plan_s {
   int fwd_ks = 1;  // K split of the forward product
   int64_t fwd_kchunk = 0;
   int64_t ldpf = 0;  // row stride of the forward split partials
+  int storage = RPCA_A_F32;
+  // low-precision storage: bfloat16 hi/lo planes of the float operand
+  int64_t ldxs = 0;  // X planes: cpad_x rows of ldxs (n rounded up to 64)
+  int cpad_x = 0;
+  int64_t ldzs = 0;  // transposed Z planes: cpad_z rows of ldzs (m rounded up to 32)
+  int cpad_z = 0;
 
   std::vector<void*> allocs;
   // device buffers
@@ -98,6 +104,10 @@ struct rpca_plan_s {
   double* sqp = nullptr;    // sum of squares partials
   float* corr = nullptr;    // L
   int* flags = nullptr;     // [0] nonfinite, [1] chol breakdown round 1, [2] round 2, [3] round 3
+  uint16_t* Xh = nullptr;   // low-precision storage only
+  uint16_t* Xl = nullptr;
+  uint16_t* Zh = nullptr;
+  uint16_t* Zl = nullptr;
   int64_t sqp_cap = 0;
 
   bool have_state = false;
@@ -192,7 +202,6 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   rpca_status vs = validate_desc(desc);
   if (vs != RPCA_OK) return vs;
   if (desc->source != RPCA_SRC_DEVICE) return RPCA_ERR_UNSUPPORTED;
-  if (desc->storage != RPCA_A_F32) return RPCA_ERR_UNSUPPORTED;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev) {
     (void)hipGetLastError();
@@ -225,12 +234,25 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   plan->ldp = round_up(n, 4);
 
   const int64_t slots = (int64_t)prop.multiProcessorCount * 2;  // two 256-thread blocks per CU
-  adj_split(m, n, l, slots, &plan->ns_y, &plan->rps_y);
-  adj_split(m, n, L, slots, &plan->ns_t, &plan->rps_t);
+  plan->storage = desc->storage;
+  const bool lowp = desc->storage != RPCA_A_F32;
+  if (lowp) {
+    const int64_t lp_slots = desc->storage == RPCA_A_BF16_HILO ? slots / 2 : slots;
+    adj_split_lp(m, n, l, lp_slots, &plan->ns_y, &plan->rps_y);
+    adj_split_lp(m, n, L, lp_slots, &plan->ns_t, &plan->rps_t);
+    fwd_split_lp(m, n, lp_slots, &plan->fwd_ks, &plan->fwd_kchunk);
+    plan->ldxs = round_up(n, 64);
+    plan->cpad_x = (int)round_up(l, 64);
+    plan->ldzs = round_up(m, 32);
+    plan->cpad_z = (int)round_up(L, 64);
+  } else {
+    adj_split(m, n, l, slots, &plan->ns_y, &plan->rps_y);
+    adj_split(m, n, L, slots, &plan->ns_t, &plan->rps_t);
+    fwd_split(m, n, slots, &plan->fwd_ks, &plan->fwd_kchunk);
+  }
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
   choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
   choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
-  fwd_split(m, n, slots, &plan->fwd_ks, &plan->fwd_kchunk);
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
 
   const int64_t ldx = plan->ldx;
@@ -278,6 +300,12 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(sqp, plan->sqp_cap);
   ALLOC(corr, L);
   ALLOC(flags, 8);
+  if (lowp) {
+    ALLOC(Xh, (int64_t)plan->cpad_x * plan->ldxs);
+    ALLOC(Xl, (int64_t)plan->cpad_x * plan->ldxs);
+    ALLOC(Zh, (int64_t)plan->cpad_z * plan->ldzs);
+    ALLOC(Zl, (int64_t)plan->cpad_z * plan->ldzs);
+  }
 #undef ALLOC
   // zero the padded transposed blocks and the shift once (padding must stay 0)
   if (hipMemset(plan->X, 0, sizeof(float) * (size_t)(i + 1) * l * ldx) != hipSuccess ||
@@ -334,7 +362,6 @@ rpca_status cholqr_round(rpca_plan_s* plan, bool x_f64, const void* X, double* X
 extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
                                    rpca_panel_cb cb, void* user, const float* G, float* U, int64_t ldu, float* S,
                                    float* V, int64_t ldv) {
-  (void)col_scale;
   (void)cb;
   (void)user;
   if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
@@ -353,7 +380,15 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const bool rescale = !(plan->d.flags & RPCA_FLAG_NO_RESCALE);
   const bool vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0);
   const int64_t ldx = plan->ldx;
-  const int64_t bpe = 4;  // bytes per stored element (F32)
+  const int storage = plan->storage;
+  const bool lowp = storage != RPCA_A_F32;
+  // low-precision formats are read 16 bytes at a time from 16-byte aligned rows
+  if (lowp && (!vec || lda % 16 != 0)) return RPCA_ERR_INVALID_ARG;
+  if (storage == RPCA_A_FP8_E4M3 && col_scale == nullptr) return RPCA_ERR_INVALID_ARG;
+  const float* cs = storage == RPCA_A_FP8_E4M3 ? col_scale : nullptr;
+  const int64_t plane = storage == RPCA_A_BF16_HILO ? m * lda : 0;
+  // bytes per stored element
+  const int64_t bpe = storage == RPCA_A_FP8_E4M3 ? 1 : (storage == RPCA_A_BF16 ? 2 : 4);
 
   RPCA_TRY(hipMemsetAsync(plan->flags, 0, 8 * sizeof(int), st));
 
@@ -362,11 +397,17 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   // plan's zero-filled buffer (never written for such a plan).
   const float* shift = plan->shift;
   const double* dres = nullptr;
+  // Low-precision storage has no in-register shift: d is the whole mean.
   if (center) {
-    RPCA_TRY(launch_colsum(ST_F32, A, lda, m, n, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
-    RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, n, 1.0 / (double)m, plan->mu, plan->shift, plan->dres,
-                                  st));
-    dres = plan->dres;
+    RPCA_TRY(launch_colsum(storage, A, lda, m, n, cs, plane, plan->rps_cs, plan->ns_cs, plan->csp, st));
+    if (lowp) {
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, n, 1.0 / (double)m, plan->mu, nullptr, nullptr, st));
+      dres = plan->mu;
+    } else {
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, n, 1.0 / (double)m, plan->mu, plan->shift, plan->dres,
+                                    st));
+      dres = plan->dres;
+    }
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
   }
@@ -405,7 +446,16 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       fa.ev_begin = ev->a;
       fa.ev_end = ev->b;
     }
-    RPCA_TRY(launch_fwd_f32(fa, st));
+    if (lowp) {
+      RPCA_TRY(launch_split_x(Xj, ldx, n, l, cs, plan->Xh, plan->Xl, plan->ldxs, plan->cpad_x, st));
+      fa.Xh = plan->Xh;
+      fa.Xl = plan->Xl;
+      fa.ldxs = plan->ldxs;
+      fa.plane = plane;
+      RPCA_TRY(launch_fwd_lowp(storage, fa, st));
+    } else {
+      RPCA_TRY(launch_fwd_f32(fa, st));
+    }
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
     if (j == i) break;
@@ -433,10 +483,19 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.ev_begin = ev->a;
       aa.ev_end = ev->b;
     }
-    RPCA_TRY(launch_adj_f32(aa, st));
+    if (lowp) {
+      RPCA_TRY(launch_split_zt(aa.Z, L, m, l, plan->Zh, plan->Zl, plan->ldzs, plan->cpad_z, st));
+      aa.Zh = plan->Zh;
+      aa.Zl = plan->Zl;
+      aa.ldzs = plan->ldzs;
+      aa.plane = plane;
+      RPCA_TRY(launch_adj_lowp(storage, aa, st));
+    } else {
+      RPCA_TRY(launch_adj_f32(aa, st));
+    }
     float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
     int npart = 0;
-    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, dres,
+    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, cs, dres,
                              center ? plan->zsum : nullptr, Xn, ldx, plan->sqp, &npart, st));
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
@@ -515,8 +574,17 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.ev_begin = ev->a;
       aa.ev_end = ev->b;
     }
-    RPCA_TRY(launch_adj_f32(aa, st));
-    RPCA_TRY(launch_reduce_t(plan->P, plan->ns_t, aa.split_stride, plan->ldp, L, n, dres,
+    if (lowp) {
+      RPCA_TRY(launch_split_zt(plan->Q32, L, m, L, plan->Zh, plan->Zl, plan->ldzs, plan->cpad_z, st));
+      aa.Zh = plan->Zh;
+      aa.Zl = plan->Zl;
+      aa.ldzs = plan->ldzs;
+      aa.plane = plane;
+      RPCA_TRY(launch_adj_lowp(storage, aa, st));
+    } else {
+      RPCA_TRY(launch_adj_f32(aa, st));
+    }
+    RPCA_TRY(launch_reduce_t(plan->P, plan->ns_t, aa.split_stride, plan->ldp, L, n, cs, dres,
                              center ? plan->zsum : nullptr, plan->T, L, st));
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
@@ -620,7 +688,43 @@ extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t ld
 }
 
 extern "C" rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out,
-                                     int64_t ldo, float* col_scale, void* hip_stream) {
-  (void)storage; (void)m; (void)n; (void)A; (void)lda; (void)out; (void)ldo; (void)col_scale; (void)hip_stream;
-  return RPCA_ERR_UNSUPPORTED;
+                                     int64_t ldo, float* col_scale, float* shift, int32_t shift_mode,
+                                     void* hip_stream) {
+  if (storage != RPCA_A_BF16 && storage != RPCA_A_FP8_E4M3 && storage != RPCA_A_BF16_HILO)
+    return RPCA_ERR_INVALID_ARG;
+  if (m <= 0 || n <= 0 || A == nullptr || out == nullptr || lda < n || ldo < n || ldo % 16 != 0 ||
+      (reinterpret_cast<uintptr_t>(out) & 15) != 0)
+    return RPCA_ERR_INVALID_ARG;
+  if (storage == RPCA_A_FP8_E4M3 && col_scale == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (shift_mode < 0 || shift_mode > 2 || (shift_mode != 0 && shift == nullptr)) return RPCA_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  int ns = 1;
+  int64_t rps = 0;
+  choose_rows(m, 4096, 256, &ns, &rps);
+  // scratch: column-sum partials (float64) and column maxima (float)
+  void* scratch = nullptr;
+  const size_t nbytes = (size_t)ns * (size_t)n * (sizeof(double) + sizeof(float)) + (size_t)n * sizeof(double);
+  hipError_t e = hipMalloc(&scratch, nbytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? RPCA_ERR_OUT_OF_MEMORY : RPCA_ERR_HIP;
+  }
+  double* csp = reinterpret_cast<double*>(scratch);
+  double* mu = csp + (size_t)ns * n;
+  float* amax = reinterpret_cast<float*>(mu + n);
+  if (shift_mode == 2) {
+    e = launch_colsum(ST_F32, A, lda, m, n, nullptr, 0, rps, ns, csp, st);
+    if (e == hipSuccess) e = launch_colsum_reduce(csp, ns, n, 1.0 / (double)m, mu, shift, nullptr, st);
+  }
+  if (e == hipSuccess)
+    e = launch_quantize(storage, m, n, A, lda, shift_mode != 0 ? shift : nullptr, out, ldo, col_scale, amax, ns, rps,
+                        st);
+  const hipError_t es = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = es;
+  (void)hipFree(scratch);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return RPCA_ERR_HIP;
+  }
+  return RPCA_OK;
 }

@@ -14,6 +14,50 @@ from . import _lib
 from ._lib import check, load, Desc, Stats, STORAGE, SOURCE, STATE, PANEL_CB
 
 _STATE_DTYPE = {"H": torch.float32}
+_STORED_DTYPE = {"bf16": torch.int16, "bf16_hilo": torch.int16, "fp8_e4m3": torch.uint8}
+
+
+class Stored:
+    """A matrix in one of the library's stored formats (output of :func:`quantize`).
+
+    data: bf16 -> int16 (m, ld) bit patterns; bf16_hilo -> int16 (2, m, ld) (hi plane, lo plane);
+    fp8_e4m3 -> uint8 (m, ld) codes with col_scale (n,) float32.  shift (n,) float32 or None is
+    the per-column value subtracted before conversion.
+    """
+
+    def __init__(self, storage, data, m, n, col_scale=None, shift=None):
+        self.storage, self.data, self.m, self.n = storage, data, int(m), int(n)
+        self.col_scale, self.shift = col_scale, shift
+        self.ld = data.stride(-2)
+
+
+def quantize(A, storage, shift=None, ld=None):
+    """Convert a float32 device matrix with rpca_quantize.
+
+    shift: None (no shift), "mean" (column means computed by the library), or an (n,) float32 tensor.
+    """
+    lib = load()
+    if A.dtype != torch.float32 or A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a row-major 2-D float32 tensor")
+    m, n = A.shape
+    ld = int(ld) if ld is not None else (n + 15) // 16 * 16
+    dt = _STORED_DTYPE[storage]
+    shape = (2, m, ld) if storage == "bf16_hilo" else (m, ld)
+    data = torch.empty(shape, dtype=dt, device=A.device)
+    col_scale = torch.empty((n,), dtype=torch.float32, device=A.device) if storage == "fp8_e4m3" else None
+    if shift is None:
+        mode, sh = 0, None
+    elif isinstance(shift, str):
+        if shift != "mean":
+            raise ValueError("shift must be None, 'mean' or a tensor")
+        mode, sh = 2, torch.empty((n,), dtype=torch.float32, device=A.device)
+    else:
+        if shift.dtype != torch.float32 or tuple(shift.shape) != (n,) or not shift.is_contiguous():
+            raise ValueError(f"shift must be a contiguous float32 ({n},) tensor")
+        mode, sh = 1, shift
+    check(lib.rpca_quantize(STORAGE[storage], m, n, _ptr(A), A.stride(0), _ptr(data), ld, _ptr(col_scale),
+                            _ptr(sh), mode, _stream(A.device)), "rpca_quantize")
+    return Stored(storage, data, m, n, col_scale=col_scale, shift=sh)
 
 
 def _ptr(t):
@@ -65,11 +109,20 @@ class Plan:
         self.close()
 
     def factor(self, A, G=None, col_scale=None, out=None):
+        """A: a float32 row-major tensor (f32 plans) or a :class:`Stored` from :func:`quantize`."""
         m, n, k = self.m, self.n, self.k
-        if A.device != self.device:
+        if isinstance(A, Stored):
+            if A.storage != self.storage or A.m != m or A.n != n:
+                raise ValueError(f"stored matrix is {A.storage} {A.m} x {A.n}; plan is {self.storage} {m} x {n}")
+            data, lda, col_scale = A.data, A.ld, A.col_scale
+        else:
+            if self.storage != "f32":
+                raise ValueError("a low-precision plan takes the Stored result of quantize()")
+            if A.dim() != 2 or A.shape[0] < m or A.stride(1) != 1 or A.dtype != torch.float32:
+                raise ValueError("A must be a row-major 2-D float32 tensor")
+            data, lda = A, A.stride(0)
+        if data.device != self.device:
             raise ValueError("A must live on the plan's device")
-        if A.dim() != 2 or A.shape[0] < m or A.stride(1) != 1:
-            raise ValueError("A must be a row-major 2-D tensor")
         if G is not None:
             if G.dtype != torch.float32 or tuple(G.shape) != (n, self.l) or not G.is_contiguous():
                 raise ValueError(f"G must be a contiguous float32 {n} x {self.l} tensor")
@@ -79,9 +132,8 @@ class Plan:
             V = torch.empty((n, k), dtype=torch.float32, device=self.device)
         else:
             U, S, V = out
-        lda = A.stride(0)
         cb = PANEL_CB()
-        rc = self.lib.rpca_factor(self.handle, _ptr(A), lda, _ptr(col_scale), cb, None, _ptr(G),
+        rc = self.lib.rpca_factor(self.handle, _ptr(data), lda, _ptr(col_scale), cb, None, _ptr(G),
                                   _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0))
         check(rc, "rpca_factor")
         return U, S, V

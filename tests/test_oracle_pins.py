@@ -308,3 +308,53 @@ def test_planted_mistakes_are_caught(monkeypatch):
     bad = O.rpca(p["A"], 4, 5, 1, G2, center=True)
     assert np.abs(np.ones(200) @ good.U).max() < 1e-10
     assert np.abs(np.ones(200) @ bad.U).max() > 1e-3
+
+
+# ---------------------------------------------------------------- stored formats (reference definitions)
+def test_bf16_reference_rounding():
+    """bf16 rounding is nearest (half an ulp, 2^-9 relative at most); hi+lo keeps 16 bits."""
+    from oracle import quantize_ref as Qr
+    rng = np.random.default_rng(1)
+    v = rng.standard_normal(100000).astype(np.float32)
+    r = Qr.bf16_to_f32(Qr.bf16_bits(v)).astype(np.float64)
+    assert np.all(np.abs(r - v) <= np.abs(v) * 2.0 ** -8)
+    # exactly representable values pass through unchanged
+    exact = np.array([1.0, -2.5, 0.0, 2.0 ** -100, 3.0 * 2.0 ** 60], dtype=np.float32)
+    assert np.array_equal(Qr.bf16_to_f32(Qr.bf16_bits(exact)), exact)
+    hi, lo = Qr.hilo_bits(v)
+    rr = Qr.dequantize("bf16_hilo", (hi, lo))
+    assert np.all(np.abs(rr - v) <= np.abs(v) * 2.0 ** -16)
+
+
+def test_bf16_ties_to_even():
+    from oracle import quantize_ref as Qr
+    one = np.float32(1.0)
+    tie = np.float32(1.0 + 2.0 ** -8)          # halfway between 1 and 1 + 2^-7
+    above = np.float32(1.0 + 2.0 ** -8 + 2.0 ** -15)
+    tie_odd = np.float32(1.0 + 3 * 2.0 ** -8)  # halfway between 1+2^-7 (odd) and 1+2^-6 (even)
+    r = Qr.bf16_to_f32(Qr.bf16_bits(np.array([one, tie, above, tie_odd], dtype=np.float32)))
+    assert list(r) == [1.0, 1.0, 1.0 + 2.0 ** -7, 1.0 + 2.0 ** -6]
+
+
+def test_e4m3_reference_codes():
+    """OCP E4M3: max 448, min subnormal 2^-9, NaN only at S.1111.111, ties to even, saturation."""
+    from oracle import quantize_ref as Qr
+    t = Qr.E4M3
+    assert t[0x7E] == 448.0 and np.isnan(t[0x7F]) and np.isnan(t[0xFF])
+    assert t[0x01] == 2.0 ** -9 and t[0x08] == 2.0 ** -6 and t[0x38] == 1.0
+    pos = t[:0x7F]
+    assert np.all(np.diff(pos) > 0)
+    codes = Qr.e4m3_bits(np.array([0.0, 1.0, -1.0, 448.0, 1000.0, -1000.0, 2.0 ** -10, 3 * 2.0 ** -10,
+                                   1.0 + 1.0 / 16, 1.0 + 3.0 / 16], dtype=np.float32))
+    # 2^-10 is a tie between 0 and 2^-9 -> 0 (even); 3*2^-10 between 2^-9 (code 1) and 2^-8 (code 2) -> 2
+    # 1+1/16 ties 1 (code 0x38) and 1.125 (0x39) -> 0x38; 1+3/16 ties 1.125 and 1.25 (0x3A) -> 0x3A
+    assert list(codes) == [0x00, 0x38, 0xB8, 0x7E, 0x7E, 0xFE, 0x00, 0x02, 0x38, 0x3A]
+    rng = np.random.default_rng(2)
+    v = (rng.standard_normal(50000) * 50).astype(np.float32)
+    q = Qr.e4m3_bits(v)
+    back = t[q]
+    inrange = np.abs(v) <= 448
+    # nearest representable value: no code is strictly closer
+    err = np.abs(back[inrange] - v[inrange])
+    nearest = np.min(np.abs(pos[None, :] - np.abs(v[inrange])[:, None]), axis=1)
+    assert np.all(err <= nearest + 1e-12)
