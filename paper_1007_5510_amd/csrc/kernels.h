@@ -65,8 +65,9 @@ void adj_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int6
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st);
 hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st);
 hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st);
-void fwd_split_lp(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);
-void adj_split_lp(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);
+void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);
+void adj_split_lp(int storage, int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit,
+                  int64_t* rows_per_split);
 // hi/lo bfloat16 planes of (col_scale o Xt): cpad x ldxs (ldxs % 64 == 0, cpad % 64 == 0)
 hipError_t launch_split_x(const float* Xt, int64_t ldx, int64_t n, int ncols, const float* col_scale,
                           uint16_t* Xh, uint16_t* Xl, int64_t ldxs, int cpad, hipStream_t st);

@@ -169,14 +169,57 @@ __global__ __launch_bounds__(256) void split_zt_kernel(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// forward: a wave owns 64 rows (two 32-row tiles) x 64 columns (two tiles);
-// a block of 4 waves 256 rows.  X hi/lo is staged per block in LDS, 64 K per
-// stage, double buffered; A goes to registers, 16 bytes per lane per load.
+// Pipelining (both kernels).  Both streamed operands go from global memory
+// straight into LDS (global_load_lds_dwordx4: lane l's 16 bytes land at
+// M0 + 16 l), through a ring of NB stages: the loads of stage t + NB - 1 are
+// issued as soon as the workgroup has finished stage t - 1, so NB - 1 stages
+// are in flight without costing registers.  A is private to each wave (its
+// slot holds exactly the bytes each lane would have loaded, read back at
+// lane * 16, conflict-free); the float operand (X or Z hi/lo) is shared by
+// the workgroup and stored with the 16-byte chunk index XOR-swizzled by the
+// column (chunk c of column j at position c ^ (j & 7)), which makes the
+// column-strided 16-byte operand reads conflict-free.  Every wave issues the
+// same number of loads per stage (addresses clamped past the end), so a
+// counted s_waitcnt vmcnt(P (NB - 2)) means "this wave's loads of the
+// current stage have landed"; a plain s_barrier after it makes all waves'
+// loads visible.  No __syncthreads (its fence would wait for every load).
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef const __attribute__((address_space(1))) void* gbl_ptr_t;
+
+RPCA_DEV void dma16(const void* g, void* lds) {
+  __builtin_amdgcn_global_load_lds((gbl_ptr_t)g, (lds_ptr_t)lds, 16, 0, 0);
+}
+
+// s_waitcnt immediate (gfx9 encoding): vmcnt <= vm, lgkmcnt <= lgkm, expcnt not waited
+constexpr int waitcnt_imm(int vm, int lgkm) {
+  return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | ((lgkm & 15) << 8);
+}
+
+template <int ST>
+struct LpCfg {
+  static constexpr int ES = ST == ST_FP8 ? 1 : 2;  // bytes per stored element
+  static constexpr int W = ST == ST_HILO ? 4 : 8;  // waves per workgroup
+  static constexpr int NB = ST == ST_FP8 ? 4 : 3;  // ring stages
+  // A bytes per wave per stage: 32 rows x 64 K (forward) or 64 rows x 32 columns (adjoint)
+  static constexpr int SA = 2048 * ES * (ST == ST_HILO ? 2 : 1);
+  static constexpr int AQ = SA / 1024;         // 16-byte loads per lane per stage for A
+  static constexpr int XQ = 16 / W;            // loads per lane per stage for the shared operand
+  static constexpr int P = AQ + XQ;            // loads per lane per stage
+  static constexpr int SX = 16384;             // shared operand bytes per stage (2 planes x 64 x 64 bf16)
+  static constexpr int LDS = NB * (SX + W * SA);
+};
+
+// swizzled byte offset of 16-byte chunk c of column j (128-byte rows)
+RPCA_DEV int swz(int j, int c) { return j * 128 + 16 * (c ^ (j & 7)); }
+
+// ---------------------------------------------------------------------------
+// forward: a wave owns 32 rows x 64 columns (two tiles of 32); a workgroup of
+// W waves 32 W rows.  Stage = 64 K = 4 MFMA steps.
 // K offsets within a stage of the 8-entry group of MFMA step s, lane group g:
 //   bf16 / hi+lo: 16 s + 8 g;   fp8: 32 (s/2) + 16 g + 8 (s%2)  (16-byte loads)
 // ---------------------------------------------------------------------------
 constexpr int LP_KST = 64;
-constexpr int LP_XP = LP_KST + 8;  // LDS row of 72 bf16 (144 B)
 
 template <int ST>
 RPCA_DEV int lp_koff(int s, int g) {
@@ -184,200 +227,192 @@ RPCA_DEV int lp_koff(int s, int g) {
 }
 
 template <int ST>
-struct FwdStage {
-  static constexpr int NL = ST == ST_FP8 ? 2 : (ST == ST_HILO ? 8 : 4);  // 16-byte loads per row tile
-  u32x4 a[2][NL];
-};
-
-template <int ST>
-__global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void fwd_lp_kernel(
+__global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void fwd_lp_kernel(
     const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, int64_t plane,
     const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl, int64_t ldxs, int ncols, int64_t kchunk,
     const float* __restrict__ corr, const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz,
     int64_t split_stride, int direct) {
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][2][64][LP_XP];  // [buffer][hi, lo][column][k]
-  constexpr int ES = ST == ST_FP8 ? 1 : 2;  // bytes per stored element
-  constexpr int NL = FwdStage<ST>::NL;
+  using C = LpCfg<ST>;
+  constexpr int ES = C::ES, W = C::W, NB = C::NB, SA = C::SA, AQ = C::AQ, XQ = C::XQ, P = C::P, SX = C::SX;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, g = lane >> 5;
-  const int64_t r0 = (int64_t)blockIdx.x * 256 + wave * 64;
+  const int64_t r0 = (int64_t)blockIdx.x * (32 * W) + wave * 32;
   const int sk = blockIdx.y;
   const int c0 = blockIdx.z * 64;
   const int64_t kbeg = (int64_t)sk * kchunk;
   const int64_t kend = kbeg + kchunk < n ? kbeg + kchunk : n;
-  const unsigned char* __restrict__ arow[2];
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    const int64_t r = r0 + 32 * rt + li;
-    arow[rt] = reinterpret_cast<const unsigned char*>(Av) + (r < m ? r : m - 1) * lda * ES;
-  }
+  const int64_t row = r0 + li;
+  const unsigned char* __restrict__ arow =
+      reinterpret_cast<const unsigned char*>(Av) + (row < m ? row : m - 1) * lda * ES;
   const int64_t plane_bytes = plane * ES;
-  // cooperative X loader: chunk e = tid + 256 q -> plane e/512, column (e/8)%64, k 8 (e%8)
-  const uint16_t* xsrc[4];
-  int xdst[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
-    const int pl = e >> 9, col = (e >> 3) & 63, kq = e & 7;
-    xsrc[q] = (pl ? Xl : Xh) + (int64_t)(c0 + col) * ldxs + 8 * kq;
-    xdst[q] = ((pl * 64 + col) * LP_XP) + 8 * kq;
-  }
+  unsigned char* const xring = lds;                                // NB x SX
+  unsigned char* const aring = lds + NB * SX + wave * (NB * SA);   // this wave's NB x SA
 
-  floatx16 acc[2][2], acc2[2][2];
+  // shared-operand loads of this wave: instruction j covers plane j/8, columns 8 (j%8) .. +7
+  const uint16_t* xsrc[XQ];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[rt][ct][v] = 0.f;
-        acc2[rt][ct][v] = 0.f;
-      }
-  auto fold = [&]() {
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct) {
-        acc2[rt][ct] += acc[rt][ct];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[rt][ct][v] = 0.f;
-      }
-  };
-  // byte offset (within a row) of 16-byte load q of a stage at K position kb
+  for (int q = 0; q < XQ; ++q) {
+    const int j = wave * XQ + q;
+    const int col = 8 * (j & 7) + (lane >> 3);
+    const int c = (lane & 7) ^ (col & 7);
+    xsrc[q] = ((j >> 3) ? Xl : Xh) + (int64_t)(c0 + col) * ldxs + 8 * c;
+  }
+  // byte offset (within the row) of A load q of the stage at K position kb
   auto aoff = [&](int q, int64_t kb) -> int64_t {
     if (ST == ST_FP8) return kb + 32 * q + 16 * g;
     if (ST == ST_HILO) return (q & 4 ? plane_bytes : 0) + 2 * (kb + 16 * (q & 3) + 8 * g);
     return 2 * (kb + 16 * q + 8 * g);
   };
-  // element index of the first entry of load q (for tail masking) and its length
   auto aelem = [&](int q, int64_t kb) -> int64_t {
     if (ST == ST_FP8) return kb + 32 * q + 16 * g;
     return kb + 16 * (q & 3) + 8 * g;
   };
-  auto load_a = [&](FwdStage<ST>& b, int64_t kb) {
+
+  const int64_t nfull = (kend - kbeg) / LP_KST;
+  const int64_t kt = kbeg + nfull * LP_KST;
+  const bool tail = kt < kend;
+  const int64_t nst = nfull + (tail ? 1 : 0);  // stages that need X
+  // issue the P loads of stage t into ring slot t % NB (A clamped to full stages, X to all stages)
+  auto issue = [&](int64_t t, int slot) {
+    const int64_t tx = t < nst ? t : nst - 1;
+    const int64_t ta = t < nfull ? t : (nfull > 0 ? nfull - 1 : 0);
+    const int64_t kbx = kbeg + tx * LP_KST;
+    const int64_t kba = kbeg + ta * LP_KST;
+    unsigned char* xs = xring + slot * SX;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int q = 0; q < XQ; ++q) dma16(xsrc[q] + kbx, xs + 1024 * (wave * XQ + q));
+    unsigned char* as = aring + slot * SA;
+    if (nfull > 0) {
 #pragma unroll
-      for (int q = 0; q < NL; ++q) b.a[rt][q] = ld16(arow[rt] + aoff(q, kb));
-  };
-  auto load_a_tail = [&](FwdStage<ST>& b, int64_t kb) {
+      for (int q = 0; q < AQ; ++q) dma16(arow + aoff(q, kba), as + 1024 * q);
+    } else {  // no full stage: keep the load count with an in-bounds dummy source (never used)
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int64_t e0 = aelem(q, kb);
-        const int64_t valid = kend - e0;
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (valid > 0) {
-          v = ld16(arow[rt] + aoff(q, kb));
-          if (ST == ST_FP8)
-            v = keep_u8(v, valid < 16 ? (int)valid : 16);
-          else
-            v = keep_bf16(v, valid < 8 ? (int)valid : 8);
-        }
-        b.a[rt][q] = v;
-      }
-  };
-  struct XStage {
-    u32x4 x[4];
-  };
-  auto load_x = [&](XStage& b, int64_t kb) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) b.x[q] = ld16(xsrc[q] + kb);
-  };
-  auto store_x = [&](const XStage& b, int buf) {
-    uint16_t* base = &Xs[buf][0][0][0];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) *reinterpret_cast<u32x4*>(base + xdst[q]) = b.x[q];
-  };
-  // A operand (bf16 bits) of row tile rt, MFMA step s; lo plane when LO
-  auto a_op = [&](const FwdStage<ST>& b, int rt, int s, bool lo) -> u32x4 {
-    if (ST == ST_FP8) {
-      const u32x4 w = b.a[rt][s >> 1];
-      return (s & 1) ? fp8x8_to_bf16(w.z, w.w) : fp8x8_to_bf16(w.x, w.y);
-    }
-    if (ST == ST_HILO) return b.a[rt][s + (lo ? 4 : 0)];
-    return b.a[rt][s];
-  };
-  // One stage of MFMAs.  With REFILL, the registers of each A load are
-  // reloaded from the next stage (K position kn) right after their last use,
-  // so one register stage gives one stage of prefetch distance.
-  auto compute = [&](FwdStage<ST>& b, int buf, bool refill, int64_t kn) {
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int ko = lp_koff<ST>(s, g);
-      u32x4 xo[2][2];
-#pragma unroll
-      for (int ct = 0; ct < 2; ++ct)
-#pragma unroll
-        for (int hl = 0; hl < 2; ++hl) xo[ct][hl] = ld16(&Xs[buf][hl][32 * ct + li][ko]);
-      u32x4 a[2], al[2];
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt) {
-        a[rt] = a_op(b, rt, s, false);
-        if (ST == ST_HILO) al[rt] = a_op(b, rt, s, true);
-      }
-      // hi parts for the four accumulators, then lo parts (independent chains back to back)
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = mfma_bf16(a[rt], xo[ct][0], acc[rt][ct]);
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = mfma_bf16(a[rt], xo[ct][1], acc[rt][ct]);
-      if (ST == ST_HILO) {
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = mfma_bf16(al[rt], xo[ct][0], acc[rt][ct]);
-      }
-      if (refill) {
-#pragma unroll
-        for (int rt = 0; rt < 2; ++rt) {
-          if (ST == ST_FP8) {
-            if (s & 1) b.a[rt][s >> 1] = ld16(arow[rt] + aoff(s >> 1, kn));
-          } else {
-            b.a[rt][s] = ld16(arow[rt] + aoff(s, kn));
-            if (ST == ST_HILO) b.a[rt][s + 4] = ld16(arow[rt] + aoff(s + 4, kn));
-          }
-        }
-      }
+      for (int q = 0; q < AQ; ++q) dma16(Xh + 8 * lane, as + 1024 * q);
     }
   };
 
-  const int64_t nfull = (kend - kbeg) / LP_KST;
-  int it = 0;
-  FwdStage<ST> ac;
-  if (nfull > 0) {
-    XStage xr;
-    load_x(xr, kbeg);
-    load_a(ac, kbeg);
-    store_x(xr, 0);
-    __syncthreads();
-    for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * LP_KST;
-      load_x(xr, kn);
-      compute(ac, (int)(st & 1), true, kn);
-      store_x(xr, (int)((st + 1) & 1));
-      __syncthreads();
-      if (++it == 2) {  // fold every 2 stages (128 K, 256 products per chain with hi + lo)
-        it = 0;
-        fold();
+  floatx16 acc[2], acc2[2];
+#pragma unroll
+  for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      acc[ct][v] = 0.f;
+      acc2[ct][v] = 0.f;
+    }
+  auto fold = [&]() {
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      acc2[ct] += acc[ct];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[ct][v] = 0.f;
+    }
+  };
+  auto read_x = [&](u32x4 (&xo)[2][2], const unsigned char* xs, int s) {
+    const int c = lp_koff<ST>(s, g) >> 3;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int hl = 0; hl < 2; ++hl) xo[ct][hl] = ld16(xs + hl * 8192 + swz(32 * ct + li, c));
+  };
+  // A operands (hi, lo) of step s; `mask` >= 0 keeps only entries with K < kend (tail stage)
+  auto read_a = [&](const unsigned char* as, int s, int64_t kb, bool masked, u32x4& ah, u32x4& al) {
+    if (ST == ST_FP8) {
+      u32x4 w = ld16(as + 1024 * (s >> 1) + 16 * lane);
+      if (masked) {
+        const int64_t valid = kend - aelem(s >> 1, kb);
+        w = keep_u8(w, valid <= 0 ? 0 : (valid >= 16 ? 16 : (int)valid));
+      }
+      ah = (s & 1) ? fp8x8_to_bf16(w.z, w.w) : fp8x8_to_bf16(w.x, w.y);
+    } else {
+      ah = ld16(as + 1024 * s + 16 * lane);
+      if (ST == ST_HILO) al = ld16(as + 1024 * (s + 4) + 16 * lane);
+      if (masked) {
+        const int64_t valid = kend - aelem(s, kb);
+        const int v = valid <= 0 ? 0 : (valid >= 8 ? 8 : (int)valid);
+        ah = keep_bf16(ah, v);
+        if (ST == ST_HILO) al = keep_bf16(al, v);
       }
     }
+  };
+  auto compute = [&](int slot, int64_t kb, bool masked) {
+    const unsigned char* xs = xring + slot * SX;
+    const unsigned char* as = aring + slot * SA;
+    u32x4 xo[2][2], xn[2][2], ah, al, nh, nl;
+    read_x(xo, xs, 0);
+    read_a(as, 0, kb, masked, ah, al);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if (s < 3) {  // operands of the next step are read while this step runs
+        read_x(xn, xs, s + 1);
+        read_a(as, s + 1, kb, masked, nh, nl);
+      }
+#pragma unroll
+      for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma_bf16(ah, xo[ct][hl], acc[ct]);
+      if (ST == ST_HILO) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma_bf16(al, xo[ct][0], acc[ct]);
+      }
+      if (s < 3) {
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl) xo[ct][hl] = xn[ct][hl];
+        ah = nh;
+        al = nl;
+      }
+    }
+  };
+  // wait for this wave's loads of the current stage (NB - 2 younger stages may stay in flight)
+  // and its LDS reads, then meet the other waves
+  auto stage_sync = [&]() {
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(P * (NB - 2), 0));
+    __builtin_amdgcn_s_barrier();
+  };
+
+  if (nst > 0) {
+#pragma unroll
+    for (int u = 0; u < NB - 1; ++u) issue(u, u);
   }
-  const int64_t kt = kbeg + nfull * LP_KST;
-  if (kt < kend) {  // tail stage: X is zero-padded to a whole stage, A masked by column
-    XStage xt;
-    load_x(xt, kt);
-    load_a_tail(ac, kt);
-    store_x(xt, (int)(nfull & 1));
-    __syncthreads();
-    compute(ac, (int)(nfull & 1), false, kt);
+  int64_t t = 0;
+  for (; t + NB <= nfull; t += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      stage_sync();
+      issue(t + u + NB - 1, (u + NB - 1) % NB);  // into the slot stage t+u-1 used
+      compute(u, 0, false);
+    }
+    fold();  // NB stages per float32 chain before folding
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    if (t + u < nfull) {  // leftover full stages (same issue pattern keeps the counts uniform)
+      stage_sync();
+      issue(t + u + NB - 1, (u + NB - 1) % NB);
+      compute(u, 0, false);
+    }
   }
   fold();
+  if (tail) {
+    // X of stage nfull is (or will be) in slot nfull % NB; A of the tail is reloaded masked
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
+    __builtin_amdgcn_s_barrier();
+    const int slot = (int)(nfull % NB);
+    unsigned char* as = aring + slot * SA;
+#pragma unroll
+    for (int q = 0; q < AQ; ++q) {
+      const int64_t valid = kend - aelem(q, kt);
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (valid > 0) v = ld16(arow + aoff(q, kt));
+      *reinterpret_cast<u32x4*>(as + 1024 * q + 16 * lane) = v;
+    }
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
+    compute(slot, kt, true);
+    fold();
+  }
 
   const double alpha = (direct && alpha_ptr != nullptr) ? *alpha_ptr : 1.0;
   float* __restrict__ Zs = Z + (direct ? 0 : (int64_t)sk * split_stride);
@@ -387,12 +422,10 @@ __global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void fwd_lp_kernel(
     if (c >= ncols) continue;
     const double cr = (direct && corr != nullptr) ? (double)corr[c] : 0.0;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = r0 + 32 * rt + 8 * (v >> 2) + 4 * g + (v & 3);
-        if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * ((double)acc2[rt][ct][v] - cr)) : acc2[rt][ct][v];
-      }
+    for (int v = 0; v < 16; ++v) {
+      const int64_t r = r0 + 8 * (v >> 2) + 4 * g + (v & 3);
+      if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * ((double)acc2[ct][v] - cr)) : acc2[ct][v];
+    }
   }
 }
 
@@ -414,32 +447,27 @@ __global__ __launch_bounds__(256) void fwd_lp_reduce_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// adjoint: a wave owns 64 columns of A (two 32-column tiles) and 64 columns
-// of Z (two tiles); a block of 4 waves 256 columns of A.  Rows of the split
-// are walked 32 at a time; Z hi/lo for the stage is staged in LDS.
-// Lane i + 32 g loads columns 16 g .. 16 g + 15 of its row within a tile;
+// adjoint: a wave owns 32 columns of A and 64 columns of Z (two tiles); a
+// workgroup of W waves 32 W columns of A.  Stage = 64 rows (two 32-row
+// halves).  Lane i + 32 g loads columns 16 g .. 16 g + 15 of row i of a half;
 // after the transposing MFMAs lane j + 32 h holds tile column
 //   cmap(j) = 16 ((j % 16) / 8) + 8 (j / 16) + j % 8
-// at rows 8 (v/4) + 4 h + v%4 (register v).
+// at rows 8 (v/4) + 4 h + v%4 (register v) of the half.  The Z planes hold
+// rows permuted within 32-row groups so that the 8-row chunk 4 h + 2 s + g of
+// a stage is the B operand of half h, step s (alpha 0, beta 1), lane group g.
 // ---------------------------------------------------------------------------
-constexpr int LA_RS = 32;
-constexpr int LA_ZP = LA_RS + 8;  // LDS row of 40 bf16 (80 B)
+constexpr int LA_RS = 64;
 
 template <int ST>
-struct AdjStage {
-  static constexpr int NL = ST == ST_FP8 ? 1 : (ST == ST_HILO ? 4 : 2);  // 16-byte loads per tile
-  u32x4 a[2][NL];
-};
-
-template <int ST>
-__global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void adj_lp_kernel(
+__global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
     const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, int64_t plane,
     const uint16_t* __restrict__ Zh, const uint16_t* __restrict__ Zl, int64_t ldzs, int ncols,
     int64_t rows_per_split, int jtiles, int ctiles, int nsplit, float* __restrict__ P, int64_t ldp,
     int64_t split_stride) {
-  __shared__ __attribute__((aligned(16))) uint16_t Zs[2][2][64][LA_ZP];  // [buffer][hi, lo][Z column][permuted row]
-  constexpr int ES = ST == ST_FP8 ? 1 : 2;
-  constexpr int NL = AdjStage<ST>::NL;
+  using C = LpCfg<ST>;
+  constexpr int ES = C::ES, W = C::W, NB = C::NB, SA = C::SA, AQ = C::AQ, XQ = C::XQ, PQ = C::P, SX = C::SX;
+  constexpr int HQ = AQ / 2;  // A loads per 32-row half
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const int64_t total = (int64_t)jtiles * ctiles * nsplit;
   const int64_t logical = xcd_remap_lp(blockIdx.x, total);
   const int jt = (int)(logical % jtiles);
@@ -450,22 +478,18 @@ __global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void adj_lp_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, g = lane >> 5;
-  const int64_t cw = (int64_t)ct * 256 + wave * 64;
+  const int64_t cw = (int64_t)ct * (32 * W) + wave * 32;
   const int j0 = jt * 64;
   const int64_t rbeg = (int64_t)sp * rows_per_split;
   const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
   const int64_t plane_bytes = plane * ES;
+  unsigned char* const zring = lds;
+  unsigned char* const aring = lds + NB * SX + wave * (NB * SA);
 
-  // this lane's 16 columns of each tile: address (clamped to column 0 past n) and valid count
-  int64_t coff[2];
-  int cvalid[2];
-#pragma unroll
-  for (int at = 0; at < 2; ++at) {
-    const int64_t c = cw + 32 * at + 16 * g;
-    const int64_t v = n - c;
-    cvalid[at] = v <= 0 ? 0 : (v >= 16 ? 16 : (int)v);
-    coff[at] = (c < n ? c : 0) * ES;
-  }
+  // this lane's 16 columns: address (column 0 past n) and valid count
+  const int64_t cA = cw + 16 * g;
+  const int cvalid = n - cA <= 0 ? 0 : (n - cA >= 16 ? 16 : (int)(n - cA));
+  const int64_t coff = (cA < n ? cA : 0) * ES;
   // routing matrices of the transpose (bf16 1.0 = 0x3F80)
   u32x4 E1 = {0u, 0u, 0u, 0u}, E2 = {0u, 0u, 0u, 0u};
   {
@@ -478,71 +502,60 @@ __global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void adj_lp_kernel(
         E2[e >> 1] = one;
     }
   }
-  // cooperative Z loader: chunk e = tid + 256 q -> plane e/256, column (e/4)%64, rows 8 (e%4)
-  const uint16_t* zsrc[2];
-  int zdst[2];
+  // shared Z loads of this wave: instruction j covers plane j/8, Z columns 8 (j%8) .. +7
+  const uint16_t* zsrc[XQ];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int e = tid + 256 * q;
-    const int pl = e >> 8, col = (e >> 2) & 63, rq = e & 3;
-    zsrc[q] = (pl ? Zl : Zh) + (int64_t)(j0 + col) * ldzs + 8 * rq;
-    zdst[q] = (pl * 64 + col) * LA_ZP + 8 * rq;
+  for (int q = 0; q < XQ; ++q) {
+    const int j = wave * XQ + q;
+    const int col = 8 * (j & 7) + (lane >> 3);
+    const int c = (lane & 7) ^ (col & 7);
+    zsrc[q] = ((j >> 3) ? Zl : Zh) + (int64_t)(j0 + col) * ldzs + 8 * c;
   }
-
-  floatx16 acc[2][2], acc2[2][2];
+  // rows past m read row m-1 (finite) against zero Z rows
+  const int64_t nfull = rend > rbeg ? (rend - rbeg + LA_RS - 1) / LA_RS : 0;
+  auto issue = [&](int64_t t, int slot) {
+    const int64_t tc = t < nfull ? t : nfull - 1;
+    const int64_t rb = rbeg + tc * LA_RS;
+    unsigned char* zs = zring + slot * SX;
 #pragma unroll
-  for (int at = 0; at < 2; ++at)
+    for (int q = 0; q < XQ; ++q) dma16(zsrc[q] + rb, zs + 1024 * (wave * XQ + q));
+    unsigned char* as = aring + slot * SA;
 #pragma unroll
-    for (int zt = 0; zt < 2; ++zt)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[at][zt][v] = 0.f;
-        acc2[at][zt][v] = 0.f;
-      }
-  auto fold = [&]() {
-#pragma unroll
-    for (int at = 0; at < 2; ++at)
-#pragma unroll
-      for (int zt = 0; zt < 2; ++zt) {
-        acc2[at][zt] += acc[at][zt];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[at][zt][v] = 0.f;
-      }
-  };
-  auto load_a = [&](AdjStage<ST>& b, int64_t rb) {
-    const int64_t r = rb + li < m ? rb + li : m - 1;
-    const unsigned char* base = reinterpret_cast<const unsigned char*>(Av) + r * lda * ES;
-#pragma unroll
-    for (int at = 0; at < 2; ++at) {
-      const unsigned char* p = base + coff[at];
+    for (int h = 0; h < 2; ++h) {
+      const int64_t r = rb + 32 * h + li < m ? rb + 32 * h + li : m - 1;
+      const unsigned char* p = reinterpret_cast<const unsigned char*>(Av) + r * lda * ES + coff;
       if (ST == ST_FP8) {
-        b.a[at][0] = ld16(p);
+        dma16(p, as + 1024 * h);
       } else {
-        b.a[at][0] = ld16(p);
-        b.a[at][1] = ld16(p + 16);
+        dma16(p, as + 1024 * (HQ * h));
+        dma16(p + 16, as + 1024 * (HQ * h + 1));
         if (ST == ST_HILO) {
-          b.a[at][2] = ld16(p + plane_bytes);
-          b.a[at][3] = ld16(p + plane_bytes + 16);
+          dma16(p + plane_bytes, as + 1024 * (HQ * h + 2));
+          dma16(p + plane_bytes + 16, as + 1024 * (HQ * h + 3));
         }
       }
     }
   };
-  struct ZStage {
-    u32x4 z[2];
-  };
-  auto load_z = [&](ZStage& b, int64_t rb) {
+
+  floatx16 acc[2], acc2[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) b.z[q] = ld16(zsrc[q] + rb);
-  };
-  auto store_z = [&](const ZStage& b, int buf) {
-    uint16_t* base = &Zs[buf][0][0][0];
+  for (int zt = 0; zt < 2; ++zt)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) *reinterpret_cast<u32x4*>(base + zdst[q]) = b.z[q];
+    for (int v = 0; v < 16; ++v) {
+      acc[zt][v] = 0.f;
+      acc2[zt][v] = 0.f;
+    }
+  auto fold = [&]() {
+#pragma unroll
+    for (int zt = 0; zt < 2; ++zt) {
+      acc2[zt] += acc[zt];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[zt][v] = 0.f;
+    }
   };
-  // transposed operands (alpha: tile rows 0..15, beta: rows 16..31) of tile `at`
-  auto transpose = [&](u32x4 t1, u32x4 t2, int valid, u32x4& oa, u32x4& ob) {
-    t1 = keep_bf16(t1, valid < 8 ? valid : 8);
-    t2 = keep_bf16(t2, valid > 8 ? valid - 8 : 0);
+  auto transpose = [&](u32x4 t1, u32x4 t2, u32x4& oa, u32x4& ob) {
+    t1 = keep_bf16(t1, cvalid < 8 ? cvalid : 8);
+    t2 = keep_bf16(t2, cvalid > 8 ? cvalid - 8 : 0);
     floatx16 d;
 #pragma unroll
     for (int v = 0; v < 16; ++v) d[v] = 0.f;
@@ -551,64 +564,71 @@ __global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void adj_lp_kernel(
     oa = u32x4{pack_bf16(d[0], d[1]), pack_bf16(d[2], d[3]), pack_bf16(d[4], d[5]), pack_bf16(d[6], d[7])};
     ob = u32x4{pack_bf16(d[8], d[9]), pack_bf16(d[10], d[11]), pack_bf16(d[12], d[13]), pack_bf16(d[14], d[15])};
   };
-  auto compute = [&](const AdjStage<ST>& b, int buf) {
-    u32x4 oa[2], ob[2], la[2], lb[2];
-#pragma unroll
-    for (int at = 0; at < 2; ++at) {
-      if (ST == ST_FP8) {
-        const u32x4 w = b.a[at][0];
-        transpose(fp8x8_to_bf16(w.x, w.y), fp8x8_to_bf16(w.z, w.w), cvalid[at], oa[at], ob[at]);
-      } else {
-        transpose(b.a[at][0], b.a[at][1], cvalid[at], oa[at], ob[at]);
-        if (ST == ST_HILO) transpose(b.a[at][2], b.a[at][3], cvalid[at], la[at], lb[at]);
-      }
+  auto tr_half = [&](const unsigned char* as, int h, u32x4& oa, u32x4& ob, u32x4& la, u32x4& lb) {
+    if (ST == ST_FP8) {
+      const u32x4 w = ld16(as + 1024 * h + 16 * lane);
+      transpose(fp8x8_to_bf16(w.x, w.y), fp8x8_to_bf16(w.z, w.w), oa, ob);
+    } else {
+      transpose(ld16(as + 1024 * (HQ * h) + 16 * lane), ld16(as + 1024 * (HQ * h + 1) + 16 * lane), oa, ob);
+      if (ST == ST_HILO)
+        transpose(ld16(as + 1024 * (HQ * h + 2) + 16 * lane), ld16(as + 1024 * (HQ * h + 3) + 16 * lane), la, lb);
     }
+  };
+  auto compute = [&](int slot) {
+    const unsigned char* zs = zring + slot * SX;
+    const unsigned char* as = aring + slot * SA;
+    u32x4 oa[2], ob[2], la[2], lb[2];
+    tr_half(as, 0, oa[0], ob[0], la[0], lb[0]);
+    tr_half(as, 1, oa[1], ob[1], la[1], lb[1]);
 #pragma unroll
-    for (int zt = 0; zt < 2; ++zt) {
-      const u32x4 zah = ld16(&Zs[buf][0][32 * zt + li][8 * g]);
-      const u32x4 zbh = ld16(&Zs[buf][0][32 * zt + li][16 + 8 * g]);
-      const u32x4 zal = ld16(&Zs[buf][1][32 * zt + li][8 * g]);
-      const u32x4 zbl = ld16(&Zs[buf][1][32 * zt + li][16 + 8 * g]);
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int at = 0; at < 2; ++at) {
-        acc[at][zt] = mfma_bf16(oa[at], zah, acc[at][zt]);
-        acc[at][zt] = mfma_bf16(oa[at], zal, acc[at][zt]);
-        acc[at][zt] = mfma_bf16(ob[at], zbh, acc[at][zt]);
-        acc[at][zt] = mfma_bf16(ob[at], zbl, acc[at][zt]);
+      for (int zt = 0; zt < 2; ++zt) {
+        const int col = 32 * zt + li;
+        const u32x4 zah = ld16(zs + swz(col, 4 * h + g));
+        const u32x4 zbh = ld16(zs + swz(col, 4 * h + 2 + g));
+        const u32x4 zal = ld16(zs + 8192 + swz(col, 4 * h + g));
+        const u32x4 zbl = ld16(zs + 8192 + swz(col, 4 * h + 2 + g));
+        acc[zt] = mfma_bf16(oa[h], zah, acc[zt]);
+        acc[zt] = mfma_bf16(ob[h], zbh, acc[zt]);
+        acc[zt] = mfma_bf16(oa[h], zal, acc[zt]);
+        acc[zt] = mfma_bf16(ob[h], zbl, acc[zt]);
         if (ST == ST_HILO) {
-          acc[at][zt] = mfma_bf16(la[at], zah, acc[at][zt]);
-          acc[at][zt] = mfma_bf16(lb[at], zbh, acc[at][zt]);
+          acc[zt] = mfma_bf16(la[h], zah, acc[zt]);
+          acc[zt] = mfma_bf16(lb[h], zbh, acc[zt]);
         }
       }
     }
   };
+  auto stage_sync = [&]() {
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(PQ * (NB - 2), 0));
+    __builtin_amdgcn_s_barrier();
+  };
 
-  // rows past m read row m-1 (finite) against zero Z rows
-  const int64_t nst = (rend - rbeg + LA_RS - 1) / LA_RS;
-  int it = 0;
-  if (nst > 0) {
-    AdjStage<ST> ac, an;
-    ZStage zr;
-    load_z(zr, rbeg);
-    load_a(ac, rbeg);
-    store_z(zr, 0);
-    __syncthreads();
-    for (int64_t st = 0; st < nst; ++st) {
-      const int64_t rn = rbeg + (st + 1 < nst ? st + 1 : st) * LA_RS;
-      load_z(zr, rn);
-      load_a(an, rn);
-      __builtin_amdgcn_sched_barrier(0);
-      compute(ac, (int)(st & 1));
-      store_z(zr, (int)((st + 1) & 1));
-      __syncthreads();
-      ac = an;
-      if (++it == 4) {  // fold every 4 stages (128 rows)
-        it = 0;
-        fold();
-      }
+  if (nfull > 0) {
+#pragma unroll
+    for (int u = 0; u < NB - 1; ++u) issue(u, u);
+  }
+  int64_t t = 0;
+  for (; t + NB <= nfull; t += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      stage_sync();
+      issue(t + u + NB - 1, (u + NB - 1) % NB);
+      compute(u);
+    }
+    fold();
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    if (t + u < nfull) {
+      stage_sync();
+      issue(t + u + NB - 1, (u + NB - 1) % NB);
+      compute(u);
     }
   }
   fold();
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));  // no load in flight at exit
 
   float* __restrict__ Ps = P + (int64_t)sp * split_stride;
 #pragma unroll
@@ -617,20 +637,17 @@ __global__ __launch_bounds__(256, ST == ST_HILO ? 1 : 2) void adj_lp_kernel(
     if (j >= ncols) continue;
     float* __restrict__ prow = Ps + (int64_t)j * ldp;
 #pragma unroll
-    for (int at = 0; at < 2; ++at)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t c = cw + 32 * at + 16 * (q & 1) + 8 * (q >> 1) + 4 * g;
-        const floatx4 o = {acc2[at][zt][4 * q], acc2[at][zt][4 * q + 1], acc2[at][zt][4 * q + 2],
-                           acc2[at][zt][4 * q + 3]};
-        if (c + 3 < n) {
-          *reinterpret_cast<floatx4*>(prow + c) = o;
-        } else {
-          if (c < n) prow[c] = o.x;
-          if (c + 1 < n) prow[c + 1] = o.y;
-          if (c + 2 < n) prow[c + 2] = o.z;
-        }
+    for (int q = 0; q < 4; ++q) {
+      const int64_t c = cw + 16 * (q & 1) + 8 * (q >> 1) + 4 * g;
+      const floatx4 o = {acc2[zt][4 * q], acc2[zt][4 * q + 1], acc2[zt][4 * q + 2], acc2[zt][4 * q + 3]};
+      if (c + 3 < n) {
+        *reinterpret_cast<floatx4*>(prow + c) = o;
+      } else {
+        if (c < n) prow[c] = o.x;
+        if (c + 1 < n) prow[c + 1] = o.y;
+        if (c + 2 < n) prow[c + 2] = o.z;
       }
+    }
   }
 }
 
@@ -651,17 +668,19 @@ hipError_t launch_split_x(const float* Xt, int64_t ldx, int64_t n, int ncols, co
 
 hipError_t launch_split_zt(const float* Z, int64_t ldz, int64_t m, int ncols, uint16_t* Zh, uint16_t* Zl,
                            int64_t ldzs, int cpad, hipStream_t st) {
-  if (ldzs % LA_RS != 0 || ldzs < m || cpad % 64 != 0 || cpad < ncols) return hipErrorInvalidValue;
+  if (ldzs % 32 != 0 || ldzs < m || cpad % 64 != 0 || cpad < ncols) return hipErrorInvalidValue;
   dim3 grid((unsigned)(ldzs / 32), (unsigned)(cpad / 64));
   hipLaunchKernelGGL(split_zt_kernel, grid, dim3(256), 0, st, Z, ldz, m, ncols, Zh, Zl, ldzs);
   return hipGetLastError();
 }
 
 template <int ST>
-static void launch_fwd_lp_t(const FwdArgs& a, dim3 grid, float* out, int64_t ldo, int64_t kchunk, bool direct,
-                            hipStream_t st) {
-  hipLaunchKernelGGL((fwd_lp_kernel<ST>), grid, dim3(256), 0, st, a.A, a.lda, a.m, a.n, a.plane, a.Xh, a.Xl,
-                     a.ldxs, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
+static void launch_fwd_lp_t(const FwdArgs& a, int ns, int ctiles, float* out, int64_t ldo, int64_t kchunk,
+                            bool direct, hipStream_t st) {
+  using C = LpCfg<ST>;
+  dim3 grid((unsigned)((a.m + 32 * C::W - 1) / (32 * C::W)), (unsigned)ns, (unsigned)ctiles);
+  hipLaunchKernelGGL((fwd_lp_kernel<ST>), grid, dim3(64 * C::W), C::LDS, st, a.A, a.lda, a.m, a.n, a.plane, a.Xh,
+                     a.Xl, a.ldxs, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
 }
 
 hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st) {
@@ -675,15 +694,14 @@ hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st) {
                  (int64_t)ns * a.kchunk < a.n || a.split_stride < a.m * a.ldp))
     return hipErrorInvalidValue;
   const int ctiles = (a.ncols + 63) / 64;
-  dim3 grid((unsigned)((a.m + 255) / 256), (unsigned)ns, (unsigned)ctiles);
   const bool direct = ns == 1;
   float* out = direct ? a.Z : a.P;
   const int64_t ldo = direct ? a.ldz : a.ldp;
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
   switch (storage) {
-    case ST_BF16: launch_fwd_lp_t<ST_BF16>(a, grid, out, ldo, kchunk, direct, st); break;
-    case ST_FP8: launch_fwd_lp_t<ST_FP8>(a, grid, out, ldo, kchunk, direct, st); break;
-    case ST_HILO: launch_fwd_lp_t<ST_HILO>(a, grid, out, ldo, kchunk, direct, st); break;
+    case ST_BF16: launch_fwd_lp_t<ST_BF16>(a, ns, ctiles, out, ldo, kchunk, direct, st); break;
+    case ST_FP8: launch_fwd_lp_t<ST_FP8>(a, ns, ctiles, out, ldo, kchunk, direct, st); break;
+    case ST_HILO: launch_fwd_lp_t<ST_HILO>(a, ns, ctiles, out, ldo, kchunk, direct, st); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -696,10 +714,12 @@ hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st) {
 }
 
 template <int ST>
-static void launch_adj_lp_t(const AdjArgs& a, int jtiles, int ctiles, hipStream_t st) {
+static void launch_adj_lp_t(const AdjArgs& a, int jtiles, hipStream_t st) {
+  using C = LpCfg<ST>;
+  const int ctiles = (int)((a.n + 32 * C::W - 1) / (32 * C::W));
   const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
-  hipLaunchKernelGGL((adj_lp_kernel<ST>), dim3((unsigned)total), dim3(256), 0, st, a.A, a.lda, a.m, a.n, a.plane,
-                     a.Zh, a.Zl, a.ldzs, a.ncols, a.rows_per_split, jtiles, ctiles, a.nsplit, a.P, a.ldp,
+  hipLaunchKernelGGL((adj_lp_kernel<ST>), dim3((unsigned)total), dim3(64 * C::W), C::LDS, st, a.A, a.lda, a.m, a.n,
+                     a.plane, a.Zh, a.Zl, a.ldzs, a.ncols, a.rows_per_split, jtiles, ctiles, a.nsplit, a.P, a.ldp,
                      a.split_stride);
 }
 
@@ -712,12 +732,11 @@ hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st) {
     return hipErrorInvalidValue;
   if (storage == ST_HILO && a.plane < a.m * a.lda) return hipErrorInvalidValue;
   const int jtiles = (a.ncols + 63) / 64;
-  const int ctiles = (int)((a.n + 255) / 256);
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
   switch (storage) {
-    case ST_BF16: launch_adj_lp_t<ST_BF16>(a, jtiles, ctiles, st); break;
-    case ST_FP8: launch_adj_lp_t<ST_FP8>(a, jtiles, ctiles, st); break;
-    case ST_HILO: launch_adj_lp_t<ST_HILO>(a, jtiles, ctiles, st); break;
+    case ST_BF16: launch_adj_lp_t<ST_BF16>(a, jtiles, st); break;
+    case ST_FP8: launch_adj_lp_t<ST_FP8>(a, jtiles, st); break;
+    case ST_HILO: launch_adj_lp_t<ST_HILO>(a, jtiles, st); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -725,9 +744,13 @@ hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st) {
   return e;
 }
 
-// K split for the low-precision forward product (256-row blocks, 64-K stages)
-void fwd_split_lp(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk) {
-  const int64_t rt = (m + 255) / 256;
+static int lp_waves(int storage) { return storage == ST_HILO ? LpCfg<ST_HILO>::W : LpCfg<ST_BF16>::W; }
+
+// K split for the low-precision forward product (32 W-row workgroups, 64-K stages;
+// slots = workgroups resident at once, one per CU)
+void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk) {
+  const int64_t rows = 32 * lp_waves(storage);
+  const int64_t rt = (m + rows - 1) / rows;
   int best = 1;
   double best_eff = 0.0;
   for (int s = 1; s <= 8; ++s) {
@@ -747,9 +770,11 @@ void fwd_split_lp(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kch
   *kchunk = chunk;
 }
 
-// Row split of the low-precision adjoint (rows per split a multiple of 32)
-void adj_split_lp(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split) {
-  const int64_t per = (int64_t)((ncols + 63) / 64) * ((n + 255) / 256);
+// Row split of the low-precision adjoint (rows per split a multiple of 64)
+void adj_split_lp(int storage, int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit,
+                  int64_t* rows_per_split) {
+  const int64_t cols = 32 * lp_waves(storage);
+  const int64_t per = (int64_t)((ncols + 63) / 64) * ((n + cols - 1) / cols);
   int64_t lo = (2 * slots + per - 1) / per;
   int64_t hi = lo * 4 + 8;
   const int64_t maxs = m / 128 > 0 ? m / 128 : 1;

@@ -66,7 +66,7 @@ struct rpca_plan_s {
   // low-precision storage: bfloat16 hi/lo planes of the float operand
   int64_t ldxs = 0;  // X planes: cpad_x rows of ldxs (n rounded up to 64)
   int cpad_x = 0;
-  int64_t ldzs = 0;  // transposed Z planes: cpad_z rows of ldzs (m rounded up to 32)
+  int64_t ldzs = 0;  // transposed Z planes: cpad_z rows of ldzs (m rounded up to 64)
   int cpad_z = 0;
 
   std::vector<void*> allocs;
@@ -237,13 +237,13 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   plan->storage = desc->storage;
   const bool lowp = desc->storage != RPCA_A_F32;
   if (lowp) {
-    const int64_t lp_slots = desc->storage == RPCA_A_BF16_HILO ? slots / 2 : slots;
-    adj_split_lp(m, n, l, lp_slots, &plan->ns_y, &plan->rps_y);
-    adj_split_lp(m, n, L, lp_slots, &plan->ns_t, &plan->rps_t);
-    fwd_split_lp(m, n, lp_slots, &plan->fwd_ks, &plan->fwd_kchunk);
+    const int64_t lp_slots = prop.multiProcessorCount;  // one low-precision workgroup per CU (LDS)
+    adj_split_lp(desc->storage, m, n, l, lp_slots, &plan->ns_y, &plan->rps_y);
+    adj_split_lp(desc->storage, m, n, L, lp_slots, &plan->ns_t, &plan->rps_t);
+    fwd_split_lp(desc->storage, m, n, lp_slots, &plan->fwd_ks, &plan->fwd_kchunk);
     plan->ldxs = round_up(n, 64);
     plan->cpad_x = (int)round_up(l, 64);
-    plan->ldzs = round_up(m, 32);
+    plan->ldzs = round_up(m, 64);
     plan->cpad_z = (int)round_up(L, 64);
   } else {
     adj_split(m, n, l, slots, &plan->ns_y, &plan->rps_y);
