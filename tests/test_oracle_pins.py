@@ -358,3 +358,81 @@ def test_e4m3_reference_codes():
     err = np.abs(back[inrange] - v[inrange])
     nearest = np.min(np.abs(pos[None, :] - np.abs(v[inrange])[:, None]), axis=1)
     assert np.all(err <= nearest + 1e-12)
+
+
+# ---------------------------------------------------------------- backward oracle (derivative of Steps 1-6)
+def _bw_problem(seed, m, n, decay, rank=None):
+    rng = np.random.default_rng(seed)
+    U0 = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    V0 = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = decay ** np.arange(n)
+    if rank is not None:
+        s[rank:] = 0.0
+    return (U0 * s) @ V0.T
+
+
+@pytest.mark.parametrize("center,i", [(False, 1), (True, 1), (False, 0), (True, 2)])
+def test_backward_oracle_matches_central_differences(center, i):
+    """Directional derivatives of the oracle gradient equal central differences of its forward."""
+    from oracle import rpca_backward as B
+    m, n, k, l = 40, 25, 3, 4
+    A = _bw_problem(3, m, n, 0.8) + (0.3 if center else 0.0)
+    rng = np.random.default_rng(4)
+    G = rng.standard_normal((n, l))
+    gS, gU, gV = rng.standard_normal(k), rng.standard_normal((m, k)), rng.standard_normal((n, k))
+    dA = B.gradient(A, k, l, i, G, center, gS, gU, gV)
+    h = 1e-5
+    for t in range(5):
+        E = rng.standard_normal((m, n))
+        E /= np.linalg.norm(E)
+        fd = (B.loss(A + h * E, k, l, i, G, center, gS, gU, gV) -
+              B.loss(A - h * E, k, l, i, G, center, gS, gU, gV)) / (2 * h)
+        an = float(np.sum(dA * E))
+        assert abs(fd - an) <= 1e-7 * max(1.0, np.linalg.norm(dA)), (t, fd, an)
+
+
+def test_backward_oracle_singular_value_closed_form():
+    """When range(A) is captured exactly, d sigma_j = u_j v_j^T (first-order perturbation of a
+    simple singular value); with centring, of the centred matrix, projected by I - 11^T/m."""
+    from oracle import rpca_backward as B
+    m, n, k, l, i = 60, 30, 4, 6, 1
+    A = _bw_problem(5, m, n, 0.7, rank=5)           # rank 5 <= L = 12: exact range
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((n, l))
+    w = rng.standard_normal(k)
+    dA = B.gradient(A, k, l, i, G, False, gS=w)
+    Us, ss, Vts = np.linalg.svd(A)
+    ref = (Us[:, :k] * w) @ Vts[:k]
+    assert np.linalg.norm(dA - ref) <= 1e-9 * np.linalg.norm(ref)
+    # centred: rank of A - 1 mu^T is still <= 6 <= L
+    Ac0 = A + np.arange(n)[None, :] * 0.1
+    dA = B.gradient(Ac0, k, l, i, G, True, gS=w)
+    Acc = Ac0 - Ac0.mean(axis=0)
+    Us, ss, Vts = np.linalg.svd(Acc)
+    ref = (Us[:, :k] * w) @ Vts[:k]
+    ref = ref - ref.mean(axis=0)[None, :]
+    assert np.linalg.norm(dA - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_backward_oracle_converges_to_full_svd_gradient():
+    """When the top-k subspace is captured to roundoff and H stays well conditioned (kappa(H) enters
+    through R^-T in the QR adjoint), the gradient equals that of the truncated SVD itself (the
+    textbook SVD adjoint, via autograd of a full SVD)."""
+    import torch
+    from oracle import rpca_backward as B
+    m, n, k, l, i = 80, 40, 3, 8, 2
+    A = _bw_problem(8, m, n, 0.7)
+    rng = np.random.default_rng(9)
+    G = rng.standard_normal((n, l))
+    gS, gU, gV = rng.standard_normal(k), rng.standard_normal((m, k)), rng.standard_normal((n, k))
+    dA = B.gradient(A, k, l, i, G, False, gS, gU, gV)
+    At = torch.tensor(A, requires_grad=True)
+    Uf, Sf, Vhf = torch.linalg.svd(At, full_matrices=False)
+    U, S, V = Uf[:, :k], Sf[:k], Vhf[:k].T
+    with torch.no_grad():
+        idx = torch.argmax(V.abs(), dim=0)
+        sg = torch.sign(V[idx, torch.arange(k)])
+    loss = (S * torch.tensor(gS)).sum() + (U * sg * torch.tensor(gU)).sum() + (V * sg * torch.tensor(gV)).sum()
+    loss.backward()
+    ref = At.grad.numpy()
+    assert np.linalg.norm(dA - ref) <= 2e-5 * np.linalg.norm(ref)
