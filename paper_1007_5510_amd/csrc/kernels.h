@@ -131,7 +131,7 @@ hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st);
 // column scale, FP64 and/or FP32 outputs
 hipError_t launch_gemm64(bool a_is_f64, const void* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
                          int N, int K, bool b_upper, const double* colscale, double* C, int64_t ldc, float* C32,
-                         int64_t ldc32, hipStream_t st);
+                         int64_t ldc32, hipStream_t st, const double* Cin = nullptr, int64_t ldcin = 0);
 // C (L x L) = A (L x L upper) * B (L x L upper)
 hipError_t launch_trmm_upper(const double* A, const double* B, int L, double* C, hipStream_t st);
 
@@ -146,5 +146,30 @@ hipError_t launch_normalize_sign(double* V, int64_t rows, int k, int64_t ldv, do
 // out32[r][j] = (float) (X[r][j] * colscale[j])
 hipError_t launch_to_f32(const double* X, int64_t rows, int cols, int64_t ldx, const double* colscale,
                          float* out, int64_t ldo, hipStream_t st);
+
+// ---------------------------------------------------------------- backward (backward.hip)
+// out (na x nb) = (X^T Y) * colscale (columns), X rows x na, Y rows x nb, split over rows
+hipError_t launch_xty(bool x64, const void* X, int64_t ldx, int na, bool y64, const void* Y, int64_t ldy, int nb,
+                      int64_t rows, int64_t rows_per_split, int nsplit, const double* colscale, double* part,
+                      double* out, hipStream_t st);
+hipError_t launch_svdadj_prep(const double* W, const double* sig, const double* sgn, int L, int k, double* WT,
+                              double* Wsc, double* Ck, double* Bp, hipStream_t st);
+hipError_t launch_svdadj_mid(const double* XV, const double* YW, const double* sig, const float* gS, int L, int k,
+                             double* N, hipStream_t st);
+hipError_t launch_copyltu_neg(const double* M2, int L, double* S, hipStream_t st);
+hipError_t launch_transpose_sq(const double* in, int L, bool upper_only, double* out, hipStream_t st);
+hipError_t launch_transpose_out(const double* X, int64_t ldx, int64_t rows, int cols, float* out32, double* out64,
+                                int64_t ldo, hipStream_t st);
+hipError_t launch_widen(const float* X, int64_t ldx, int nrows, int64_t ncols, double* Y, int64_t ldy,
+                        hipStream_t st);
+hipError_t launch_add_f32(const float* Z, int64_t ldz, int64_t rows, int cols, double* C, int64_t ldc,
+                          bool accumulate, hipStream_t st);
+hipError_t launch_combine(const double* Hb, int64_t ldh, const float* Zf, int64_t ldz, int64_t rows, int cols,
+                          const double* alpha, double* out64, int64_t ld64, float* out32, int64_t ld32,
+                          hipStream_t st);
+hipError_t launch_copy_cols(bool x64, const void* X, int64_t ldx, int64_t rows, int cols, double* out, int64_t ldo,
+                            hipStream_t st);
+hipError_t launch_center_f64(double* X, int64_t ldx, int64_t rows, int cols, int64_t rows_per_split, int nsplit,
+                             double* part, hipStream_t st);
 
 }  // namespace rpca

@@ -112,6 +112,25 @@ struct rpca_plan_s {
 
   bool have_state = false;
   bool Qfinal_is_Q1 = false;
+  const void* A_last = nullptr;  // matrix of the last factorisation (for the backward passes)
+  int64_t lda_last = 0;
+
+  // reverse-mode workspace, allocated by the first rpca_backward
+  struct Backward {
+    bool ready = false;
+    int R = 0;                                       // rank of dA = P Y^T: (3i + 2) l
+    double *Qbar = nullptr, *Hbar = nullptr;         // m x L
+    float *Zf = nullptr, *Zin = nullptr;             // m x L, m x l
+    double *Pm = nullptr, *Yt = nullptr;             // m x R, R x ldx
+    float* Xbar = nullptr;                           // i blocks of l x ldx (transposed)
+    double* Tbar = nullptr;                          // n x L
+    float* TbarT = nullptr;                          // L x ldx
+    double *NtV = nullptr, *Wbar = nullptr, *XV = nullptr, *YW = nullptr;  // L x k
+    double *WT = nullptr, *Wsc = nullptr, *Nm = nullptr, *Tmp = nullptr, *Bmat = nullptr;  // L x L
+    double *M2 = nullptr, *Smat = nullptr, *Rf = nullptr, *Rt = nullptr, *RfInv = nullptr, *RinvT = nullptr;
+    double *Ck = nullptr, *Bp = nullptr;             // k x L
+    double* ppart = nullptr;                         // column-sum partials of P
+  } bw;
   rpca_stats stats{};
   std::vector<EventPair> ev_fwd, ev_adj;
   int nev_fwd = 0, nev_adj = 0;
@@ -376,6 +395,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   sx = rpca_stats{};
   plan->have_state = false;
   plan->nev_fwd = plan->nev_adj = 0;
+  plan->A_last = A;
+  plan->lda_last = lda;
   const bool center = plan->d.center != 0;
   const bool rescale = !(plan->d.flags & RPCA_FLAG_NO_RESCALE);
   const bool vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0);
@@ -671,11 +692,210 @@ extern "C" rpca_status rpca_get_state(rpca_plan_t plan, int32_t which, void* dst
   return RPCA_OK;
 }
 
+namespace {
+
+rpca_status backward_alloc(rpca_plan_s* plan) {
+  auto& b = plan->bw;
+  if (b.ready) return RPCA_OK;
+  const int64_t m = plan->m, ldx = plan->ldx;
+  const int k = plan->k, l = plan->l, i = plan->i, L = plan->L;
+  b.R = (3 * i + 2) * l;
+  const int64_t LL = (int64_t)L * L;
+  hipError_t e = hipSuccess;
+#define BALLOC(ptr, cnt)                                                   \
+  do {                                                                     \
+    e = plan->alloc(&b.ptr, (cnt));                                        \
+    if (e != hipSuccess)                                                   \
+      return e == hipErrorOutOfMemory ? RPCA_ERR_OUT_OF_MEMORY : RPCA_ERR_HIP; \
+  } while (0)
+  BALLOC(Qbar, m * L);
+  BALLOC(Hbar, m * L);
+  BALLOC(Zf, m * L);
+  BALLOC(Zin, m * l);
+  BALLOC(Pm, m * b.R);
+  BALLOC(Yt, (int64_t)b.R * ldx);
+  BALLOC(Xbar, (int64_t)(i > 0 ? i : 1) * l * ldx);
+  BALLOC(Tbar, plan->n * L);
+  BALLOC(TbarT, (int64_t)L * ldx);
+  BALLOC(NtV, (int64_t)L * k);
+  BALLOC(Wbar, (int64_t)L * k);
+  BALLOC(XV, (int64_t)L * k);
+  BALLOC(YW, (int64_t)L * k);
+  BALLOC(WT, LL);
+  BALLOC(Wsc, LL);
+  BALLOC(Nm, LL);
+  BALLOC(Tmp, LL);
+  BALLOC(Bmat, LL);
+  BALLOC(M2, LL);
+  BALLOC(Smat, LL);
+  BALLOC(Rf, LL);
+  BALLOC(Rt, LL);
+  BALLOC(RfInv, LL);
+  BALLOC(RinvT, LL);
+  BALLOC(Ck, (int64_t)k * L);
+  BALLOC(Bp, (int64_t)k * L);
+  BALLOC(ppart, (int64_t)plan->ns_cs * b.R);
+#undef BALLOC
+  b.ready = true;
+  return RPCA_OK;
+}
+
+}  // namespace
+
+// Reverse sweep of Steps 1-6 (reading: exact derivative of the computed
+// function with G fixed).  Small steps in float64, passes over A on the
+// float32 panel kernels, dA = P Y^T assembled in float64 with
+//   P = [Q | a_0 Z_0 .. a_i Z_i | H^(0) .. H^(i-1)],  Y = [T_bar | X_0 .. X_i | X_bar_1 .. X_bar_i]
+// where Z_i = H_bar_i, Z_j = H_bar_j + A~ X_bar_{j+1}, X_bar_j = a_j A~^T Z_j, and
+// a_j are the positive block scales of the forward (constants: Q does not depend on them).
 extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, int64_t ldgu,
                                      const float* gV, int64_t ldgv, float* dA, int64_t ldda) {
-  (void)gS; (void)gU; (void)ldgu; (void)gV; (void)ldgv; (void)dA; (void)ldda;
-  if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
-  return RPCA_ERR_UNSUPPORTED;
+  if (plan == nullptr || dA == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (!plan->have_state || !(plan->d.flags & RPCA_FLAG_KEEP_STATE) || plan->A_last == nullptr)
+    return RPCA_ERR_NO_STATE;
+  if (plan->storage != RPCA_A_F32) return RPCA_ERR_UNSUPPORTED;
+  const int64_t m = plan->m, n = plan->n, ldx = plan->ldx;
+  const int k = plan->k, l = plan->l, i = plan->i, L = plan->L;
+  if (ldda < n || (gU != nullptr && ldgu < k) || (gV != nullptr && ldgv < k)) return RPCA_ERR_INVALID_ARG;
+  DevGuard g(plan->device);
+  rpca_status as = backward_alloc(plan);
+  if (as != RPCA_OK) return as;
+  auto& b = plan->bw;
+  hipStream_t st = plan->stream;
+  const int R = b.R;
+  const bool center = plan->d.center != 0;
+  const double* dres = center ? plan->dres : nullptr;
+  const float* A = static_cast<const float*>(plan->A_last);
+  const int64_t lda = plan->lda_last;
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0);
+  const double* Q = plan->Qfinal_is_Q1 ? plan->Q1 : plan->Q;
+  const int64_t LL = (int64_t)L * L;
+
+  // ---- small SVD adjoint: T_bar = T B + V_bar S~^-1 W^T
+  if (gU != nullptr)
+    RPCA_TRY(launch_xty(true, Q, L, L, false, gU, ldgu, k, m, plan->rps_g, plan->ns_g, plan->sgn, plan->gp, b.Wbar,
+                        st));
+  else
+    RPCA_TRY(hipMemsetAsync(b.Wbar, 0, sizeof(double) * (size_t)L * k, st));
+  if (gV != nullptr)
+    RPCA_TRY(launch_xty(true, plan->T, L, L, false, gV, ldgv, k, n, plan->rps_gt, plan->ns_gt, plan->sgn, plan->gp,
+                        b.NtV, st));
+  else
+    RPCA_TRY(hipMemsetAsync(b.NtV, 0, sizeof(double) * (size_t)L * k, st));
+  RPCA_TRY(launch_svdadj_prep(plan->Wsorted, plan->sigL, plan->sgn, L, k, b.WT, b.Wsc, b.Ck, b.Bp, st));
+  RPCA_TRY(launch_gemm64(true, b.WT, L, b.NtV, k, L, k, L, false, nullptr, b.XV, k, nullptr, 0, st));
+  RPCA_TRY(launch_gemm64(true, b.WT, L, b.Wbar, k, L, k, L, false, nullptr, b.YW, k, nullptr, 0, st));
+  RPCA_TRY(launch_svdadj_mid(b.XV, b.YW, plan->sigL, gS, L, k, b.Nm, st));
+  RPCA_TRY(launch_gemm64(true, b.Wsc, L, b.Nm, L, L, L, L, false, nullptr, b.Tmp, L, nullptr, 0, st));
+  RPCA_TRY(launch_gemm64(true, b.Tmp, L, b.WT, L, L, L, L, false, nullptr, b.Bmat, L, nullptr, 0, st));
+  RPCA_TRY(launch_gemm64(true, plan->T, L, b.Bmat, L, n, L, L, false, nullptr, b.Tbar, L, nullptr, 0, st));
+  if (gV != nullptr)
+    RPCA_TRY(launch_gemm64(false, gV, ldgv, b.Ck, L, n, L, k, false, nullptr, b.Tbar, L, nullptr, 0, st, b.Tbar, L));
+  // T_bar^T: float32 for the panel product, float64 into the first L rows of Y^T
+  RPCA_TRY(launch_transpose_out(b.Tbar, L, n, L, b.TbarT, b.Yt, ldx, st));
+
+  // ---- T = A~^T Q:  Q_bar = G_U' W_k^T + A~ T_bar
+  {
+    if (center) RPCA_TRY(launch_dot_rows(dres, b.TbarT, ldx, n, L, plan->corr, st));
+    FwdArgs fa;
+    fa.A = A;
+    fa.lda = lda;
+    fa.m = m;
+    fa.n = n;
+    fa.shift = plan->shift;
+    fa.Xt = b.TbarT;
+    fa.ldx = ldx;
+    fa.ncols = L;
+    fa.corr = center ? plan->corr : nullptr;
+    fa.Z = b.Zf;
+    fa.ldz = L;
+    fa.vec = vec;
+    RPCA_TRY(launch_fwd_f32(fa, st));
+  }
+  if (gU != nullptr) {
+    RPCA_TRY(launch_gemm64(false, gU, ldgu, b.Bp, L, m, L, k, false, nullptr, b.Qbar, L, nullptr, 0, st));
+    RPCA_TRY(launch_add_f32(b.Zf, L, m, L, b.Qbar, L, true, st));
+  } else {
+    RPCA_TRY(launch_add_f32(b.Zf, L, m, L, b.Qbar, L, false, st));
+  }
+
+  // ---- QR adjoint: H_bar = (Q_bar + Q copyltu(-Q_bar^T Q)) R^-T, R = R2 R1 (R3 R2 R1 after the fallback)
+  RPCA_TRY(launch_xty(true, b.Qbar, L, L, true, Q, L, L, m, plan->rps_g, plan->ns_g, nullptr, plan->gp, b.M2, st));
+  RPCA_TRY(launch_copyltu_neg(b.M2, L, b.Smat, st));
+  RPCA_TRY(launch_gemm64(true, Q, L, b.Smat, L, m, L, L, false, nullptr, b.Qbar, L, nullptr, 0, st, b.Qbar, L));
+  RPCA_TRY(launch_trmm_upper(plan->R2, plan->R1, L, b.Rf, st));
+  if (plan->stats.qr_fallback) {
+    RPCA_TRY(launch_trmm_upper(plan->R3, b.Rf, L, b.Rt, st));
+    RPCA_TRY(hipMemcpyAsync(b.Rf, b.Rt, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+  }
+  RPCA_TRY(launch_triinv(b.Rf, L, b.RfInv, st));
+  RPCA_TRY(launch_transpose_sq(b.RfInv, L, true, b.RinvT, st));
+  RPCA_TRY(launch_gemm64(true, b.Qbar, L, b.RinvT, L, m, L, L, false, nullptr, b.Hbar, L, nullptr, 0, st));
+
+  // ---- reverse power sweep
+  const int64_t ldp = R;
+  RPCA_TRY(launch_combine(b.Hbar + (int64_t)i * l, L, nullptr, 0, m, l, plan->alpha + i, b.Pm + L + (int64_t)i * l,
+                          ldp, b.Zin, l, st));
+  for (int j = i; j >= 1; --j) {
+    // X_bar_j = A~^T (a_j Z_j)
+    if (center) {
+      RPCA_TRY(launch_colsum(ST_F32, b.Zin, l, m, l, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, l, 1.0, plan->zsum, nullptr, nullptr, st));
+    }
+    AdjArgs aa;
+    aa.A = A;
+    aa.lda = lda;
+    aa.m = m;
+    aa.n = n;
+    aa.shift = plan->shift;
+    aa.Z = b.Zin;
+    aa.ldz = l;
+    aa.ncols = l;
+    aa.rows_per_split = plan->rps_y;
+    aa.nsplit = plan->ns_y;
+    aa.P = plan->P;
+    aa.ldp = plan->ldp;
+    aa.split_stride = (int64_t)l * plan->ldp;
+    aa.vec = vec;
+    RPCA_TRY(launch_adj_f32(aa, st));
+    float* Xb = b.Xbar + (int64_t)(j - 1) * l * ldx;
+    int npart = 0;
+    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, nullptr, dres,
+                             center ? plan->zsum : nullptr, Xb, ldx, plan->sqp, &npart, st));
+    // Z_{j-1} = H_bar_{j-1} + A~ X_bar_j
+    if (center) RPCA_TRY(launch_dot_rows(dres, Xb, ldx, n, l, plan->corr, st));
+    FwdArgs fa;
+    fa.A = A;
+    fa.lda = lda;
+    fa.m = m;
+    fa.n = n;
+    fa.shift = plan->shift;
+    fa.Xt = Xb;
+    fa.ldx = ldx;
+    fa.ncols = l;
+    fa.corr = center ? plan->corr : nullptr;
+    fa.Z = b.Zf;
+    fa.ldz = l;
+    fa.vec = vec;
+    fa.ksplit = plan->fwd_ks;
+    fa.kchunk = plan->fwd_kchunk;
+    fa.P = plan->Pf;
+    fa.ldp = plan->ldpf;
+    fa.split_stride = m * plan->ldpf;
+    RPCA_TRY(launch_fwd_f32(fa, st));
+    RPCA_TRY(launch_combine(b.Hbar + (int64_t)(j - 1) * l, L, b.Zf, l, m, l, plan->alpha + (j - 1),
+                            b.Pm + L + (int64_t)(j - 1) * l, ldp, b.Zin, l, st));
+  }
+
+  // ---- factors of dA and the dense product
+  RPCA_TRY(launch_copy_cols(true, Q, L, m, L, b.Pm, ldp, st));
+  if (i > 0) RPCA_TRY(launch_copy_cols(false, plan->H, L, m, i * l, b.Pm + 2 * L, ldp, st));
+  RPCA_TRY(launch_widen(plan->X, ldx, L, n, b.Yt + (int64_t)L * ldx, ldx, st));
+  if (i > 0) RPCA_TRY(launch_widen(b.Xbar, ldx, i * l, n, b.Yt + (int64_t)2 * L * ldx, ldx, st));
+  if (center) RPCA_TRY(launch_center_f64(b.Pm, ldp, m, R, plan->rps_cs, plan->ns_cs, b.ppart, st));
+  RPCA_TRY(launch_gemm64(true, b.Pm, ldp, b.Yt, ldx, m, (int)n, R, false, nullptr, nullptr, 0, dA, ldda, st));
+  RPCA_TRY(hipStreamSynchronize(st));
+  return RPCA_OK;
 }
 
 extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,

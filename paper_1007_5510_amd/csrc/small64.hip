@@ -245,13 +245,14 @@ hipError_t launch_trmm_upper(const double* A, const double* B, int L, double* C,
 }
 
 // ---------------------------------------------------------------- FP64 GEMM
-// C[M x N] = A[M x K] B[K x N] (* colscale); 64 x 64 tiles, 4 x 4 per thread.
+// C[M x N] = A[M x K] B[K x N] (* colscale) (+ Cin); 64 x 64 tiles, 4 x 4 per thread.
+// Cin may alias C (each element is read and written by the same thread).
 template <typename TA>
 __global__ __launch_bounds__(256) void gemm64_kernel(const TA* __restrict__ A, int64_t lda,
                                                      const double* __restrict__ B, int64_t ldb, int64_t M, int N,
                                                      int K, int b_upper, const double* __restrict__ colscale,
-                                                     double* __restrict__ C, int64_t ldc, float* __restrict__ C32,
-                                                     int64_t ldc32) {
+                                                     const double* Cin, int64_t ldcin, double* C, int64_t ldc,
+                                                     float* __restrict__ C32, int64_t ldc32) {
   __shared__ double As[16][65];
   __shared__ double Bs[16][65];
   const int64_t R0 = (int64_t)blockIdx.x * 64;
@@ -297,7 +298,8 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const TA* __restrict__ A, i
     for (int a = 0; a < 4; ++a) {
       const int64_t r = R0 + ty + 16 * a;
       if (r >= M) continue;
-      const double v = acc[a][b] * sc;
+      double v = acc[a][b] * sc;
+      if (Cin != nullptr) v += Cin[r * ldcin + c];
       if (C != nullptr) C[r * ldc + c] = v;
       if (C32 != nullptr) C32[r * ldc32 + c] = (float)v;
     }
@@ -306,14 +308,15 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const TA* __restrict__ A, i
 
 hipError_t launch_gemm64(bool a_is_f64, const void* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int N,
                          int K, bool b_upper, const double* colscale, double* C, int64_t ldc, float* C32,
-                         int64_t ldc32, hipStream_t st) {
+                         int64_t ldc32, hipStream_t st, const double* Cin, int64_t ldcin) {
+  if (M <= 0 || N <= 0) return hipSuccess;
   dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
   if (a_is_f64)
     hipLaunchKernelGGL(gemm64_kernel<double>, grid, dim3(256), 0, st, (const double*)A, lda, B, ldb, M, N, K,
-                       b_upper ? 1 : 0, colscale, C, ldc, C32, ldc32);
+                       b_upper ? 1 : 0, colscale, Cin, ldcin, C, ldc, C32, ldc32);
   else
     hipLaunchKernelGGL(gemm64_kernel<float>, grid, dim3(256), 0, st, (const float*)A, lda, B, ldb, M, N, K,
-                       b_upper ? 1 : 0, colscale, C, ldc, C32, ldc32);
+                       b_upper ? 1 : 0, colscale, Cin, ldcin, C, ldc, C32, ldc32);
   return hipGetLastError();
 }
 

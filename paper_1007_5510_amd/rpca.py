@@ -138,6 +138,19 @@ class Plan:
         check(rc, "rpca_factor")
         return U, S, V
 
+    def backward(self, gS=None, gU=None, gV=None, out=None):
+        """dL/dA for L = <gS, S> + <gU, U> + <gV, V> after a factor() with FLAG_KEEP_STATE (G held fixed)."""
+        m, n, k = self.m, self.n, self.k
+        for name, t, shape in (("gS", gS, (k,)), ("gU", gU, (m, k)), ("gV", gV, (n, k))):
+            if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != shape or t.stride(-1) != 1
+                                  or t.device != self.device):
+                raise ValueError(f"{name} must be a float32 {shape} tensor on the plan's device")
+        dA = out if out is not None else torch.empty((m, n), dtype=torch.float32, device=self.device)
+        check(self.lib.rpca_backward(self.handle, _ptr(gS), _ptr(gU), gU.stride(0) if gU is not None else 0,
+                                     _ptr(gV), gV.stride(0) if gV is not None else 0, _ptr(dA), dA.stride(0)),
+              "rpca_backward")
+        return dA
+
     def state(self, which: str):
         m, n, L = self.m, self.n, self.L
         shapes = {"H": ((m, L), torch.float32), "HSCALE": ((self.i + 1,), torch.float64),
@@ -160,3 +173,29 @@ def factor(A, k, l, i, *, center=False, G=None, seed=0, flags=0):
     m, n = A.shape
     with Plan(m, n, k, l, i, center=center, seed=seed, flags=flags, device=A.device) as p:
         return p.factor(A, G=G)
+
+
+class _RPCAFunction(torch.autograd.Function):
+    """(U, S, V) = rpca(A) with the library's reverse sweep as the backward (G fixed)."""
+
+    @staticmethod
+    def forward(ctx, A, plan, G):
+        U, S, V = plan.factor(A, G=G)
+        ctx.plan = plan
+        return U, S, V
+
+    @staticmethod
+    def backward(ctx, gU, gS, gV):
+        c = lambda t: None if t is None else t.contiguous()
+        dA = ctx.plan.backward(gS=c(gS), gU=c(gU), gV=c(gV))
+        return dA, None, None
+
+
+def rpca_autograd(A, k, l, i, *, center=False, G=None, seed=0):
+    """Differentiable randomized PCA of a float32 device matrix: returns (U, S, V) with autograd support.
+
+    The plan (holding the forward state the backward needs) lives as long as the returned tensors' graph.
+    """
+    m, n = A.shape
+    plan = Plan(m, n, k, l, i, center=center, seed=seed, flags=_lib.FLAG_KEEP_STATE, device=A.device)
+    return _RPCAFunction.apply(A, plan, G)
