@@ -146,7 +146,8 @@ hipError_t launch_dot_rows(const double* d, const float* Xt, int64_t ldx, int64_
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void reduce_y_kernel(const float* __restrict__ P, int nsplit,
+template <typename TP>
+__global__ __launch_bounds__(256) void reduce_y_kernel(const TP* __restrict__ P, int nsplit,
                                                        int64_t split_stride, int64_t ldp, int64_t n,
                                                        const float* __restrict__ cs, const double* __restrict__ d,
                                                        const double* __restrict__ zsum, float* __restrict__ Xt,
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void reduce_y_kernel(const float* __restrict__
   double sq = 0.0;
   if (c < n) {
     double v = 0.0;
-    const float* p = P + (int64_t)j * ldp + c;
+    const TP* p = P + (int64_t)j * ldp + c;
     for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
     if (cs != nullptr) v *= (double)cs[c];
     if (d != nullptr) v -= d[c] * zsum[j];
@@ -174,7 +175,16 @@ hipError_t launch_reduce_y(const float* P, int nsplit, int64_t split_stride, int
                            double* sq_part, int* n_sq_part, hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
   *n_sq_part = (int)(grid.x * grid.y);
-  hipLaunchKernelGGL(reduce_y_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, n, col_scale, d, zsum,
+  hipLaunchKernelGGL(reduce_y_kernel<float>, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, n, col_scale, d,
+                     zsum, Xt, ldx, sq_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_y64(const double* P, int64_t ldp, int ncols, int64_t n, const double* d, const double* zsum,
+                             float* Xt, int64_t ldx, double* sq_part, int* n_sq_part, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+  *n_sq_part = (int)(grid.x * grid.y);
+  hipLaunchKernelGGL(reduce_y_kernel<double>, grid, dim3(256), 0, st, P, 1, (int64_t)0, ldp, n, nullptr, d, zsum,
                      Xt, ldx, sq_part);
   return hipGetLastError();
 }
@@ -203,7 +213,8 @@ hipError_t launch_finish_scale(const double* sq_part, int n_part, bool rescale, 
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void reduce_t_kernel(const float* __restrict__ P, int nsplit,
+template <typename TP>
+__global__ __launch_bounds__(256) void reduce_t_kernel(const TP* __restrict__ P, int nsplit,
                                                        int64_t split_stride, int64_t ldp, int ncols, int64_t n,
                                                        const float* __restrict__ cs, const double* __restrict__ d,
                                                        const double* __restrict__ qsum, double* __restrict__ T,
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const float* __restrict__
   const int j = blockIdx.y;
   if (c >= n) return;
   double v = 0.0;
-  const float* p = P + (int64_t)j * ldp + c;
+  const TP* p = P + (int64_t)j * ldp + c;
   for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
   if (cs != nullptr) v *= (double)cs[c];
   if (d != nullptr) v -= d[c] * qsum[j];
@@ -223,8 +234,42 @@ hipError_t launch_reduce_t(const float* P, int nsplit, int64_t split_stride, int
                            const float* col_scale, const double* d, const double* qsum, double* T, int64_t ldt,
                            hipStream_t st) {
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
-  hipLaunchKernelGGL(reduce_t_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, ncols, n, col_scale, d,
+  hipLaunchKernelGGL(reduce_t_kernel<float>, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, ncols, n,
+                     col_scale, d, qsum, T, ldt);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_t64(const double* P, int64_t ldp, int ncols, int64_t n, const double* d, const double* qsum,
+                             double* T, int64_t ldt, hipStream_t st) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
+  hipLaunchKernelGGL(reduce_t_kernel<double>, grid, dim3(256), 0, st, P, 1, (int64_t)0, ldp, ncols, n, nullptr, d,
                      qsum, T, ldt);
+  return hipGetLastError();
+}
+
+// acc[r][c] += sum_s part[s][r][c] (float or double partials; rows x cols with leading dimension ld)
+template <typename TP>
+__global__ __launch_bounds__(256) void accumulate_parts_kernel(const TP* __restrict__ part, int nsplit,
+                                                               int64_t split_stride, int64_t rows, int64_t cols,
+                                                               int64_t ld, double* __restrict__ acc) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (c >= cols || r >= rows) return;
+  double v = 0.0;
+  const TP* p = part + r * ld + c;
+  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  acc[r * ld + c] += v;
+}
+
+hipError_t launch_accumulate_parts(bool f64, const void* part, int nsplit, int64_t split_stride, int64_t rows,
+                                   int64_t cols, int64_t ld, double* acc, hipStream_t st) {
+  dim3 grid((unsigned)((cols + 255) / 256), (unsigned)rows);
+  if (f64)
+    hipLaunchKernelGGL(accumulate_parts_kernel<double>, grid, dim3(256), 0, st, (const double*)part, nsplit,
+                       split_stride, rows, cols, ld, acc);
+  else
+    hipLaunchKernelGGL(accumulate_parts_kernel<float>, grid, dim3(256), 0, st, (const float*)part, nsplit,
+                       split_stride, rows, cols, ld, acc);
   return hipGetLastError();
 }
 

@@ -106,6 +106,14 @@ hipError_t launch_finish_scale(const double* sq_part, int n_part, bool rescale, 
 hipError_t launch_reduce_t(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
                            const float* col_scale, const double* d, const double* qsum, double* T, int64_t ldt,
                            hipStream_t st);
+// the same reductions from a single float64 accumulator (streamed passes)
+hipError_t launch_reduce_y64(const double* P, int64_t ldp, int ncols, int64_t n, const double* d, const double* zsum,
+                             float* Xt, int64_t ldx, double* sq_part, int* n_sq_part, hipStream_t st);
+hipError_t launch_reduce_t64(const double* P, int64_t ldp, int ncols, int64_t n, const double* d, const double* qsum,
+                             double* T, int64_t ldt, hipStream_t st);
+// acc[r][c] += sum_s part[s][r][c] over rows x cols (leading dimension ld)
+hipError_t launch_accumulate_parts(bool f64, const void* part, int nsplit, int64_t split_stride, int64_t rows,
+                                   int64_t cols, int64_t ld, double* acc, hipStream_t st);
 // flag |= nonfinite(x) over a float matrix
 hipError_t launch_check_finite_f32(const float* X, int64_t rows, int64_t cols, int64_t ld, int* flag,
                                    hipStream_t st);

@@ -63,6 +63,19 @@ struct rpca_plan_s {
   int64_t fwd_kchunk = 0;
   int64_t ldpf = 0;  // row stride of the forward split partials
   int storage = RPCA_A_F32;
+  // streamed sources (A in pinned host memory or produced by a callback), Section 4
+  bool streamed = false;
+  int64_t panel_rows = 0;       // rows per panel
+  int64_t ldb = 0;              // leading dimension of the device panel buffers
+  hipStream_t cstream = nullptr;  // host -> device copies
+  hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
+  float* dbuf[2] = {nullptr, nullptr};    // device panel buffers
+  float* staging[2] = {nullptr, nullptr};  // pinned host staging (callback source)
+  int ns_py = 1, ns_pt = 1, ns_pcs = 1;    // per-panel split counts (adjoint l / L columns, column sums)
+  int64_t rps_py = 0, rps_pt = 0, rps_pcs = 0;
+  int fwd_ks_p = 1;
+  int64_t fwd_kchunk_p = 0;
+  double* acc = nullptr;        // float64 accumulator of the adjoint products (L x ldp) or column sums
   // low-precision storage: bfloat16 hi/lo planes of the float operand
   int64_t ldxs = 0;  // X planes: cpad_x rows of ldxs (n rounded up to 64)
   int cpad_x = 0;
@@ -137,7 +150,15 @@ struct rpca_plan_s {
 
   ~rpca_plan_s() {
     DevGuard g(device);
+    if (cstream != nullptr) (void)hipStreamSynchronize(cstream);
+    if (stream != nullptr || streamed) (void)hipStreamSynchronize(stream);
     for (void* p : allocs) (void)hipFree(p);
+    for (int q = 0; q < 2; ++q) {
+      if (staging[q]) (void)hipHostFree(staging[q]);
+      if (ev_ready[q]) (void)hipEventDestroy(ev_ready[q]);
+      if (ev_free[q]) (void)hipEventDestroy(ev_free[q]);
+    }
+    if (cstream != nullptr) (void)hipStreamDestroy(cstream);
     for (auto& e : ev_fwd) {
       if (e.a) (void)hipEventDestroy(e.a);
       if (e.b) (void)hipEventDestroy(e.b);
@@ -220,7 +241,8 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   *out = nullptr;
   rpca_status vs = validate_desc(desc);
   if (vs != RPCA_OK) return vs;
-  if (desc->source != RPCA_SRC_DEVICE) return RPCA_ERR_UNSUPPORTED;
+  // streamed sources carry float32 data
+  if (desc->source != RPCA_SRC_DEVICE && desc->storage != RPCA_A_F32) return RPCA_ERR_UNSUPPORTED;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev) {
     (void)hipGetLastError();
@@ -273,10 +295,22 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
   choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
+  plan->streamed = desc->source != RPCA_SRC_DEVICE;
+  if (plan->streamed) {
+    const int64_t pr = desc->panel_rows > 0 ? desc->panel_rows : 16384;
+    plan->panel_rows = pr < m ? pr : m;
+    plan->ldb = round_up(n, 4);
+    adj_split(plan->panel_rows, n, l, slots, &plan->ns_py, &plan->rps_py);
+    adj_split(plan->panel_rows, n, L, slots, &plan->ns_pt, &plan->rps_pt);
+    fwd_split(plan->panel_rows, n, slots, &plan->fwd_ks_p, &plan->fwd_kchunk_p);
+    choose_rows(plan->panel_rows, 1024, 64, &plan->ns_pcs, &plan->rps_pcs);
+  }
 
   const int64_t ldx = plan->ldx;
-  const int64_t pcount =
-      std::max<int64_t>((int64_t)plan->ns_y * l, (int64_t)plan->ns_t * L) * plan->ldp;
+  int64_t pcount = std::max<int64_t>((int64_t)plan->ns_y * l, (int64_t)plan->ns_t * L) * plan->ldp;
+  if (plan->streamed)
+    pcount = std::max<int64_t>(pcount, std::max<int64_t>((int64_t)plan->ns_py * l, (int64_t)plan->ns_pt * L) *
+                                           plan->ldp);
   const int64_t LL = (int64_t)L * L;
   plan->sqp_cap = ((n + 255) / 256) * (int64_t)std::max(l, 1) + 16;
   hipError_t e = hipSuccess;
@@ -295,9 +329,12 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(Q, m * L);
   ALLOC(Q32, m * L);
   ALLOC(P, pcount);
-  ALLOC(Pf, plan->fwd_ks > 1 ? (int64_t)plan->fwd_ks * m * plan->ldpf : 1);
+  if (plan->streamed)
+    ALLOC(Pf, plan->fwd_ks_p > 1 ? (int64_t)plan->fwd_ks_p * plan->panel_rows * plan->ldpf : 1);
+  else
+    ALLOC(Pf, plan->fwd_ks > 1 ? (int64_t)plan->fwd_ks * m * plan->ldpf : 1);
   ALLOC(T, n * L);
-  ALLOC(csp, (int64_t)plan->ns_cs * ldx + (int64_t)plan->ns_cs * L);
+  ALLOC(csp, (int64_t)std::max(plan->ns_cs, plan->ns_pcs) * (ldx + L));
   ALLOC(gp, (int64_t)std::max(plan->ns_g, plan->ns_gt) * LL);
   ALLOC(Wg, LL);
   ALLOC(R1, LL);
@@ -319,6 +356,27 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(sqp, plan->sqp_cap);
   ALLOC(corr, L);
   ALLOC(flags, 8);
+  if (plan->streamed) {
+    ALLOC(dbuf[0], plan->panel_rows * plan->ldb);
+    ALLOC(dbuf[1], plan->panel_rows * plan->ldb);
+    ALLOC(acc, (int64_t)L * plan->ldp);
+    if (desc->source == RPCA_SRC_CALLBACK) {
+      for (int q = 0; q < 2; ++q) {
+        void* hp = nullptr;
+        if (hipHostMalloc(&hp, sizeof(float) * (size_t)(plan->panel_rows * plan->ldb), hipHostMallocDefault) !=
+            hipSuccess) {
+          (void)hipGetLastError();
+          return fail(RPCA_ERR_OUT_OF_MEMORY);
+        }
+        plan->staging[q] = static_cast<float*>(hp);
+      }
+    }
+    if (hipStreamCreateWithFlags(&plan->cstream, hipStreamNonBlocking) != hipSuccess) return fail(RPCA_ERR_HIP);
+    for (int q = 0; q < 2; ++q)
+      if (hipEventCreateWithFlags(&plan->ev_ready[q], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&plan->ev_free[q], hipEventDisableTiming) != hipSuccess)
+        return fail(RPCA_ERR_HIP);
+  }
   if (lowp) {
     ALLOC(Xh, (int64_t)plan->cpad_x * plan->ldxs);
     ALLOC(Xl, (int64_t)plan->cpad_x * plan->ldxs);
@@ -378,16 +436,76 @@ rpca_status cholqr_round(rpca_plan_s* plan, bool x_f64, const void* X, double* X
 
 }  // namespace
 
+namespace {
+
+// One pass over A in row panels (Section 4: rows as they fit), double
+// buffered: the copy stream moves panel b into device buffer b % 2 while the
+// compute stream works on panel b - 1; `fn(panel, ldb, row0, rows)` enqueues
+// the panel's kernels on the compute stream.
+template <typename Fn>
+rpca_status stream_panels(rpca_plan_s* plan, const float* Ahost, int64_t lda, rpca_panel_cb cb, void* user,
+                          Fn&& fn) {
+  const int64_t m = plan->m, n = plan->n, pr = plan->panel_rows, ldb = plan->ldb;
+  hipStream_t st = plan->stream, cs = plan->cstream;
+  const int64_t np = (m + pr - 1) / pr;
+  // the buffers may still be read by work already queued on the compute stream
+  RPCA_TRY(hipEventRecord(plan->ev_free[0], st));
+  RPCA_TRY(hipStreamWaitEvent(cs, plan->ev_free[0], 0));
+  // the staging buffers may still be read by the last copies of the previous pass
+  if (cb != nullptr) RPCA_TRY(hipStreamSynchronize(cs));
+  for (int64_t b = 0; b < np; ++b) {
+    const int s = (int)(b & 1);
+    const int64_t row0 = b * pr;
+    const int64_t rows = pr < m - row0 ? pr : m - row0;
+    if (b >= 2) RPCA_TRY(hipStreamWaitEvent(cs, plan->ev_free[s], 0));
+    const float* src = nullptr;
+    int64_t sld = lda;
+    if (cb != nullptr) {
+      // the staging buffer's previous copy must be done before the callback refills it
+      if (b >= 2) RPCA_TRY(hipEventSynchronize(plan->ev_ready[s]));
+      if (cb(user, row0, rows, plan->staging[s], ldb, nullptr) != 0) {
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamSynchronize(st);
+        return RPCA_ERR_CALLBACK;
+      }
+      src = plan->staging[s];
+      sld = ldb;
+    } else {
+      src = Ahost + row0 * lda;
+    }
+    if (sld == ldb)
+      RPCA_TRY(hipMemcpyAsync(plan->dbuf[s], src, sizeof(float) * (size_t)(rows * ldb), hipMemcpyHostToDevice, cs));
+    else
+      RPCA_TRY(hipMemcpy2DAsync(plan->dbuf[s], sizeof(float) * (size_t)ldb, src, sizeof(float) * (size_t)sld,
+                                sizeof(float) * (size_t)n, (size_t)rows, hipMemcpyHostToDevice, cs));
+    RPCA_TRY(hipEventRecord(plan->ev_ready[s], cs));
+    RPCA_TRY(hipStreamWaitEvent(st, plan->ev_ready[s], 0));
+    rpca_status r = fn(plan->dbuf[s], ldb, row0, rows);
+    if (r != RPCA_OK) return r;
+    RPCA_TRY(hipEventRecord(plan->ev_free[s], st));
+    plan->stats.h2d_bytes += rows * n * (int64_t)sizeof(float);
+  }
+  return RPCA_OK;
+}
+
+}  // namespace
+
 extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
                                    rpca_panel_cb cb, void* user, const float* G, float* U, int64_t ldu, float* S,
                                    float* V, int64_t ldv) {
-  (void)cb;
-  (void)user;
   if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
   const int64_t m = plan->m, n = plan->n;
   const int k = plan->k, l = plan->l, i = plan->i, L = plan->L;
-  if (A == nullptr || U == nullptr || S == nullptr || V == nullptr) return RPCA_ERR_INVALID_ARG;
-  if (lda < n || ldu < k || ldv < k) return RPCA_ERR_INVALID_ARG;
+  const int source = plan->d.source;
+  if (U == nullptr || S == nullptr || V == nullptr || ldu < k || ldv < k) return RPCA_ERR_INVALID_ARG;
+  if (source == RPCA_SRC_CALLBACK) {
+    if (cb == nullptr) return RPCA_ERR_INVALID_ARG;
+  } else {
+    if (A == nullptr || lda < n) return RPCA_ERR_INVALID_ARG;
+    cb = nullptr;
+  }
+  const bool streamed = plan->streamed;
+  const float* Ahost = streamed ? static_cast<const float*>(A) : nullptr;
   DevGuard g(plan->device);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t st = plan->stream;
@@ -395,11 +513,12 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   sx = rpca_stats{};
   plan->have_state = false;
   plan->nev_fwd = plan->nev_adj = 0;
-  plan->A_last = A;
+  plan->A_last = streamed ? nullptr : A;
   plan->lda_last = lda;
   const bool center = plan->d.center != 0;
   const bool rescale = !(plan->d.flags & RPCA_FLAG_NO_RESCALE);
-  const bool vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0);
+  // streamed panels sit in 16-byte aligned device buffers with ldb % 4 == 0
+  const bool vec = streamed || (((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0));
   const int64_t ldx = plan->ldx;
   const int storage = plan->storage;
   const bool lowp = storage != RPCA_A_F32;
@@ -419,7 +538,20 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const float* shift = plan->shift;
   const double* dres = nullptr;
   // Low-precision storage has no in-register shift: d is the whole mean.
-  if (center) {
+  if (center && streamed) {
+    // a streamed pass of column sums (float64, accumulated over the panels)
+    RPCA_TRY(launch_fill_f64(plan->acc, n, 0.0, st));
+    rpca_status r = stream_panels(plan, Ahost, lda, cb, user, [&](const float* P, int64_t ldb, int64_t, int64_t rows) {
+      RPCA_TRY(launch_colsum(ST_F32, P, ldb, rows, n, nullptr, 0, plan->rps_pcs, plan->ns_pcs, plan->csp, st));
+      RPCA_TRY(launch_accumulate_parts(true, plan->csp, plan->ns_pcs, n, 1, n, n, plan->acc, st));
+      return RPCA_OK;
+    });
+    if (r != RPCA_OK) return r;
+    RPCA_TRY(launch_colsum_reduce(plan->acc, 1, n, 1.0 / (double)m, plan->mu, plan->shift, plan->dres, st));
+    dres = plan->dres;
+    sx.passes += 1;
+    sx.a_bytes_read += m * n * bpe;
+  } else if (center) {
     RPCA_TRY(launch_colsum(storage, A, lda, m, n, cs, plane, plan->rps_cs, plan->ns_cs, plan->csp, st));
     if (lowp) {
       RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, n, 1.0 / (double)m, plan->mu, nullptr, nullptr, st));
@@ -441,7 +573,73 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_gen_G(plan->d.seed, n, l, X0, ldx, st));
   RPCA_TRY(launch_fill_f64(plan->alpha, i + 1, 1.0, st));
 
-  for (int j = 0; j <= i; ++j) {
+  // streamed: one host-link transfer per pass; each panel runs the forward
+  // product and the adjoint of its own rows while it is resident in HBM
+  for (int j = 0; streamed && j <= i; ++j) {
+    float* Xj = plan->X + (int64_t)j * l * ldx;
+    if (center) RPCA_TRY(launch_dot_rows(dres, Xj, ldx, n, l, plan->corr, st));
+    if (j < i) RPCA_TRY(launch_fill_f64(plan->acc, (int64_t)l * plan->ldp, 0.0, st));
+    rpca_status r = stream_panels(plan, Ahost, lda, cb, user,
+                                  [&](const float* P, int64_t ldb, int64_t row0, int64_t rows) {
+      FwdArgs fa;
+      fa.A = P;
+      fa.lda = ldb;
+      fa.m = rows;
+      fa.n = n;
+      fa.shift = shift;
+      fa.Xt = Xj;
+      fa.ldx = ldx;
+      fa.ncols = l;
+      fa.corr = center ? plan->corr : nullptr;
+      fa.alpha = plan->alpha + j;
+      fa.Z = plan->H + row0 * L + (int64_t)j * l;
+      fa.ldz = L;
+      fa.vec = true;
+      fa.ksplit = plan->fwd_ks_p;
+      fa.kchunk = plan->fwd_kchunk_p;
+      fa.P = plan->Pf;
+      fa.ldp = plan->ldpf;
+      fa.split_stride = rows * plan->ldpf;
+      RPCA_TRY(launch_fwd_f32(fa, st));
+      if (j < i) {
+        AdjArgs aa;
+        aa.A = P;
+        aa.lda = ldb;
+        aa.m = rows;
+        aa.n = n;
+        aa.shift = shift;
+        aa.Z = fa.Z;
+        aa.ldz = L;
+        aa.ncols = l;
+        aa.rows_per_split = plan->rps_py;
+        aa.nsplit = plan->ns_py;
+        aa.P = plan->P;
+        aa.ldp = plan->ldp;
+        aa.split_stride = (int64_t)l * plan->ldp;
+        aa.vec = true;
+        RPCA_TRY(launch_adj_f32(aa, st));
+        RPCA_TRY(launch_accumulate_parts(false, plan->P, plan->ns_py, aa.split_stride, l, n, plan->ldp, plan->acc,
+                                         st));
+      }
+      return RPCA_OK;
+    });
+    if (r != RPCA_OK) return r;
+    sx.passes += 1;
+    sx.a_bytes_read += m * n * bpe;
+    if (j == i) break;
+    if (center) {
+      RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cs, plan->ns_cs,
+                             plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, l, 1.0, plan->zsum, nullptr, nullptr, st));
+    }
+    float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
+    int npart = 0;
+    RPCA_TRY(launch_reduce_y64(plan->acc, plan->ldp, l, n, dres, center ? plan->zsum : nullptr, Xn, ldx, plan->sqp,
+                               &npart, st));
+    RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
+  }
+
+  for (int j = 0; !streamed && j <= i; ++j) {
     float* Xj = plan->X + (int64_t)j * l * ldx;
     if (center) RPCA_TRY(launch_dot_rows(dres, Xj, ldx, n, l, plan->corr, st));
     FwdArgs fa;
@@ -575,7 +773,34 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_colsum(ST_F32, plan->Q32, L, m, L, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
     RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, L, 1.0, plan->zsum, nullptr, nullptr, st));
   }
-  {
+  if (streamed) {
+    RPCA_TRY(launch_fill_f64(plan->acc, (int64_t)L * plan->ldp, 0.0, st));
+    rpca_status r = stream_panels(plan, Ahost, lda, cb, user,
+                                  [&](const float* P, int64_t ldb, int64_t row0, int64_t rows) {
+      AdjArgs aa;
+      aa.A = P;
+      aa.lda = ldb;
+      aa.m = rows;
+      aa.n = n;
+      aa.shift = shift;
+      aa.Z = plan->Q32 + row0 * L;
+      aa.ldz = L;
+      aa.ncols = L;
+      aa.rows_per_split = plan->rps_pt;
+      aa.nsplit = plan->ns_pt;
+      aa.P = plan->P;
+      aa.ldp = plan->ldp;
+      aa.split_stride = (int64_t)L * plan->ldp;
+      aa.vec = true;
+      RPCA_TRY(launch_adj_f32(aa, st));
+      RPCA_TRY(launch_accumulate_parts(false, plan->P, plan->ns_pt, aa.split_stride, L, n, plan->ldp, plan->acc, st));
+      return RPCA_OK;
+    });
+    if (r != RPCA_OK) return r;
+    RPCA_TRY(launch_reduce_t64(plan->acc, plan->ldp, L, n, dres, center ? plan->zsum : nullptr, plan->T, L, st));
+    sx.passes += 1;
+    sx.a_bytes_read += m * n * bpe;
+  } else {
     AdjArgs aa;
     aa.A = A;
     aa.lda = lda;
@@ -751,6 +976,7 @@ rpca_status backward_alloc(rpca_plan_s* plan) {
 extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, int64_t ldgu,
                                      const float* gV, int64_t ldgv, float* dA, int64_t ldda) {
   if (plan == nullptr || dA == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (plan->streamed) return RPCA_ERR_UNSUPPORTED;  // the reverse sweep reads A from HBM
   if (!plan->have_state || !(plan->d.flags & RPCA_FLAG_KEEP_STATE) || plan->A_last == nullptr)
     return RPCA_ERR_NO_STATE;
   if (plan->storage != RPCA_A_F32) return RPCA_ERR_UNSUPPORTED;

@@ -84,6 +84,7 @@ class Plan:
         self.L = (self.i + 1) * self.l
         self.center = bool(center)
         self.storage = storage
+        self.source = source
         d = Desc(m=self.m, n=self.n, k=self.k, l=self.l, i=self.i, storage=STORAGE[storage],
                  source=SOURCE[source], center=1 if center else 0, panel_rows=int(panel_rows),
                  seed=int(seed) & 0xFFFFFFFFFFFFFFFF, flags=int(flags), device=self.device.index or 0)
@@ -108,10 +109,36 @@ class Plan:
     def __exit__(self, *exc):
         self.close()
 
-    def factor(self, A, G=None, col_scale=None, out=None):
-        """A: a float32 row-major tensor (f32 plans) or a :class:`Stored` from :func:`quantize`."""
+    def factor(self, A=None, G=None, col_scale=None, out=None, panel_fn=None):
+        """A: a float32 row-major tensor (f32 plans) or a :class:`Stored` from :func:`quantize`.
+
+        source "host_pinned": A is a pinned CPU float32 tensor.  source "callback": A is None and
+        panel_fn(row0, nrows, buf) fills buf[:, :n] (a float32 NumPy view of nrows x ld, pinned host
+        memory) with rows row0 .. row0 + nrows - 1 and returns nothing (an exception is reported as
+        RPCA_ERR_CALLBACK).
+        """
         m, n, k = self.m, self.n, self.k
-        if isinstance(A, Stored):
+        cb = PANEL_CB()
+        data, lda = None, 0
+        if self.source == "callback":
+            if panel_fn is None:
+                raise ValueError("a callback plan needs panel_fn")
+            import numpy as np
+
+            def _cb(user, row0, nrows, dst, ld, cs):
+                try:
+                    buf = np.ctypeslib.as_array(ctypes.cast(dst, ctypes.POINTER(ctypes.c_float)),
+                                                shape=(int(nrows), int(ld)))
+                    panel_fn(int(row0), int(nrows), buf)
+                    return 0
+                except Exception:
+                    return 1
+            cb = PANEL_CB(_cb)
+        elif self.source == "host_pinned":
+            if A.device.type != "cpu" or not A.is_pinned() or A.dtype != torch.float32 or A.stride(1) != 1:
+                raise ValueError("a host_pinned plan takes a pinned CPU float32 row-major tensor")
+            data, lda = A, A.stride(0)
+        elif isinstance(A, Stored):
             if A.storage != self.storage or A.m != m or A.n != n:
                 raise ValueError(f"stored matrix is {A.storage} {A.m} x {A.n}; plan is {self.storage} {m} x {n}")
             data, lda, col_scale = A.data, A.ld, A.col_scale
@@ -121,7 +148,7 @@ class Plan:
             if A.dim() != 2 or A.shape[0] < m or A.stride(1) != 1 or A.dtype != torch.float32:
                 raise ValueError("A must be a row-major 2-D float32 tensor")
             data, lda = A, A.stride(0)
-        if data.device != self.device:
+        if self.source == "device" and data.device != self.device:
             raise ValueError("A must live on the plan's device")
         if G is not None:
             if G.dtype != torch.float32 or tuple(G.shape) != (n, self.l) or not G.is_contiguous():
@@ -132,7 +159,6 @@ class Plan:
             V = torch.empty((n, k), dtype=torch.float32, device=self.device)
         else:
             U, S, V = out
-        cb = PANEL_CB()
         rc = self.lib.rpca_factor(self.handle, _ptr(data), lda, _ptr(col_scale), cb, None, _ptr(G),
                                   _ptr(U), U.stride(0), _ptr(S), _ptr(V), V.stride(0))
         check(rc, "rpca_factor")
