@@ -198,35 +198,35 @@ hipError_t launch_transpose_sq(const double* in, int L, bool upper_only, double*
 __global__ void transpose_out_kernel(const double* __restrict__ X, int64_t ldx, int64_t rows, int cols,
                                      float* __restrict__ out32, double* __restrict__ out64, int64_t ldo) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int c = blockIdx.y;
   if (r >= rows) return;
-  const double v = X[r * ldx + c];
-  if (out32 != nullptr) out32[(int64_t)c * ldo + r] = (float)v;
-  if (out64 != nullptr) out64[(int64_t)c * ldo + r] = v;
+  for (int c = blockIdx.y; c < cols; c += gridDim.y) {
+    const double v = X[r * ldx + c];
+    if (out32 != nullptr) out32[(int64_t)c * ldo + r] = (float)v;
+    if (out64 != nullptr) out64[(int64_t)c * ldo + r] = v;
+  }
 }
 
 hipError_t launch_transpose_out(const double* X, int64_t ldx, int64_t rows, int cols, float* out32, double* out64,
                                 int64_t ldo, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)cols);
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)(cols < 65535 ? cols : 65535));
   hipLaunchKernelGGL(transpose_out_kernel, grid, dim3(256), 0, st, X, ldx, rows, cols, out32, out64, ldo);
   return hipGetLastError();
 }
 
 // Y64[c][r] = (double) X32[c][r] for c < rows_t (row-major copy of transposed float blocks)
-__global__ void widen_kernel(const float* __restrict__ X, int64_t ldx, int64_t cols, double* __restrict__ Y,
-                             int64_t ldy) {
+__global__ void widen_kernel(const float* __restrict__ X, int64_t ldx, int nrows, int64_t cols,
+                             double* __restrict__ Y, int64_t ldy) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int c = blockIdx.y;
   if (r >= cols) return;
-  Y[(int64_t)c * ldy + r] = (double)X[(int64_t)c * ldx + r];
+  for (int c = blockIdx.y; c < nrows; c += gridDim.y) Y[(int64_t)c * ldy + r] = (double)X[(int64_t)c * ldx + r];
 }
 
 hipError_t launch_widen(const float* X, int64_t ldx, int nrows, int64_t ncols, double* Y, int64_t ldy,
                         hipStream_t st) {
   if (nrows <= 0 || ncols <= 0) return hipSuccess;
-  dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)nrows);
-  hipLaunchKernelGGL(widen_kernel, grid, dim3(256), 0, st, X, ldx, ncols, Y, ldy);
+  dim3 grid((unsigned)((ncols + 255) / 256), (unsigned)(nrows < 65535 ? nrows : 65535));
+  hipLaunchKernelGGL(widen_kernel, grid, dim3(256), 0, st, X, ldx, nrows, ncols, Y, ldy);
   return hipGetLastError();
 }
 
@@ -342,6 +342,58 @@ hipError_t launch_center_f64(double* X, int64_t ldx, int64_t rows, int cols, int
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sub_colmean_kernel, dim3((unsigned)rows, (unsigned)((cols + 255) / 256)), dim3(256), 0, st, X,
                      ldx, rows, cols, part, nsplit, 1.0 / (double)rows);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- residual estimator helpers
+// out[r][c] = normal(seed, stream, r * cols + c) (float64)
+__global__ void gen_normal64_kernel(uint64_t seed, uint32_t stream, int64_t rows, int cols, double* __restrict__ out,
+                                    int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e / cols;
+  const int c = (int)(e % cols);
+  out[r * ldo + c] = normal_elem(seed, stream, (uint64_t)e);
+}
+
+hipError_t launch_gen_normal64(uint64_t seed, uint32_t stream, int64_t rows, int cols, double* out, int64_t ldo,
+                               hipStream_t st) {
+  const int64_t tot = rows * cols;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gen_normal64_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, seed, stream, rows,
+                     cols, out, ldo);
+  return hipGetLastError();
+}
+
+// C[a][b] = -s[a] * C[a][b]  (k x q)
+__global__ void neg_rowscale_kernel(double* __restrict__ C, const float* __restrict__ s, int k, int q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * q) return;
+  C[e] = -(double)s[e / q] * C[e];
+}
+
+hipError_t launch_neg_rowscale(double* C, const float* s, int k, int q, hipStream_t st) {
+  if (k * q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(neg_rowscale_kernel, dim3((unsigned)((k * q + 255) / 256)), dim3(256), 0, st, C, s, k, q);
+  return hipGetLastError();
+}
+
+// out = sqrt(max_c v[c]) (one workgroup)
+__global__ __launch_bounds__(256) void sqrt_max_kernel(const double* __restrict__ v, int q, double* __restrict__ out) {
+  __shared__ double sh[256];
+  double best = 0.0;
+  for (int c = threadIdx.x; c < q; c += 256) best = fmax(best, v[c]);
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(sh[0]);
+}
+
+hipError_t launch_sqrt_max(const double* v, int q, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sqrt_max_kernel, dim3(1), dim3(256), 0, st, v, q, out);
   return hipGetLastError();
 }
 

@@ -179,5 +179,10 @@ hipError_t launch_copy_cols(bool x64, const void* X, int64_t ldx, int64_t rows, 
                             hipStream_t st);
 hipError_t launch_center_f64(double* X, int64_t ldx, int64_t rows, int cols, int64_t rows_per_split, int nsplit,
                              double* part, hipStream_t st);
+// residual estimator helpers
+hipError_t launch_gen_normal64(uint64_t seed, uint32_t stream, int64_t rows, int cols, double* out, int64_t ldo,
+                               hipStream_t st);
+hipError_t launch_neg_rowscale(double* C, const float* s, int k, int q, hipStream_t st);
+hipError_t launch_sqrt_max(const double* v, int q, double* out, hipStream_t st);
 
 }  // namespace rpca

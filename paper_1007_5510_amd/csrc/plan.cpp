@@ -1124,13 +1124,130 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   return RPCA_OK;
 }
 
+// Appendix estimator p_{j,q}(D) of ||D||_2 for D = A~ - U S V^T: the q start
+// vectors (Philox stream 9, iid N(0,1)) run through j products with D^T D as
+// one block; each column is divided by its norm after every product (which
+// changes neither the ratios nor their maximum), the last norms are the
+// ratios ||(D^T D)^j w|| / ||(D^T D)^(j-1) w||, and the estimate is the square
+// root of the largest.  Passes over A use the float32 panel kernels; the
+// rank-k correction and the normalisation run in float64.
 extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
                                      const float* U, int64_t ldu, const float* S, const float* V, int64_t ldv,
                                      int32_t j, int32_t q, uint64_t seed, double* estimate) {
-  (void)A; (void)lda; (void)col_scale; (void)U; (void)ldu; (void)S; (void)V; (void)ldv; (void)j; (void)q;
-  (void)seed; (void)estimate;
-  if (plan == nullptr) return RPCA_ERR_INVALID_ARG;
-  return RPCA_ERR_UNSUPPORTED;
+  (void)col_scale;
+  if (plan == nullptr || A == nullptr || U == nullptr || S == nullptr || V == nullptr || estimate == nullptr)
+    return RPCA_ERR_INVALID_ARG;
+  if (plan->storage != RPCA_A_F32 || plan->streamed) return RPCA_ERR_UNSUPPORTED;
+  const int64_t m = plan->m, n = plan->n, ldx = plan->ldx, ldp = plan->ldp;
+  const int k = plan->k;
+  if (j < 1 || q < 1 || q > 1024 || lda < n || ldu < k || ldv < k) return RPCA_ERR_INVALID_ARG;
+  DevGuard g(plan->device);
+  hipStream_t st = plan->stream;
+  const bool center = plan->d.center != 0;
+  const float* Af = static_cast<const float*>(A);
+  const bool vec = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0);
+  hipDeviceProp_t prop;
+  RPCA_TRY(hipGetDeviceProperties(&prop, plan->device));
+  int ns = 1;
+  int64_t rps = 0;
+  adj_split(m, n, q, (int64_t)prop.multiProcessorCount * 2, &ns, &rps);
+  // workspace (freed on return)
+  if (center && !plan->have_state) return RPCA_ERR_NO_STATE;  // the column means come from rpca_factor
+  std::vector<void*> mem;
+  bool ok = true;
+  auto grab = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      ok = false;
+      return nullptr;
+    }
+    mem.push_back(p);
+    return p;
+  };
+  struct Free {
+    std::vector<void*>* v;
+    ~Free() {
+      for (void* p : *v) (void)hipFree(p);
+    }
+  } freer{&mem};
+  double* x = static_cast<double*>(grab(sizeof(double) * (size_t)(n * q)));
+  float* xt = static_cast<float*>(grab(sizeof(float) * (size_t)(q * ldx)));
+  float* z = static_cast<float*>(grab(sizeof(float) * (size_t)(m * q)));
+  double* dx = static_cast<double*>(grab(sizeof(double) * (size_t)(m * q)));
+  float* yt = static_cast<float*>(grab(sizeof(float) * (size_t)(q * ldx)));
+  double* y = static_cast<double*>(grab(sizeof(double) * (size_t)(n * q)));
+  double* c = static_cast<double*>(grab(sizeof(double) * (size_t)(k * q)));
+  double* nrm = static_cast<double*>(grab(sizeof(double) * (size_t)q));
+  double* sg = static_cast<double*>(grab(sizeof(double) * (size_t)q));
+  double* est = static_cast<double*>(grab(sizeof(double)));
+  float* part = static_cast<float*>(grab(sizeof(float) * (size_t)(ns * q * ldp)));
+  double* xpart = static_cast<double*>(grab(sizeof(double) * (size_t)(std::max(plan->ns_g, plan->ns_gt) * k * q)));
+  float* corr = static_cast<float*>(grab(sizeof(float) * (size_t)q));
+  double* zsum = static_cast<double*>(grab(sizeof(double) * (size_t)q));
+  double* sq = static_cast<double*>(grab(sizeof(double) * (size_t)(((n + 255) / 256) * q + 16)));
+  if (!ok) return RPCA_ERR_OUT_OF_MEMORY;
+  const double* dres = center ? plan->dres : nullptr;
+
+  RPCA_TRY(launch_gen_normal64(seed, 9u, n, q, x, q, st));
+  RPCA_TRY(launch_normalize_sign(x, n, q, q, nrm, sg, st));
+  for (int step = 0; step < j; ++step) {
+    // D x = A~ x - U (S o (V^T x))
+    RPCA_TRY(launch_transpose_out(x, q, n, q, xt, nullptr, ldx, st));
+    if (center) RPCA_TRY(launch_dot_rows(dres, xt, ldx, n, q, corr, st));
+    FwdArgs fa;
+    fa.A = Af;
+    fa.lda = lda;
+    fa.m = m;
+    fa.n = n;
+    fa.shift = plan->shift;
+    fa.Xt = xt;
+    fa.ldx = ldx;
+    fa.ncols = q;
+    fa.corr = center ? corr : nullptr;
+    fa.Z = z;
+    fa.ldz = q;
+    fa.vec = vec;
+    RPCA_TRY(launch_fwd_f32(fa, st));
+    RPCA_TRY(launch_add_f32(z, q, m, q, dx, q, false, st));
+    RPCA_TRY(launch_xty(false, V, ldv, k, true, x, q, q, n, plan->rps_gt, plan->ns_gt, nullptr, xpart, c, st));
+    RPCA_TRY(launch_neg_rowscale(c, S, k, q, st));
+    RPCA_TRY(launch_gemm64(false, U, ldu, c, q, m, q, k, false, nullptr, dx, q, z, q, st, dx, q));
+    // y = A~^T (D x) - V (S o (U^T D x))
+    if (center) {
+      RPCA_TRY(launch_colsum(ST_F32, z, q, m, q, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, q, 1.0, zsum, nullptr, nullptr, st));
+    }
+    AdjArgs aa;
+    aa.A = Af;
+    aa.lda = lda;
+    aa.m = m;
+    aa.n = n;
+    aa.shift = plan->shift;
+    aa.Z = z;
+    aa.ldz = q;
+    aa.ncols = q;
+    aa.rows_per_split = rps;
+    aa.nsplit = ns;
+    aa.P = part;
+    aa.ldp = ldp;
+    aa.split_stride = (int64_t)q * ldp;
+    aa.vec = vec;
+    RPCA_TRY(launch_adj_f32(aa, st));
+    int npart = 0;
+    RPCA_TRY(launch_reduce_y(part, ns, aa.split_stride, ldp, q, n, nullptr, dres, center ? zsum : nullptr, yt, ldx,
+                             sq, &npart, st));
+    RPCA_TRY(launch_widen(yt, ldx, q, n, y, n, st));  // y^T (q x n) in float64
+    RPCA_TRY(launch_transpose_out(y, n, q, (int)n, nullptr, x, q, st));  // x = y (n x q)
+    RPCA_TRY(launch_xty(false, U, ldu, k, true, dx, q, q, m, plan->rps_g, plan->ns_g, nullptr, xpart, c, st));
+    RPCA_TRY(launch_neg_rowscale(c, S, k, q, st));
+    RPCA_TRY(launch_gemm64(false, V, ldv, c, q, n, q, k, false, nullptr, x, q, nullptr, 0, st, x, q));
+    RPCA_TRY(launch_normalize_sign(x, n, q, q, nrm, sg, st));
+  }
+  RPCA_TRY(launch_sqrt_max(nrm, q, est, st));
+  RPCA_TRY(hipMemcpyAsync(estimate, est, sizeof(double), hipMemcpyDeviceToHost, st));
+  RPCA_TRY(hipStreamSynchronize(st));
+  return RPCA_OK;
 }
 
 extern "C" rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out,

@@ -177,6 +177,15 @@ class Plan:
               "rpca_backward")
         return dA
 
+    def residual(self, A, U, S, V, j=6, q=None, seed=0):
+        """Appendix estimate p_{j,q} of ||A~ - U S V^T||_2 (q start vectors, default k; device float32 inputs)."""
+        q = self.k if q is None else int(q)
+        est = ctypes.c_double(0.0)
+        check(self.lib.rpca_residual(self.handle, _ptr(A), A.stride(0), None, _ptr(U), U.stride(0), _ptr(S), _ptr(V),
+                                     V.stride(0), int(j), q, int(seed) & 0xFFFFFFFFFFFFFFFF, ctypes.byref(est)),
+              "rpca_residual")
+        return est.value
+
     def state(self, which: str):
         m, n, L = self.m, self.n, self.L
         shapes = {"H": ((m, L), torch.float32), "HSCALE": ((self.i + 1,), torch.float64),
