@@ -247,6 +247,54 @@ hipError_t launch_reduce_t64(const double* P, int64_t ldp, int ncols, int64_t n,
   return hipGetLastError();
 }
 
+// Centring fused into pass 0.  Pass 0 runs with the shift s0 (mean of a first
+// row panel) and its adjoint also forms the column sums of A - 1 s0^T (row
+// `row` of each split partial).  Then d0 = those sums / m, mu = s0 + d0, and
+// the shift of the later passes becomes fl32(mu) with residual mu - fl32(mu).
+__global__ __launch_bounds__(256) void pass0_center_kernel(const float* __restrict__ P, int nsplit,
+                                                           int64_t split_stride, int64_t ldp, int row, int64_t n,
+                                                           double inv_m, float* __restrict__ shift,
+                                                           double* __restrict__ d0, double* __restrict__ mu,
+                                                           double* __restrict__ dres) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  double v = 0.0;
+  const float* p = P + (int64_t)row * ldp + c;
+  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  const double d = v * inv_m;
+  const double u = (double)shift[c] + d;
+  const float s1 = (float)u;
+  d0[c] = d;
+  mu[c] = u;
+  shift[c] = s1;
+  dres[c] = u - (double)s1;
+}
+
+hipError_t launch_pass0_center(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int row, int64_t n,
+                               int64_t m, float* shift, double* d0, double* mu, double* dres, hipStream_t st) {
+  hipLaunchKernelGGL(pass0_center_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, nsplit,
+                     split_stride, ldp, row, n, 1.0 / (double)m, shift, d0, mu, dres);
+  return hipGetLastError();
+}
+
+// X[r][c] -= corr[c] (float32, rows x cols)
+__global__ void sub_cols_kernel(float* __restrict__ X, int64_t ldx, int64_t rows, int cols,
+                                const float* __restrict__ corr) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t r = e / cols;
+  const int c = (int)(e % cols);
+  X[r * ldx + c] -= corr[c];
+}
+
+hipError_t launch_sub_cols(float* X, int64_t ldx, int64_t rows, int cols, const float* corr, hipStream_t st) {
+  const int64_t tot = rows * cols;
+  if (tot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sub_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, X, ldx, rows, cols,
+                     corr);
+  return hipGetLastError();
+}
+
 // acc[r][c] += sum_s part[s][r][c] (float or double partials; rows x cols with leading dimension ld)
 template <typename TP>
 __global__ __launch_bounds__(256) void accumulate_parts_kernel(const TP* __restrict__ part, int nsplit,

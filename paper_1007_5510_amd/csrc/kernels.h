@@ -44,6 +44,7 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
   int ncols = 0;
   int64_t rows_per_split = 0;     // multiple of 4
   int nsplit = 0;
+  bool ones = false;              // float32 kernel: row ncols of each P_s = column sums of A_s - 1 s^T
   float* P = nullptr;             // [nsplit][ncols][ldp]
   int64_t ldp = 0, split_stride = 0;
   bool vec = false;
@@ -114,6 +115,12 @@ hipError_t launch_reduce_t64(const double* P, int64_t ldp, int ncols, int64_t n,
 // acc[r][c] += sum_s part[s][r][c] over rows x cols (leading dimension ld)
 hipError_t launch_accumulate_parts(bool f64, const void* part, int nsplit, int64_t split_stride, int64_t rows,
                                    int64_t cols, int64_t ld, double* acc, hipStream_t st);
+// centring fused into pass 0: d0 = colsum(A - 1 s0^T)/m from row `row` of the adjoint partials,
+// mu = s0 + d0, shift <- fl32(mu), dres = mu - fl32(mu)
+hipError_t launch_pass0_center(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int row, int64_t n,
+                               int64_t m, float* shift, double* d0, double* mu, double* dres, hipStream_t st);
+// X[r][c] -= corr[c]
+hipError_t launch_sub_cols(float* X, int64_t ldx, int64_t rows, int cols, const float* corr, hipStream_t st);
 // flag |= nonfinite(x) over a float matrix
 hipError_t launch_check_finite_f32(const float* X, int64_t rows, int64_t cols, int64_t ld, int* flag,
                                    hipStream_t st);

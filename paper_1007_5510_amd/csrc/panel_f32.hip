@@ -252,7 +252,7 @@ template <int NT, bool VEC>
 __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
     const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
     const float* __restrict__ Z, int64_t ldz, int ncols, int64_t rows_per_split, int nsplit,
-    int jtiles, int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride) {
+    int jtiles, int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride, int ones) {
   // Z rows staged per block, interleaved so that lane (p, kk) finds its NT
   // B-operand values (columns p, 16+p, 32+p, 48+p) in one 16-byte word.
   __shared__ float Zs[2][ADJ_RS][16][4];
@@ -277,13 +277,16 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
   const floatx4 sh = VEC ? ld4<true>(shift + clc) : ld4_masked(shift, cl, n);
   // cooperative Z loader: 4 elements per thread per stage, element e = tid + 256 q
   // -> row e / 64, column e % 64 (clamped to the last real column)
+  // with `ones`, column ncols of Z is an implicit column of ones (its product is the column sums)
   int zcol[4], zrow[4], zslot[4];
+  bool zone[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + 256 * q;
     const int cc = e & 63;
     zrow[q] = e >> 6;
     zcol[q] = j0 + cc < ncols ? j0 + cc : ncols - 1;
+    zone[q] = ones && j0 + cc == ncols;
     zslot[q] = (cc & 15) * 4 + (cc >> 4);  // [p][t] with column 16 t + p
   }
 
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
   };
   auto load_z = [&](ZStage& b, int64_t rb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) b.z[q] = Z[(rb + zrow[q]) * ldz + zcol[q]];
+    for (int q = 0; q < 4; ++q) b.z[q] = zone[q] ? 1.f : Z[(rb + zrow[q]) * ldz + zcol[q]];
   };
   auto store_z = [&](const ZStage& b, int buf) {
     float* base = &Zs[buf][0][0][0];
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t r = rt + zrow[q];
-      base[zrow[q] * 64 + zslot[q]] = r < rend ? Z[r * ldz + zcol[q]] : 0.f;
+      base[zrow[q] * 64 + zslot[q]] = r < rend ? (zone[q] ? 1.f : Z[r * ldz + zcol[q]]) : 0.f;
     }
     AStage at;
 #pragma unroll
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = j0 + 16 * t + p;
-    if (j >= ncols) continue;
+    if (j > ncols || (j == ncols && !ones)) continue;
     float* __restrict__ prow = Ps + (int64_t)j * ldp;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
@@ -517,7 +520,7 @@ hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
   if (a.A == nullptr || a.shift == nullptr || a.Z == nullptr || a.P == nullptr) return hipErrorInvalidValue;
   if (a.lda < a.n || a.ldp < a.n || a.rows_per_split % 4 != 0) return hipErrorInvalidValue;
   if ((int64_t)a.nsplit * a.rows_per_split < a.m) return hipErrorInvalidValue;
-  const int jtiles = (a.ncols + 63) / 64;
+  const int jtiles = (a.ncols + (a.ones ? 1 : 0) + 63) / 64;
   const int ctiles = (int)((a.n + 255) / 256);
   const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
   dim3 grid((unsigned)total);
@@ -526,11 +529,11 @@ hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
   if (vec)
     hipLaunchKernelGGL((adj_f32_kernel<4, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
                        a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P, a.ldp,
-                       a.split_stride);
+                       a.split_stride, a.ones ? 1 : 0);
   else
     hipLaunchKernelGGL((adj_f32_kernel<4, false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
                        a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P, a.ldp,
-                       a.split_stride);
+                       a.split_stride, a.ones ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
   return e;

@@ -88,6 +88,7 @@ struct rpca_plan_s {
   float* shift = nullptr;   // ldx
   double* mu = nullptr;     // n
   double* dres = nullptr;   // n: mu - fl32(mu)
+  double* d0 = nullptr;     // n: colsum(A - 1 s0^T) / m of pass 0 (centring fused into pass 0)
   float* H = nullptr;       // m x L
   double* Q1 = nullptr;     // m x L
   double* Q = nullptr;      // m x L
@@ -307,7 +308,7 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   }
 
   const int64_t ldx = plan->ldx;
-  int64_t pcount = std::max<int64_t>((int64_t)plan->ns_y * l, (int64_t)plan->ns_t * L) * plan->ldp;
+  int64_t pcount = std::max<int64_t>((int64_t)plan->ns_y * (l + 1), (int64_t)plan->ns_t * L) * plan->ldp;
   if (plan->streamed)
     pcount = std::max<int64_t>(pcount, std::max<int64_t>((int64_t)plan->ns_py * l, (int64_t)plan->ns_pt * L) *
                                            plan->ldp);
@@ -324,6 +325,7 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   ALLOC(shift, ldx);
   ALLOC(mu, n);
   ALLOC(dres, n);
+  ALLOC(d0, n);
   ALLOC(H, m * L);
   ALLOC(Q1, m * L);
   ALLOC(Q, m * L);
@@ -538,6 +540,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const float* shift = plan->shift;
   const double* dres = nullptr;
   // Low-precision storage has no in-register shift: d is the whole mean.
+  // In-core float32 folds the column means into pass 0 (no separate pass).
+  const bool fuse0 = center && !streamed && !lowp && i >= 1;
   if (center && streamed) {
     // a streamed pass of column sums (float64, accumulated over the panels)
     RPCA_TRY(launch_fill_f64(plan->acc, n, 0.0, st));
@@ -551,6 +555,15 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     dres = plan->dres;
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
+  } else if (fuse0) {
+    // shift of pass 0: the column means of the first row panel
+    const int64_t rows0 = m < 16384 ? m : 16384;
+    int ns0 = 1;
+    int64_t rps0 = 0;
+    choose_rows(rows0, 1024, 64, &ns0, &rps0);
+    RPCA_TRY(launch_colsum(ST_F32, A, lda, rows0, n, nullptr, 0, rps0, ns0, plan->csp, st));
+    RPCA_TRY(launch_colsum_reduce(plan->csp, ns0, n, 1.0 / (double)rows0, plan->mu, plan->shift, nullptr, st));
+    sx.a_bytes_read += rows0 * n * bpe;
   } else if (center) {
     RPCA_TRY(launch_colsum(storage, A, lda, m, n, cs, plane, plan->rps_cs, plan->ns_cs, plan->csp, st));
     if (lowp) {
@@ -641,7 +654,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
 
   for (int j = 0; !streamed && j <= i; ++j) {
     float* Xj = plan->X + (int64_t)j * l * ldx;
-    if (center) RPCA_TRY(launch_dot_rows(dres, Xj, ldx, n, l, plan->corr, st));
+    // with fused centring, pass 0 writes the uncorrected product (A - 1 s0^T) G and corrects it below
+    const bool p0 = fuse0 && j == 0;
+    if (center && !p0) RPCA_TRY(launch_dot_rows(dres, Xj, ldx, n, l, plan->corr, st));
     FwdArgs fa;
     fa.A = A;
     fa.lda = lda;
@@ -651,7 +666,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     fa.Xt = Xj;
     fa.ldx = ldx;
     fa.ncols = l;
-    fa.corr = center ? plan->corr : nullptr;
+    fa.corr = (center && !p0) ? plan->corr : nullptr;
     fa.alpha = plan->alpha + j;
     fa.Z = plan->H + (int64_t)j * l;
     fa.ldz = L;
@@ -696,8 +711,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     aa.nsplit = plan->ns_y;
     aa.P = plan->P;
     aa.ldp = plan->ldp;
-    aa.split_stride = (int64_t)l * plan->ldp;
+    aa.split_stride = (int64_t)(p0 ? l + 1 : l) * plan->ldp;
     aa.vec = vec;
+    aa.ones = p0;
     if (EventPair* ev = next_adj_events(plan)) {
       aa.ev_begin = ev->a;
       aa.ev_end = ev->b;
@@ -712,10 +728,21 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     } else {
       RPCA_TRY(launch_adj_f32(aa, st));
     }
+    if (p0) {
+      // d0 = colsum(A - 1 s0^T)/m; the later passes shift by fl32(s0 + d0)
+      RPCA_TRY(launch_pass0_center(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, m, plan->shift, plan->d0,
+                                   plan->mu, plan->dres, st));
+      dres = plan->dres;
+    }
     float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
     int npart = 0;
-    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, cs, dres,
+    // X_1 = (A - 1 s0^T)^T Z - d0 (1^T Z)^T with Z the uncorrected block (exact: colsum(A - 1 s0^T) = m d0)
+    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, cs, p0 ? plan->d0 : dres,
                              center ? plan->zsum : nullptr, Xn, ldx, plan->sqp, &npart, st));
+    if (p0) {  // H^(0) = (A - 1 s0^T) G - 1 (d0^T G)  (block scale 1)
+      RPCA_TRY(launch_dot_rows(plan->d0, Xj, ldx, n, l, plan->corr, st));
+      RPCA_TRY(launch_sub_cols(plan->H, L, m, l, plan->corr, st));
+    }
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
   RPCA_TRY(launch_check_finite_f32(plan->H, m, L, L, plan->flags, st));
