@@ -55,6 +55,8 @@ struct rpca_plan_s {
   int64_t rps_y = 0, rps_t = 0;
   int ns_cs = 1;  // column-sum splits over A
   int64_t rps_cs = 0;
+  int ns_cn = 1;  // column-sum splits over the narrow m-row blocks (H, Q)
+  int64_t rps_cn = 0;
   int ns_g = 1;   // Gram splits over H / Q rows
   int64_t rps_g = 0;
   int ns_gt = 1;  // Gram splits over T rows
@@ -293,8 +295,9 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     fwd_split(m, n, slots, &plan->fwd_ks, &plan->fwd_kchunk);
   }
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
-  choose_rows(m, 4096, 128, &plan->ns_g, &plan->rps_g);
-  choose_rows(n, 2048, 64, &plan->ns_gt, &plan->rps_gt);
+  choose_rows(m, 512, 1024, &plan->ns_cn, &plan->rps_cn);
+  choose_rows(m, 1024, 512, &plan->ns_g, &plan->rps_g);
+  choose_rows(n, 256, 256, &plan->ns_gt, &plan->rps_gt);
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
   plan->streamed = desc->source != RPCA_SRC_DEVICE;
   if (plan->streamed) {
@@ -336,7 +339,8 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   else
     ALLOC(Pf, plan->fwd_ks > 1 ? (int64_t)plan->fwd_ks * m * plan->ldpf : 1);
   ALLOC(T, n * L);
-  ALLOC(csp, (int64_t)std::max(plan->ns_cs, plan->ns_pcs) * (ldx + L));
+  ALLOC(csp, std::max<int64_t>((int64_t)std::max(plan->ns_cs, plan->ns_pcs) * (ldx + L),
+                                (int64_t)plan->ns_cn * std::max(L, 1024)));
   ALLOC(gp, (int64_t)std::max(plan->ns_g, plan->ns_gt) * LL);
   ALLOC(Wg, LL);
   ALLOC(R1, LL);
@@ -641,9 +645,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     sx.a_bytes_read += m * n * bpe;
     if (j == i) break;
     if (center) {
-      RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cs, plan->ns_cs,
+      RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cn, plan->ns_cn,
                              plan->csp, st));
-      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, l, 1.0, plan->zsum, nullptr, nullptr, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, l, 1.0, plan->zsum, nullptr, nullptr, st));
     }
     float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
     int npart = 0;
@@ -695,9 +699,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     if (j == i) break;
     // fused half of the pass: X_{j+1} = A~^T H^(j)
     if (center)
-      RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cs, plan->ns_cs,
+      RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cn, plan->ns_cn,
                              plan->csp, st));
-    if (center) RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, l, 1.0, plan->zsum, nullptr, nullptr, st));
+    if (center) RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, l, 1.0, plan->zsum, nullptr, nullptr, st));
     AdjArgs aa;
     aa.A = A;
     aa.lda = lda;
@@ -760,8 +764,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   for (int attempt = 0; attempt < 2; ++attempt) {
     RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 3 * sizeof(int), st));
     if (center) {
-      RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
-      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, L, 1.0, plan->zsum, nullptr, nullptr, st));
+      RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, L, 1.0, plan->zsum, nullptr, nullptr, st));
       RPCA_TRY(launch_center_cols(plan->H, L, m, L, plan->zsum, 1.0 / (double)m, plan->Q, L, st));
     }
     rpca_status s;
@@ -797,8 +801,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
 
   // Step 3: T = A~^T Q  (n x L, FP64 after the ordered split reduction)
   if (center) {
-    RPCA_TRY(launch_colsum(ST_F32, plan->Q32, L, m, L, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
-    RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, L, 1.0, plan->zsum, nullptr, nullptr, st));
+    RPCA_TRY(launch_colsum(ST_F32, plan->Q32, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
+    RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, L, 1.0, plan->zsum, nullptr, nullptr, st));
   }
   if (streamed) {
     RPCA_TRY(launch_fill_f64(plan->acc, (int64_t)L * plan->ldp, 0.0, st));
@@ -1092,8 +1096,8 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   for (int j = i; j >= 1; --j) {
     // X_bar_j = A~^T (a_j Z_j)
     if (center) {
-      RPCA_TRY(launch_colsum(ST_F32, b.Zin, l, m, l, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
-      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, l, 1.0, plan->zsum, nullptr, nullptr, st));
+      RPCA_TRY(launch_colsum(ST_F32, b.Zin, l, m, l, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, l, 1.0, plan->zsum, nullptr, nullptr, st));
     }
     AdjArgs aa;
     aa.A = A;
@@ -1242,8 +1246,8 @@ extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t ld
     RPCA_TRY(launch_gemm64(false, U, ldu, c, q, m, q, k, false, nullptr, dx, q, z, q, st, dx, q));
     // y = A~^T (D x) - V (S o (U^T D x))
     if (center) {
-      RPCA_TRY(launch_colsum(ST_F32, z, q, m, q, nullptr, 0, plan->rps_cs, plan->ns_cs, plan->csp, st));
-      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cs, q, 1.0, zsum, nullptr, nullptr, st));
+      RPCA_TRY(launch_colsum(ST_F32, z, q, m, q, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, q, 1.0, zsum, nullptr, nullptr, st));
     }
     AdjArgs aa;
     aa.A = Af;

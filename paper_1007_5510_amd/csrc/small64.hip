@@ -60,8 +60,114 @@ __global__ __launch_bounds__(256) void gram_kernel(const TX* __restrict__ X, int
     }
 }
 
+static size_t g_max_lds_gram();
+
+// ---------------------------------------------------------------- Gram on FP64 matrix cores
+// v_mfma_f64_16x16x4_f64: A operand lane i + 16 kk holds A[i][kk], B operand lane j + 16 kk holds
+// B[kk][j], D: lane j + 16 g, register v holds D[4 v + g][j] (rows interleaved by lane group,
+// unlike the float32 16x16x4 form).  For W = X^T X both operands are
+// 16-column slices of the same 4 rows of X.  One workgroup (8 waves) takes a split of rows and up
+// to GM_TILES upper-triangular 16 x 16 tiles (ta <= tb); grid.y walks groups of tiles when L is
+// large.  Rows are staged 16 at a time in LDS as float64 with a row stride of Lp doubles,
+// Lp = 16 (mod 32), so the 4 rows x 16 columns of an operand read hit distinct banks.  Each tile
+// is written to the split's partial W and mirrored (the reduction then sums full matrices).
+constexpr int GM_WAVES = 8;
+constexpr int GM_PER_WAVE = 10;
+constexpr int GM_TILES = GM_WAVES * GM_PER_WAVE;
+constexpr int GM_ROWS = 16;
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+static int gram_lp(int L) {
+  const int T = (L + 15) / 16;
+  const int lp = 16 * T;
+  return lp % 32 == 16 ? lp : lp + 16;
+}
+
+template <typename TX>
+__global__ __launch_bounds__(512) void gram_mfma_kernel(const TX* __restrict__ X, int64_t ldx, int64_t rows, int L,
+                                                        int Lp, int64_t rps, int T, int NT,
+                                                        double* __restrict__ part) {
+  extern __shared__ double gs[];  // [2][GM_ROWS][Lp]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int s = blockIdx.x;
+  const int grp = blockIdx.y;
+  const int64_t rb = (int64_t)s * rps;
+  const int64_t re = rb + rps < rows ? rb + rps : rows;
+  // this wave's tiles: t = grp * GM_TILES + q * GM_WAVES + wave, upper triangle in row-major order
+  int ta[GM_PER_WAVE], tb[GM_PER_WAVE];
+  bool ok[GM_PER_WAVE];
+#pragma unroll
+  for (int q = 0; q < GM_PER_WAVE; ++q) {
+    int t = grp * GM_TILES + q * GM_WAVES + wave;
+    ok[q] = t < NT;
+    int a = 0;
+    while (ok[q] && t >= T - a) {
+      t -= T - a;
+      ++a;
+    }
+    ta[q] = a;
+    tb[q] = a + t;
+  }
+  doublex4 acc[GM_PER_WAVE];
+#pragma unroll
+  for (int q = 0; q < GM_PER_WAVE; ++q) acc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
+  const int kr = lane >> 4, jc = lane & 15;
+  int buf = 0;
+  for (int64_t r0 = rb; r0 < re; r0 += GM_ROWS) {
+    double* xs = gs + buf * GM_ROWS * Lp;
+    for (int e = tid; e < GM_ROWS * Lp; e += 512) {
+      const int rr = e / Lp, cc = e % Lp;
+      const int64_t r = r0 + rr;
+      xs[e] = (r < re && cc < L) ? (double)X[r * ldx + cc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GM_ROWS / 4; ++kk) {
+      const double* row = xs + (4 * kk + kr) * Lp + jc;
+#pragma unroll
+      for (int q = 0; q < GM_PER_WAVE; ++q) {
+        if (ok[q]) {
+          const double a = row[16 * ta[q]];
+          const double b = row[16 * tb[q]];
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+        }
+      }
+    }
+    buf ^= 1;  // the other buffer is rewritten only after the next barrier
+  }
+  double* out = part + (int64_t)s * L * L;
+#pragma unroll
+  for (int q = 0; q < GM_PER_WAVE; ++q) {
+    if (!ok[q]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ta[q] + 4 * v + (lane >> 4);
+      const int j = 16 * tb[q] + (lane & 15);
+      if (i < L && j < L) {
+        out[(int64_t)i * L + j] = acc[q][v];
+        if (ta[q] != tb[q]) out[(int64_t)j * L + i] = acc[q][v];
+      }
+    }
+  }
+}
+
 hipError_t launch_gram(bool x_is_f64, const void* X, int64_t ldx, int64_t rows, int L, int64_t rows_per_split,
                        int nsplit, double* part, hipStream_t st) {
+  const int T = (L + 15) / 16;
+  const int NT = T * (T + 1) / 2;
+  const int Lp = gram_lp(L);
+  const size_t lds = sizeof(double) * 2 * GM_ROWS * (size_t)Lp;
+  if (lds <= g_max_lds_gram()) {
+    dim3 grid((unsigned)nsplit, (unsigned)((NT + GM_TILES - 1) / GM_TILES));
+    if (x_is_f64)
+      hipLaunchKernelGGL(gram_mfma_kernel<double>, grid, dim3(512), lds, st, (const double*)X, ldx, rows, L, Lp,
+                         rows_per_split, T, NT, part);
+    else
+      hipLaunchKernelGGL(gram_mfma_kernel<float>, grid, dim3(512), lds, st, (const float*)X, ldx, rows, L, Lp,
+                         rows_per_split, T, NT, part);
+    return hipGetLastError();
+  }
   const int tiles = (L + 63) / 64;
   dim3 grid((unsigned)(tiles * tiles), (unsigned)nsplit);
   if (x_is_f64)
@@ -176,6 +282,7 @@ __global__ __launch_bounds__(1024) void cholesky_kernel(double* __restrict__ W, 
 
 static size_t g_max_lds = 65536;  // per-workgroup LDS limit of the current device
 void set_max_lds(size_t bytes) { g_max_lds = bytes; }
+static size_t g_max_lds_gram() { return g_max_lds; }
 
 hipError_t launch_cholesky(double* W, int L, double rel_tol, int* flag, hipStream_t st) {
   const size_t bytes = ((size_t)L + (size_t)L * (L + 1) / 2) * sizeof(double);
