@@ -434,8 +434,12 @@ rpca_status cholqr_round(rpca_plan_s* plan, bool x_f64, const void* X, double* X
   hipStream_t st = plan->stream;
   RPCA_TRY(launch_gram(x_f64, X, L, m, L, plan->rps_g, plan->ns_g, plan->gp, st));
   RPCA_TRY(launch_gram_reduce(plan->gp, plan->ns_g, L, R, shift_coef, st));
-  RPCA_TRY(launch_cholesky(R, L, 1e-14, flag, st));
-  RPCA_TRY(launch_triinv(R, L, plan->Rinv, st));
+  if (cholinv_fits(L)) {
+    RPCA_TRY(launch_cholinv(R, L, 1e-14, flag, plan->Rinv, st));
+  } else {
+    RPCA_TRY(launch_cholesky(R, L, 1e-14, flag, st));
+    RPCA_TRY(launch_triinv(R, L, plan->Rinv, st));
+  }
   RPCA_TRY(launch_gemm64(x_f64, X, L, plan->Rinv, L, m, L, L, true, nullptr, Xout, L, Xout32, L, st));
   return RPCA_OK;
 }

@@ -329,6 +329,106 @@ __global__ __launch_bounds__(1024) void triinv_kernel(const double* __restrict__
   }
 }
 
+// ---------------------------------------------------------------- Cholesky and R^-1 in one workgroup
+// W (L x L symmetric, upper triangle read) = R^T R.  Each of the 1024 threads keeps up to E entries
+// (i <= j) of the upper triangle in registers, fixed at the start; step k publishes row k through
+// a double-buffered LDS row and every thread applies the rank-one update to its own entries with
+// i > k, using the unscaled pivot row (a_ij -= a_ki a_kj / p_k), so one barrier per step suffices;
+// rows are scaled by 1/sqrt(p_k) at the end.  A pivot that is not finite, not positive or below
+// rel_tol times the original diagonal sets *flag = k + 1 (first such k) and is replaced by 1.
+// Then R^-1 (upper) is formed by columns, thread j back-substituting column j against R held packed
+// in LDS (no barriers); its entries live in Rinv (each thread touches only its own column).
+template <int E, bool INV>
+__global__ __launch_bounds__(1024) void cholinv_kernel(double* __restrict__ W, int L, double rel_tol,
+                                                       int* __restrict__ flag, double* __restrict__ Rinv) {
+  extern __shared__ double cs[];
+  double* row = cs;              // [2][L]
+  double* piv = cs + 2 * L;      // [L]
+  double* dorig = cs + 3 * L;    // [L]
+  double* rp = cs + 4 * L;       // packed R (upper, row-major), L (L + 1) / 2
+  const int tid = threadIdx.x;
+  const int64_t NT = (int64_t)L * (L + 1) / 2;
+  double a[E];
+  int ij[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    int64_t e = tid + 1024 * (int64_t)q;
+    int i = 0;
+    if (e < NT) {
+      while (e >= L - i) {
+        e -= L - i;
+        ++i;
+      }
+      const int j = i + (int)e;
+      ij[q] = (i << 16) | j;
+      a[q] = W[(int64_t)i * L + j];
+    } else {
+      ij[q] = -1;
+      a[q] = 0.0;
+    }
+  }
+  for (int k = tid; k < L; k += 1024) dorig[k] = W[(int64_t)k * L + k];
+  for (int k = 0; k < L; ++k) {
+    double* rb = row + (k & 1) * L;
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+      if (ij[q] >= 0 && (ij[q] >> 16) == k) rb[ij[q] & 0xFFFF] = a[q];
+    __syncthreads();
+    double p = rb[k];
+    const bool ok = isfinite(p) && p > 0.0 && p > rel_tol * dorig[k];
+    if (!ok) p = 1.0;
+    if (tid == 0) {
+      piv[k] = p;
+      if (!ok) atomicCAS(flag, 0, k + 1);
+    }
+    const double ip = 1.0 / p;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if (ij[q] >= 0 && (ij[q] >> 16) > k) a[q] -= rb[ij[q] >> 16] * rb[ij[q] & 0xFFFF] * ip;
+    }
+  }
+  __syncthreads();
+  // R = D^-1/2 (unscaled rows); write R (lower triangle zero) and its packed copy
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    if (ij[q] < 0) continue;
+    const int i = ij[q] >> 16, j = ij[q] & 0xFFFF;
+    const double sq = sqrt(piv[i]);
+    const double r = (i == j) ? sq : a[q] / sq;
+    W[(int64_t)i * L + j] = r;
+    if (j > i) W[(int64_t)j * L + i] = 0.0;
+    if (INV) rp[(int64_t)i * L - (int64_t)i * (i - 1) / 2 + (j - i)] = r;
+  }
+  if (!INV) return;
+  __syncthreads();
+  for (int j = tid; j < L; j += 1024) {
+    double* x = Rinv + j;  // column j, stride L
+    for (int i = j + 1; i < L; ++i) x[(int64_t)i * L] = 0.0;
+    const double* rjj = rp + (int64_t)j * L - (int64_t)j * (j - 1) / 2;
+    x[(int64_t)j * L] = 1.0 / rjj[0];
+    for (int i = j - 1; i >= 0; --i) {
+      const double* ri = rp + (int64_t)i * L - (int64_t)i * (i - 1) / 2;  // ri[p - i] = R(i, p)
+      double s = 0.0;
+      for (int pp = i + 1; pp <= j; ++pp) s = fma(ri[pp - i], x[(int64_t)pp * L], s);
+      x[(int64_t)i * L] = -s / ri[0];
+    }
+  }
+}
+
+static size_t cholinv_lds(int L) { return sizeof(double) * (4 * (size_t)L + (size_t)L * (L + 1) / 2); }
+
+// the triangle must fit 16 entries per thread (L <= 180) and R packed must fit in LDS
+bool cholinv_fits(int L) { return (int64_t)L * (L + 1) / 2 <= 16 * 1024 && cholinv_lds(L) <= g_max_lds; }
+
+hipError_t launch_cholinv(double* W, int L, double rel_tol, int* flag, double* Rinv, hipStream_t st) {
+  if (!cholinv_fits(L)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((cholinv_kernel<16, false>), dim3(1), dim3(1024), cholinv_lds(L), st, W, L, rel_tol, flag,
+                     Rinv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_triinv(W, L, Rinv, st);
+}
+
 hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st) {
   hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(1024), (size_t)L * sizeof(double), st, R, L, Rinv);
   return hipGetLastError();
