@@ -1,18 +1,24 @@
 // Symmetric eigen-decomposition of the small Gram matrix M = T^T T (L x L,
 // float64) that gives the SVD of T in Step 4 (eq. svd_small3): M = W S~^2 W^T.
-// One workgroup does the whole job so that no grid-wide synchronisation or
-// chain of launches is needed:
+// Four launches on one stream:
 //
-//   1. Householder reduction to tridiagonal form, M = H T_d H^T (lower
-//      storage, reflectors kept in the zeroed part of M);
-//   2. every eigenvalue of T_d by bisection on Sturm counts, a few threads
-//      per eigenvalue evaluating several points per step;
-//   3. eigenvectors of T_d for the wanted (largest) eigenvalues by inverse
-//      iteration on the LU factors of T_d - lambda I with partial pivoting;
-//      eigenvalues closer than 1e-7 ||T_d|| are treated as a cluster and
-//      their vectors are orthogonalised against each other during the
-//      iteration;
-//   4. back-transformation W = H Y.
+//   1. tridiag_kernel (one workgroup): Householder reduction to tridiagonal
+//      form, M = H T_d H^T, on the packed lower triangle held in LDS (in
+//      global memory when it does not fit).  Per step the symmetric product
+//      p = tau A22 v takes 16 lanes per output entry, the rank-2 update one
+//      wave per column; the wave that updates the first trailing column
+//      builds the next reflector from its registers while the others finish
+//      the update, so a step costs two workgroup barriers.  The reflectors
+//      stay in the zeroed part of the packed matrix, which is written out.
+//   2. bisect_kernel: every eigenvalue of T_d by multisection on Sturm
+//      counts, one wave per eigenvalue evaluating 64 points per step.
+//   3. inviter_kernel: eigenvectors of T_d for the wanted (largest)
+//      eigenvalues by inverse iteration on the LU factors of T_d - lambda I
+//      with partial pivoting, one thread per eigenvector; eigenvalues closer
+//      than 1e-7 ||T_d|| form a cluster whose vectors the first member
+//      computes in turn, orthogonalising each against the earlier ones.
+//   4. backtrans_kernel: W = H Y, one wave per eigenvector, reflectors
+//      staged in LDS when they fit.
 //
 // The reduction is O(L^3) once, where a Jacobi method moves O(L^3) data per
 // sweep, and it is backward stable, so the eigenvalues have absolute error
@@ -24,30 +30,85 @@ namespace rpca {
 
 namespace {
 
-constexpr int EIG_THREADS = 1024;
+constexpr int TRD_THREADS = 1024;
+constexpr int TRD_WAVES = TRD_THREADS / 64;
+constexpr int BT_WAVES = 8;  // eigenvectors per back-transformation workgroup
+constexpr double EPS = 2.220446049250313e-16;
 
-// lower-triangular storage, column-major packed (column k holds rows k..L-1)
-// when PACKED, full row-major otherwise
-template <bool PACKED>
-struct LowAcc {
-  double* p;
-  int L;
-  RPCA_DEV double& at(int i, int k) const {  // requires i >= k
-    return PACKED ? p[(int64_t)k * L - (int64_t)k * (k - 1) / 2 + (i - k)] : p[(int64_t)i * L + k];
+// start of packed column k (column k holds rows k .. L-1 contiguously)
+RPCA_DEV int poff(int k, int L) { return k * L - (k * (k - 1)) / 2; }
+
+template <int CTRL>
+RPCA_DEV double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum over each group of 16 lanes (butterfly: xor 1, xor 2, half-row mirror,
+// row mirror); every lane of the group ends with the same bits
+RPCA_DEV double row_sum16(double x) {
+  x += dpp_f64<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141>(x);  // row_half_mirror
+  x += dpp_f64<0x140>(x);  // row_mirror
+  return x;
+}
+
+// all 64 lanes; every lane ends with the same bits
+RPCA_DEV double wave_sum64(double x) {
+  x = row_sum16(x);
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
+// Reflector of column jj from x[q] = A(jj + lane + 64 q, jj) (wave-wide):
+// H = I - tau v v^T with v(jj+1) = 1 maps the column below the diagonal to
+// beta e_1.  v is written to vs[jj+1 ..] and below the subdiagonal of the
+// packed column; tau to *tau_slot and taug[jj]; beta (or the unchanged
+// subdiagonal when the column is already reduced, tau = 0) to eg[jj].
+template <int NQ>
+RPCA_DEV void make_reflector(const double (&x)[NQ], int jj, int L, double* P, double* vs, double* tau_slot,
+                             double* __restrict__ eg, double* __restrict__ taug) {
+  const int lane = threadIdx.x & 63;
+  double xs = 0.0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = jj + lane + 64 * q;
+    if (i >= jj + 2 && i < L) xs = fma(x[q], x[q], xs);
   }
-  RPCA_DEV double sym(int i, int k) const { return i >= k ? at(i, k) : at(k, i); }
-};
-
-RPCA_DEV double block_reduce_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  const int nw = blockDim.x >> 6;
-  for (int q = 0; q < nw; ++q) s += red[q];
-  return s;  // every thread gets the same value
+  const double xnorm2 = wave_sum64(xs);
+  const double alpha = __shfl(x[0], 1, 64);
+  if (xnorm2 == 0.0) {  // uniform
+    if (lane == 0) {
+      *tau_slot = 0.0;
+      taug[jj] = 0.0;
+      eg[jj] = alpha;
+    }
+    return;
+  }
+  const double beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+  const double tj = (beta - alpha) / beta;
+  const double scal = 1.0 / (alpha - beta);
+  const int o = poff(jj, L) - jj;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = jj + lane + 64 * q;
+    if (i == jj + 1) {
+      vs[i] = 1.0;
+    } else if (i >= jj + 2 && i < L) {
+      const double vi = x[q] * scal;
+      vs[i] = vi;
+      P[o + i] = vi;
+    }
+  }
+  if (lane == 0) {
+    *tau_slot = tj;
+    taug[jj] = tj;
+    eg[jj] = beta;
+  }
 }
 
 // number of eigenvalues of the tridiagonal (d, e2 = e^2) smaller than x
@@ -75,291 +136,379 @@ RPCA_DEV double start_entry(int i, int r) {
   return ((double)(h >> 8) + 0.5) * (2.0 / 16777216.0) - 1.0;
 }
 
-}  // namespace
+// Scratch layout (doubles): packed reflectors, d, e, tau, ascending
+// eigenvalues, two scalars (||T_d||, pivmin), then per-eigenvector arrays
+// with entry i of vector r at [i * kk + r] (eigenvectors Y, then the five
+// LU arrays of the inverse iteration).
+struct EigWork {
+  double *P, *d, *e, *tau, *lam, *scal, *Y, *iw;
+};
 
-// work: global scratch of at least L*L + kk*6*L doubles (full-storage
-// reduction area and per-vector inverse-iteration arrays).
-template <bool PACKED>
-__global__ __launch_bounds__(EIG_THREADS) void syev_small_kernel(const double* __restrict__ M, int L, int kk,
-                                                                 double* __restrict__ work,
-                                                                 double* __restrict__ lam_desc,
-                                                                 double* __restrict__ sig_desc,
-                                                                 double* __restrict__ W, int ldw) {
+size_t packed_size(int L) { return ((size_t)L * (L + 1) / 2 + 7) / 8 * 8; }
+
+EigWork eig_layout(double* work, int L, int kk) {
+  EigWork w;
+  w.P = work;
+  w.d = work + packed_size(L);
+  w.e = w.d + L;
+  w.tau = w.e + L;
+  w.lam = w.tau + L;
+  w.scal = w.lam + L;
+  w.Y = w.scal + 8;
+  w.iw = w.Y + (size_t)L * kk;
+  return w;
+}
+
+// ---- 1. Householder tridiagonalisation, one workgroup
+// NQ >= ceil(L / 64) rows per lane for a whole column.
+template <bool IN_LDS, int NQ>
+__global__ __launch_bounds__(TRD_THREADS) void tridiag_kernel(const double* __restrict__ M, int L,
+                                                              double* __restrict__ gP, double* __restrict__ dg,
+                                                              double* __restrict__ eg, double* __restrict__ taug) {
   extern __shared__ double smem[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  double* red = smem;          // 32
-  double* d = smem + 32;       // L
-  double* e = d + L;           // L
-  double* tau = e + L;         // L
-  double* vw = tau + L;        // 2L: v (Householder vector) and p/w
-  double* lstore = vw + 2 * L; // packed lower M when PACKED
-  LowAcc<PACKED> a{PACKED ? lstore : work, L};
-  double* Y = work + (PACKED ? 0 : (int64_t)L * L);  // L x kk column-major (vector c at Y + c*L)
-  double* iw = Y + (int64_t)L * kk;                   // kk x 5L inverse-iteration work
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* red = smem;        // per-wave partial sums
+  double* tauS = smem + 16;  // tau of the pending reflector, by step parity
+  double* vS = smem + 32;    // two reflector vectors, by step parity
+  double* p = vS + 2 * L;    // tau A22 v
+  double* P = IN_LDS ? p + L : gP;
+  const int np = L * (L + 1) / 2;
 
-  // load the lower triangle
-  for (int64_t t = tid; t < (int64_t)L * L; t += nt) {
-    const int i = (int)(t / L), k = (int)(t % L);
-    if (i >= k) a.at(i, k) = M[t];
+  // packed lower triangle A(i, k), i >= k, read as row k of the symmetric M
+  for (int k = wave; k < L; k += TRD_WAVES) {
+    const int o = poff(k, L) - k;
+    for (int i = k + lane; i < L; i += 64) P[o + i] = M[(int64_t)k * L + i];
   }
   __syncthreads();
-
-  // ---- 1. tridiagonalisation (Householder from the left and right, lower)
-  double* v = vw;
-  double* pw = vw + L;
+  if (L >= 3 && wave == 0) {
+    double x[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      x[q] = i < L ? P[i] : 0.0;
+    }
+    make_reflector<NQ>(x, 0, L, P, vS, tauS, eg, taug);
+  }
   for (int j = 0; j + 2 < L; ++j) {
-    const int r0 = j + 1;  // first row of the trailing block
-    const int nr = L - r0;
-    double xs = 0.0;
-    for (int i = r0 + 1 + tid; i < L; i += nt) {
-      const double x = a.at(i, j);
-      xs = fma(x, x, xs);
-    }
-    const double xnorm2 = block_reduce_sum(xs, red);
-    const double alpha = a.at(r0, j);
-    if (xnorm2 == 0.0) {  // column already reduced: H_j = I
-      if (tid == 0) {
-        tau[j] = 0.0;
-        e[j] = alpha;
+    __syncthreads();  // reflector j and the update of step j-1 are complete
+    const int slot = j & 1;
+    const double tj = tauS[slot];
+    const double* v = vS + slot * L;
+    const int r0 = j + 1, nr = L - r0;
+    const bool next = j + 3 < L;  // reflector j+1 is still needed
+    if (tj != 0.0) {
+      // p[t] = tj sum_c A(t, c) v[c] over c >= r0; 16 lanes per t
+      const int g = lane >> 4, u0 = lane & 15;
+      double ptv = 0.0;
+      for (int tb = r0 + 4 * wave; tb < L; tb += 4 * TRD_WAVES) {
+        const int t = tb + g;
+        double s = 0.0;
+        if (t < L) {
+          const int ot = poff(t, L) - t;
+          for (int u = u0; u < nr; u += 16) {
+            const int c = r0 + u;
+            const double a = c <= t ? P[poff(c, L) + t - c] : P[ot + c];
+            s = fma(a, v[c], s);
+          }
+        }
+        s = row_sum16(s);
+        if (u0 == 0 && t < L) {
+          const double pt = tj * s;
+          p[t] = pt;
+          ptv = fma(pt, v[t], ptv);
+        }
       }
+      ptv = wave_sum64(ptv);
+      if (lane == 0) red[wave] = ptv;
       __syncthreads();
-      continue;
-    }
-    const double beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-    const double tj = (beta - alpha) / beta;
-    const double scal = 1.0 / (alpha - beta);
-    for (int i = r0 + tid; i < L; i += nt) {
-      const double vi = (i == r0) ? 1.0 : a.at(i, j) * scal;
-      v[i] = vi;
-      if (i > r0) a.at(i, j) = vi;  // reflector kept below the subdiagonal
-    }
-    if (tid == 0) {
-      tau[j] = tj;
-      e[j] = beta;
-    }
-    __syncthreads();
-    // p = tau A22 v, several threads per row, partial sums combined in-wave
-    int tpr = 1;
-    while (tpr * 2 * nr <= nt && tpr < 64) tpr *= 2;
-    {
-      const int row = r0 + tid / tpr, part = tid % tpr;
-      double s = 0.0;
-      if (tid / tpr < nr) {
-        for (int k = r0 + part; k < L; k += tpr) s = fma(a.sym(row, k), v[k], s);
+      double tot = 0.0;
+#pragma unroll
+      for (int q = 0; q < TRD_WAVES; ++q) tot += red[q];
+      const double kdot = 0.5 * tj * tot;
+      // A22 -= v w^T + w v^T with w = p - kdot v; one wave per column
+      for (int k = r0 + wave; k < L; k += TRD_WAVES) {
+        const int ok = poff(k, L) - k;
+        const double vk = v[k], wk = p[k] - kdot * vk;
+        if (next && k == r0) {  // first trailing column: keep it and build reflector j+1
+          double x[NQ];
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const int i = k + lane + 64 * q;
+            x[q] = 0.0;
+            if (i < L) {
+              const double vi = v[i], wi = p[i] - kdot * vi;
+              x[q] = P[ok + i] - (vi * wk + wi * vk);
+              P[ok + i] = x[q];
+            }
+          }
+          make_reflector<NQ>(x, r0, L, P, vS + (slot ^ 1) * L, tauS + (slot ^ 1), eg, taug);
+        } else {
+          for (int i = k + lane; i < L; i += 64) {
+            const double vi = v[i], wi = p[i] - kdot * vi;
+            P[ok + i] -= vi * wk + wi * vk;
+          }
+        }
       }
-      for (int o = tpr / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-      if (tid / tpr < nr && part == 0) pw[row] = tj * s;
+    } else if (next && wave == 0) {  // no update: reflector j+1 from the stored column
+      double x[NQ];
+      const int o = poff(r0, L) - r0;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int i = r0 + lane + 64 * q;
+        x[q] = i < L ? P[o + i] : 0.0;
+      }
+      make_reflector<NQ>(x, r0, L, P, vS + (slot ^ 1) * L, tauS + (slot ^ 1), eg, taug);
     }
-    __syncthreads();
-    double ps = 0.0;
-    for (int i = r0 + tid; i < L; i += nt) ps = fma(pw[i], v[i], ps);
-    const double kdot = 0.5 * tj * block_reduce_sum(ps, red);
-    for (int i = r0 + tid; i < L; i += nt) pw[i] -= kdot * v[i];
-    __syncthreads();
-    // A22 -= v w^T + w v^T (lower part)
-    const int64_t tot = (int64_t)nr * nr;
-    for (int64_t t = tid; t < tot; t += nt) {
-      const int i = r0 + (int)(t / nr), k = r0 + (int)(t % nr);
-      if (i >= k) a.at(i, k) -= v[i] * pw[k] + pw[i] * v[k];
-    }
-    __syncthreads();
   }
-  for (int j = tid; j < L; j += nt) {
-    d[j] = a.at(j, j);
-    if (j + 2 >= L) tau[j] = 0.0;
-  }
-  if (tid == 0 && L >= 2) e[L - 2] = a.at(L - 1, L - 2);
   __syncthreads();
+  for (int i = tid; i < L; i += TRD_THREADS) dg[i] = P[poff(i, L)];
+  if (tid == 0) {
+    if (L >= 2) {
+      eg[L - 2] = P[poff(L - 2, L) + 1];
+      taug[L - 2] = 0.0;
+    }
+    eg[L - 1] = 0.0;
+    taug[L - 1] = 0.0;
+  }
+  if (IN_LDS)
+    for (int t = tid; t < np; t += TRD_THREADS) gP[t] = P[t];
+}
 
-  // ---- 2. eigenvalues by multisection: G threads per eigenvalue
-  double* e2 = pw;  // reuse: e^2
-  for (int i = tid; i + 1 < L; i += nt) e2[i] = e[i] * e[i];
-  double* lam = v;  // ascending eigenvalues
+// ---- 2. multisection, one wave per eigenvalue (ascending index idx)
+__global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ dg, const double* __restrict__ eg,
+                                                     int L, double* __restrict__ lam, double* __restrict__ lam_desc,
+                                                     double* __restrict__ sig_desc, double* __restrict__ scal) {
+  extern __shared__ double smem[];
+  double* d = smem;
+  double* ea = smem + L;  // |e|, ea[L-1] = 0
+  double* e2 = ea + L;    // e^2
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    d[i] = dg[i];
+    const double ei = i + 1 < L ? eg[i] : 0.0;
+    ea[i] = fabs(ei);
+    e2[i] = ei * ei;
+  }
   __syncthreads();
-  double gl = 0.0, gu = 0.0, emax2 = 0.0;
-  for (int i = 0; i < L; ++i) {
-    const double off = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < L ? fabs(e[i]) : 0.0);
-    gl = i == 0 ? d[i] - off : fmin(gl, d[i] - off);
-    gu = i == 0 ? d[i] + off : fmax(gu, d[i] + off);
-    if (i + 1 < L) emax2 = fmax(emax2, e2[i]);
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (idx >= L) return;
+  // Gershgorin interval
+  double gl = __builtin_inf(), gu = -__builtin_inf(), emax2 = 0.0;
+  for (int i = lane; i < L; i += 64) {
+    const double off = (i > 0 ? ea[i - 1] : 0.0) + ea[i];
+    gl = fmin(gl, d[i] - off);
+    gu = fmax(gu, d[i] + off);
+    emax2 = fmax(emax2, e2[i]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    gl = fmin(gl, __shfl_xor(gl, o, 64));
+    gu = fmax(gu, __shfl_xor(gu, o, 64));
+    emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
   }
   const double tnorm = fmax(fabs(gl), fabs(gu));
   const double pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   // the reduction is accurate to O(u ||T_d||) in absolute terms: bisect to that
-  const double atol = 2.220446049250313e-16 * tnorm + 2.0 * pivmin;
-  {
-    int G = 1;
-    while (G * 2 * L <= nt && G < 16) G *= 2;
-    const int idx = tid / G, part = tid % G;
-    // every eigenvalue index gets a group; bisection loop is uniform inside a group
-    const bool active = idx < L;
-    double lo = gl - 2.2e-16 * tnorm - atol, hi = gu + 2.2e-16 * tnorm + atol;
-    for (int it = 0; it < 200; ++it) {
-      const double width = hi - lo;
-      const double tolr = 2.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + atol;
-      // the group's lanes are consecutive in one wave; all take the same decision
-      const bool done = !active || width <= tolr;
-      const uint64_t ballot = __ballot(!done);
-      if (ballot == 0) break;
-      double x = lo + width * (double)(part + 1) / (double)(G + 1);
-      int cnt = active ? sturm_count(d, e2, L, x, pivmin) : 0;
-      // number of group points whose count is <= idx: the eigenvalue lies right of them
-      int below = (cnt <= idx) ? 1 : 0;
-      for (int o = G / 2; o > 0; o >>= 1) below += __shfl_xor(below, o, 64);
-      if (!done) {
-        const double nlo = lo + width * (double)below / (double)(G + 1);
-        const double nhi = lo + width * (double)(below + 1) / (double)(G + 1);
-        lo = below == 0 ? lo : nlo;
-        hi = below == G ? hi : nhi;
-      }
+  const double atol = EPS * tnorm + 2.0 * pivmin;
+  double lo = gl - 2.2e-16 * tnorm - atol, hi = gu + 2.2e-16 * tnorm + atol;
+  for (int it = 0; it < 200; ++it) {
+    const double width = hi - lo;
+    const double tolr = 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + atol;
+    if (width <= tolr) break;  // lo, hi are the same in every lane
+    const double x = lo + width * (double)(lane + 1) / 65.0;
+    const int cnt = sturm_count(d, e2, L, x, pivmin);
+    // points with at most idx eigenvalues below them lie left of eigenvalue idx
+    const int below = __popcll(__ballot(cnt <= idx));
+    const double nlo = lo + width * (double)below / 65.0;
+    const double nhi = lo + width * (double)(below + 1) / 65.0;
+    lo = below == 0 ? lo : nlo;
+    hi = below == 64 ? hi : nhi;
+  }
+  if (lane == 0) {
+    const double lm = 0.5 * (lo + hi);
+    lam[idx] = lm;
+    lam_desc[L - 1 - idx] = lm;
+    sig_desc[L - 1 - idx] = sqrt(fmax(lm, 0.0));
+    if (idx == 0) {
+      scal[0] = tnorm;
+      scal[1] = pivmin;
     }
-    if (active && part == 0) lam[idx] = 0.5 * (lo + hi);
   }
-  __syncthreads();
-  for (int r = tid; r < L; r += nt) {
-    lam_desc[r] = lam[L - 1 - r];
-    sig_desc[r] = sqrt(fmax(lam[L - 1 - r], 0.0));
-  }
+}
 
-  // ---- 3. inverse iteration for the kk largest eigenvalues (one thread each;
-  // a cluster of close eigenvalues is handled by its first member, sequentially)
+// ---- 3. inverse iteration, one thread per wanted eigenvector r (descending)
+__global__ __launch_bounds__(64) void inviter_kernel(const double* __restrict__ dg, const double* __restrict__ eg,
+                                                     const double* __restrict__ lam, const double* __restrict__ scal,
+                                                     int L, int kk, double* __restrict__ Y, double* __restrict__ iw) {
+  const int r = blockIdx.x * 64 + threadIdx.x;
+  if (r >= kk) return;
+  const double tnorm = scal[0], pivmin = scal[1];
   const double ctol = 1e-7 * fmax(tnorm, 1e-300);
-  for (int r = tid; r < kk; r += nt) {
-    // skip if r belongs to a cluster that started at r-1
-    const int ia = L - 1 - r;
-    if (r > 0 && fabs(lam[ia + 1] - lam[ia]) <= ctol) continue;
-    int cend = r;
-    while (cend + 1 < kk && fabs(lam[L - 1 - cend] - lam[L - 2 - cend]) <= ctol) ++cend;
-    for (int rr = r; rr <= cend; ++rr) {
-      double* y = Y + (int64_t)rr * L;
-      double* dl = iw + (int64_t)rr * 5 * L;  // sub-diagonal multipliers
-      double* u0 = dl + L;                    // diagonal of U
-      double* u1 = u0 + L;                    // first super-diagonal of U
-      double* u2 = u1 + L;                    // second super-diagonal (fill-in)
-      double* pv = u2 + L;                    // pivot flags
-      // perturb inside a cluster so the shifted matrices differ
-      const double lambda = lam[L - 1 - rr] + (double)(rr - r) * 4.0 * 2.220446049250313e-16 * tnorm;
-      // LU of T_d - lambda I with partial pivoting (rows i, i+1)
-      double diag = d[0] - lambda, sup = L > 1 ? e[0] : 0.0, sup2 = 0.0;
+  const int ia = L - 1 - r;
+  if (r > 0 && fabs(lam[ia + 1] - lam[ia]) <= ctol) return;  // computed by the cluster's first member
+  int cend = r;
+  while (cend + 1 < kk && fabs(lam[L - 1 - cend] - lam[L - 2 - cend]) <= ctol) ++cend;
+  const int64_t S = kk;
+  const int64_t LS = (int64_t)L * kk;
+  double* dl = iw;        // multipliers
+  double* u1 = iw + LS;   // first super-diagonal of U
+  double* u2 = u1 + LS;   // second super-diagonal (fill-in)
+  double* ru0 = u2 + LS;  // 1 / diagonal of U
+  double* pv = ru0 + LS;  // pivot flags
+  const double tiny = EPS * tnorm + pivmin;
+  for (int rr = r; rr <= cend; ++rr) {
+    // perturb inside a cluster so the shifted matrices differ
+    const double lambda = lam[L - 1 - rr] + (double)(rr - r) * 4.0 * EPS * tnorm;
+    // LU of T_d - lambda I with partial pivoting (rows i, i+1)
+    double diag = dg[0] - lambda, sup = L > 1 ? eg[0] : 0.0;
+    for (int i = 0; i < L - 1; ++i) {
+      const double sub = eg[i];
+      const double nd = dg[i + 1] - lambda;
+      const double nsup = (i + 2 < L) ? eg[i + 1] : 0.0;
+      double mlt, u0v, u1v, u2v, pvv;
+      if (fabs(diag) >= fabs(sub)) {  // no swap
+        mlt = diag != 0.0 ? sub / diag : 0.0;
+        pvv = 0.0;
+        u0v = diag;
+        u1v = sup;
+        u2v = 0.0;
+        diag = nd - mlt * sup;
+        sup = nsup;
+      } else {  // swap rows i and i+1
+        mlt = diag / sub;
+        pvv = 1.0;
+        u0v = sub;
+        u1v = nd;
+        u2v = nsup;
+        diag = sup - mlt * nd;
+        sup = -mlt * nsup;
+      }
+      if (u0v == 0.0) u0v = tiny;
+      dl[i * S + rr] = mlt;
+      pv[i * S + rr] = pvv;
+      ru0[i * S + rr] = 1.0 / u0v;
+      u1[i * S + rr] = u1v;
+      u2[i * S + rr] = u2v;
+    }
+    ru0[(L - 1) * S + rr] = 1.0 / (diag != 0.0 ? diag : tiny);
+    u1[(L - 1) * S + rr] = 0.0;
+    u2[(L - 1) * S + rr] = 0.0;
+    if (L >= 2) u2[(L - 2) * S + rr] = 0.0;
+    for (int i = 0; i < L; ++i) Y[i * S + rr] = start_entry(i, rr);
+    for (int iter = 0; iter < 3; ++iter) {
+      // forward: the row swaps and multipliers, the running entry in a register
+      double cur = Y[rr];
+#pragma unroll 4
       for (int i = 0; i < L - 1; ++i) {
-        const double sub = e[i];
-        const double nd = d[i + 1] - lambda;
-        const double nsup = (i + 2 < L) ? e[i + 1] : 0.0;
-        if (fabs(diag) >= fabs(sub)) {  // no swap
-          const double mlt = diag != 0.0 ? sub / diag : 0.0;
-          dl[i] = mlt;
-          pv[i] = 0.0;
-          u0[i] = diag;
-          u1[i] = sup;
-          u2[i] = sup2;
-          diag = nd - mlt * sup;
-          sup = nsup;
-          sup2 = 0.0;
-        } else {  // swap rows i and i+1
-          const double mlt = diag / sub;
-          dl[i] = mlt;
-          pv[i] = 1.0;
-          u0[i] = sub;
-          u1[i] = nd;
-          u2[i] = nsup;
-          diag = sup - mlt * nd;
-          sup = -mlt * nsup;
-          sup2 = 0.0;
-        }
-        if (u0[i] == 0.0) u0[i] = 2.220446049250313e-16 * tnorm + pivmin;
+        const double nxt = Y[(i + 1) * S + rr];
+        const bool sw = pv[i * S + rr] != 0.0;
+        const double a = sw ? nxt : cur, b = sw ? cur : nxt;
+        Y[i * S + rr] = a;
+        cur = b - dl[i * S + rr] * a;
       }
-      u0[L - 1] = diag != 0.0 ? diag : 2.220446049250313e-16 * tnorm + pivmin;
-      u1[L - 1] = 0.0;
-      u2[L - 1] = 0.0;
-      if (L >= 2) u2[L - 2] = 0.0;
-      for (int i = 0; i < L; ++i) y[i] = start_entry(i, rr);
-      for (int iter = 0; iter < 3; ++iter) {
-        // forward: apply the row swaps and multipliers
-        for (int i = 0; i < L - 1; ++i) {
-          if (pv[i] != 0.0) {
-            const double t = y[i];
-            y[i] = y[i + 1];
-            y[i + 1] = t;
-          }
-          y[i + 1] -= dl[i] * y[i];
-        }
-        // backward substitution with U (three diagonals)
-        for (int i = L - 1; i >= 0; --i) {
-          double s = y[i];
-          if (i + 1 < L) s -= u1[i] * y[i + 1];
-          if (i + 2 < L) s -= u2[i] * y[i + 2];
-          y[i] = s / u0[i];
-        }
-        // orthogonalise against the earlier members of the cluster
-        for (int q = r; q < rr; ++q) {
-          const double* yq = Y + (int64_t)q * L;
-          double dot = 0.0;
-          for (int i = 0; i < L; ++i) dot = fma(yq[i], y[i], dot);
-          for (int i = 0; i < L; ++i) y[i] -= dot * yq[i];
-        }
-        double nrm = 0.0;
-        for (int i = 0; i < L; ++i) nrm = fma(y[i], y[i], nrm);
-        const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-        for (int i = 0; i < L; ++i) y[i] *= inv;
+      Y[(L - 1) * S + rr] = cur;
+      // backward substitution with U (three diagonals)
+      double y1 = 0.0, y2 = 0.0;
+#pragma unroll 4
+      for (int i = L - 1; i >= 0; --i) {
+        const double s = (Y[i * S + rr] - u1[i * S + rr] * y1 - u2[i * S + rr] * y2) * ru0[i * S + rr];
+        Y[i * S + rr] = s;
+        y2 = y1;
+        y1 = s;
       }
+      // orthogonalise against the earlier members of the cluster
+      for (int q = r; q < rr; ++q) {
+        double dot = 0.0;
+        for (int i = 0; i < L; ++i) dot = fma(Y[i * S + q], Y[i * S + rr], dot);
+        for (int i = 0; i < L; ++i) Y[i * S + rr] -= dot * Y[i * S + q];
+      }
+      double nrm = 0.0;
+      for (int i = 0; i < L; ++i) nrm = fma(Y[i * S + rr], Y[i * S + rr], nrm);
+      const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = 0; i < L; ++i) Y[i * S + rr] *= inv;
     }
   }
-  __syncthreads();
-  __threadfence_block();
+}
 
-  // ---- 4. back-transformation Y <- H_0 ... H_{L-3} Y (reflectors applied last-first)
-  double* dots = pw;  // kk values
+// ---- 4. W[:, c] = H_0 ... H_{L-3} Y[:, c], one wave per eigenvector
+template <bool IN_LDS, int NQ>
+__global__ __launch_bounds__(64 * BT_WAVES) void backtrans_kernel(const double* __restrict__ gP,
+                                                                  const double* __restrict__ taug, int L, int kk,
+                                                                  const double* __restrict__ Y,
+                                                                  double* __restrict__ W, int ldw) {
+  extern __shared__ double smem[];
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * BT_WAVES + (threadIdx.x >> 6);
+  if (IN_LDS) {
+    const int np = L * (L + 1) / 2;
+    for (int t = threadIdx.x; t < np; t += blockDim.x) smem[t] = gP[t];
+    __syncthreads();
+  }
+  const double* P = IN_LDS ? smem : gP;
+  if (c >= kk) return;
+  double y[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    y[q] = i < L ? Y[(int64_t)i * kk + c] : 0.0;
+  }
   for (int j = L - 3; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;  // uniform
-    const int r0 = j + 1;
-    // dots[c] = v^T Y[r0:, c]; a group of threads per column
-    int tpc = 1;
-    while (tpc * 2 * kk <= nt && tpc < 64) tpc *= 2;
-    {
-      const int c = tid / tpc, part = tid % tpc;
-      double s = 0.0;
-      if (c < kk) {
-        const double* y = Y + (int64_t)c * L;
-        for (int i = r0 + part; i < L; i += tpc) s = fma(i == r0 ? 1.0 : a.at(i, j), y[i], s);
-      }
-      for (int o = tpc / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-      if (c < kk && part == 0) dots[c] = tj * s;
+    const double tj = taug[j];
+    if (tj == 0.0) continue;
+    const int o = poff(j, L) - j;
+    double vv[NQ];
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + 64 * q;
+      vv[q] = i == j + 1 ? 1.0 : ((i > j + 1 && i < L) ? P[o + i] : 0.0);
+      s = fma(vv[q], y[q], s);
     }
-    __syncthreads();
-    const int nr = L - r0;
-    for (int64_t t = tid; t < (int64_t)kk * nr; t += nt) {
-      const int c = (int)(t / nr), i = r0 + (int)(t % nr);
-      const double vi = i == r0 ? 1.0 : a.at(i, j);
-      Y[(int64_t)c * L + i] -= dots[c] * vi;
-    }
-    __syncthreads();
+    s = tj * wave_sum64(s);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) y[q] -= s * vv[q];
   }
-  // W row-major: W[i][c] = Y[c][i]
-  for (int64_t t = tid; t < (int64_t)L * kk; t += nt) {
-    const int i = (int)(t / kk), c = (int)(t % kk);
-    W[(int64_t)i * ldw + c] = Y[(int64_t)c * L + i];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + 64 * q;
+    if (i < L) W[(int64_t)i * ldw + c] = y[q];
   }
 }
 
-size_t syev_small_lds(int L, bool packed) {
-  size_t base = (32 + 5 * (size_t)L) * sizeof(double);
-  if (packed) base += (size_t)L * (L + 1) / 2 * sizeof(double);
-  return base;
-}
+}  // namespace
 
-size_t syev_small_work(int L, int kk) { return (size_t)L * L + (size_t)kk * 6 * L + 64; }
+size_t syev_small_work(int L, int kk) { return packed_size(L) + 4 * (size_t)L + 8 + 6 * (size_t)L * kk + 64; }
 
 hipError_t launch_syev_small(const double* M, int L, int kk, double* work, double* lam_desc, double* sig_desc,
                              double* W, int ldw, size_t max_lds, hipStream_t st) {
-  if (L < 1 || kk < 1 || kk > L) return hipErrorInvalidValue;
-  const size_t packed = syev_small_lds(L, true);
-  if (packed <= max_lds)
-    hipLaunchKernelGGL(syev_small_kernel<true>, dim3(1), dim3(EIG_THREADS), packed, st, M, L, kk, work, lam_desc,
-                       sig_desc, W, ldw);
+  if (L < 1 || L > 1024 || kk < 1 || kk > L || ldw < kk) return hipErrorInvalidValue;
+  const EigWork w = eig_layout(work, L, kk);
+  const size_t np = (size_t)L * (L + 1) / 2;
+  const size_t trd_lds = (32 + 3 * (size_t)L + np) * sizeof(double);
+  if (L <= 256 && trd_lds <= max_lds)
+    hipLaunchKernelGGL((tridiag_kernel<true, 4>), dim3(1), dim3(TRD_THREADS), trd_lds, st, M, L, w.P, w.d, w.e,
+                       w.tau);
   else
-    hipLaunchKernelGGL(syev_small_kernel<false>, dim3(1), dim3(EIG_THREADS), syev_small_lds(L, false), st, M, L, kk,
-                       work, lam_desc, sig_desc, W, ldw);
+    hipLaunchKernelGGL((tridiag_kernel<false, 16>), dim3(1), dim3(TRD_THREADS), (32 + 3 * (size_t)L) * sizeof(double),
+                       st, M, L, w.P, w.d, w.e, w.tau);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bisect_kernel, dim3((unsigned)((L + 3) / 4)), dim3(256), 3 * (size_t)L * sizeof(double), st, w.d,
+                     w.e, L, w.lam, lam_desc, sig_desc, w.scal);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)((kk + 63) / 64)), dim3(64), 0, st, w.d, w.e, w.lam, w.scal, L,
+                     kk, w.Y, w.iw);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 bt_grid((unsigned)((kk + BT_WAVES - 1) / BT_WAVES)), bt_block(64 * BT_WAVES);
+  if (L <= 256 && np * sizeof(double) <= max_lds)
+    hipLaunchKernelGGL((backtrans_kernel<true, 4>), bt_grid, bt_block, np * sizeof(double), st, w.P, w.tau, L, kk,
+                       w.Y, W, ldw);
+  else if (L <= 256)
+    hipLaunchKernelGGL((backtrans_kernel<false, 4>), bt_grid, bt_block, 0, st, w.P, w.tau, L, kk, w.Y, W, ldw);
+  else
+    hipLaunchKernelGGL((backtrans_kernel<false, 16>), bt_grid, bt_block, 0, st, w.P, w.tau, L, kk, w.Y, W, ldw);
   return hipGetLastError();
 }
 
