@@ -10,25 +10,37 @@
 namespace rpca {
 
 // ---------------------------------------------------------------- column sums
+// part[s][c] = sum of X[r][c] over the rows r of split s.  A block takes 64
+// columns (one per lane) and its four waves take every fourth row, eight
+// rows in flight per lane; the wave sums are combined in a fixed order.
 template <int ST>
 __global__ __launch_bounds__(256) void colsum_kernel(const void* __restrict__ X, int64_t ld, int64_t rows,
                                                      int64_t cols, const float* __restrict__ cs, int64_t plane,
                                                      int64_t rps, double* __restrict__ part) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
   const int s = blockIdx.y;
-  if (c >= cols) return;
   const int64_t r0 = (int64_t)s * rps;
   const int64_t r1 = r0 + rps < rows ? r0 + rps : rows;
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  int64_t r = r0;
-  for (; r + 3 < r1; r += 4) {
-    acc0 += (double)load_elem<ST>(X, r * ld + c, plane);
-    acc1 += (double)load_elem<ST>(X, (r + 1) * ld + c, plane);
-    acc2 += (double)load_elem<ST>(X, (r + 2) * ld + c, plane);
-    acc3 += (double)load_elem<ST>(X, (r + 3) * ld + c, plane);
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  if (c < cols) {
+    int64_t r = r0 + w;
+    for (; r + 28 < r1; r += 32) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = load_elem<ST>(X, (r + 4 * u) * ld + c, plane);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] += (double)v[u];
+    }
+    for (; r < r1; r += 4) acc[0] += (double)load_elem<ST>(X, r * ld + c, plane);
   }
-  for (; r < r1; ++r) acc0 += (double)load_elem<ST>(X, r * ld + c, plane);
-  double tot = (acc0 + acc1) + (acc2 + acc3);
+  sh[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (w != 0 || c >= cols) return;
+  double tot = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
   if (ST == ST_FP8) tot *= (double)cs[c];
   part[(int64_t)s * cols + c] = tot;
 }
@@ -36,7 +48,7 @@ __global__ __launch_bounds__(256) void colsum_kernel(const void* __restrict__ X,
 hipError_t launch_colsum(int storage, const void* X, int64_t ld, int64_t rows, int64_t cols,
                          const float* col_scale, int64_t plane, int64_t rows_per_split, int nsplit,
                          double* part, hipStream_t st) {
-  dim3 grid((unsigned)((cols + 255) / 256), (unsigned)nsplit);
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)nsplit);
   switch (storage) {
     case ST_F32:
       hipLaunchKernelGGL(colsum_kernel<ST_F32>, grid, dim3(256), 0, st, X, ld, rows, cols, col_scale, plane,

@@ -23,11 +23,11 @@
 // sum unchanged.
 //
 // Accuracy: each float32 accumulation chain is limited to 64 MFMA K-steps and
-// then folded into an outer accumulator (float64 in the forward product,
-// a second float32 level in the adjoint, whose split partial sums are then
-// reduced in float64), so the rounding of long sums (n = 20000 in the
-// forward product, thousands of rows per split in the adjoint) grows with
-// the square root of the number of folds rather than of the chain length.
+// then folded into a second float32 level, whose split partial sums are
+// reduced in float64, so the rounding of long sums (thousands of K terms per
+// split) grows with the square root of the number of folds rather than of the
+// chain length.  A float outer level keeps the forward kernel within 128
+// registers (four workgroups per CU).
 //
 // Out-of-range rows and columns are clamped to valid addresses instead of
 // masked: their lanes compute values that the epilogue never stores, which
@@ -76,16 +76,22 @@ RPCA_DEV floatx16 mfma32(float a, float b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int F3_KST = 32;           // K per LDS stage
-constexpr int F3_XP = F3_KST + 4;    // padded LDS row (floats)
+constexpr int F3_KST = 32;  // K per LDS stage of the launched configuration
 
-template <int NT2, bool VEC>
-__global__ __launch_bounds__(256, 2) void fwd32_kernel(
+// KST: K per LDS stage (32 or 64); NCH: independent accumulation chains per
+// output tile (consecutive MFMAs of one tile alternate between them); OT:
+// type of the outer accumulator (double, or float for fewer registers);
+// MINB: workgroups per CU the register budget is sized for
+template <int NT2, bool VEC, int KST = F3_KST, int NCH = 1, class OT = float, int MINB = 4>
+__global__ __launch_bounds__(256, MINB) void fwd32_kernel(
     const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
     const float* __restrict__ Xt, int64_t ldx, int ncols, int64_t kchunk, const float* __restrict__ corr,
     const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz, int64_t split_stride, int direct) {
-  __shared__ float Xs[2][64][F3_XP];
-  __shared__ float Ss[2][F3_KST];
+  constexpr int XP = KST + 4;   // padded LDS row (floats)
+  constexpr int XV = KST / 16;  // float4 of X per thread per stage
+  constexpr int SV = KST / 4;   // float4 of the shift per stage
+  __shared__ float Xs[2][64][XP];
+  __shared__ float Ss[2][KST];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, kh = lane >> 5;
@@ -96,18 +102,19 @@ __global__ __launch_bounds__(256, 2) void fwd32_kernel(
   const int64_t kend = kbeg + kchunk < n ? kbeg + kchunk : n;
   const int64_t row = r0 + li;
   const float* __restrict__ arow = A + (row < m ? row : m - 1) * lda;
-  // cooperative stage loader: thread -> (X row xc, 8-float slice xq)
+  // cooperative stage loader: thread -> (X row xc, KST/4-float slice xq)
   const int xc = tid >> 2, xq = tid & 3;
   const float* __restrict__ xsrc = Xt + (int64_t)(c0 + xc < ncols ? c0 + xc : ncols - 1) * ldx;
 
-  floatx16 acc[NT2];
-  double accd[NT2][16];
+  floatx16 acc[NCH][NT2];
+  OT accd[NT2][16];
 #pragma unroll
   for (int t = 0; t < NT2; ++t) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      acc[t][v] = 0.f;
-      accd[t][v] = 0.0;
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) acc[ch][t][v] = 0.f;
+      accd[t][v] = (OT)0;
     }
   }
   auto fold = [&]() {
@@ -115,34 +122,37 @@ __global__ __launch_bounds__(256, 2) void fwd32_kernel(
     for (int t = 0; t < NT2; ++t) {
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        accd[t][v] += (double)acc[t][v];
-        acc[t][v] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+          accd[t][v] += (OT)acc[ch][t][v];
+          acc[ch][t][v] = 0.f;
+        }
       }
     }
   };
   struct AStage {
-    floatx4 a[F3_KST / 8];
+    floatx4 a[KST / 8];
   };
   struct XStage {
-    floatx4 x0, x1, s;
+    floatx4 x[XV], s;
   };
   auto load_a = [&](AStage& b, int64_t kb) {
 #pragma unroll
-    for (int q = 0; q < F3_KST / 8; ++q) b.a[q] = ld4<VEC>(arow + kb + 8 * q + 4 * kh);
+    for (int q = 0; q < KST / 8; ++q) b.a[q] = ld4<VEC>(arow + kb + 8 * q + 4 * kh);
   };
   auto load_x = [&](XStage& b, int64_t kb) {
-    b.x0 = ld4<true>(xsrc + kb + 8 * xq);
-    b.x1 = ld4<true>(xsrc + kb + 8 * xq + 4);
-    b.s = ld4<true>(shift + kb + 4 * (tid & 7));
+#pragma unroll
+    for (int v = 0; v < XV; ++v) b.x[v] = ld4<true>(xsrc + kb + (KST / 4) * xq + 4 * v);
+    b.s = ld4<true>(shift + kb + 4 * (tid & (SV - 1)));
   };
   auto store_x = [&](const XStage& b, int buf) {
-    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq]) = b.x0;
-    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq + 4]) = b.x1;
-    if (tid < 8) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = b.s;
+#pragma unroll
+    for (int v = 0; v < XV; ++v) *reinterpret_cast<floatx4*>(&Xs[buf][xc][(KST / 4) * xq + 4 * v]) = b.x[v];
+    if (tid < SV) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = b.s;
   };
   auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
-    for (int q = 0; q < F3_KST / 8; ++q) {
+    for (int q = 0; q < KST / 8; ++q) {
       const floatx4 sv = *reinterpret_cast<const floatx4*>(&Ss[buf][8 * q + 4 * kh]);
       const floatx4 a = b.a[q] - sv;
       floatx4 x[NT2];
@@ -151,13 +161,13 @@ __global__ __launch_bounds__(256, 2) void fwd32_kernel(
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
 #pragma unroll
-        for (int t = 0; t < NT2; ++t) acc[t] = mfma32(a[e], x[t][e], acc[t]);
+        for (int t = 0; t < NT2; ++t) acc[e % NCH][t] = mfma32(a[e], x[t][e], acc[e % NCH][t]);
       }
     }
   };
 
   // whole stages: straight-line body, the prefetch after the last one re-reads it
-  const int64_t nfull = (kend - kbeg) / F3_KST;
+  const int64_t nfull = (kend - kbeg) / KST;
   int it = 0;
   if (nfull > 0) {
     AStage ac, an;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(256, 2) void fwd32_kernel(
     store_x(xr, 0);
     __syncthreads();
     for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * F3_KST;
+      const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * KST;
       load_x(xr, kn);
       load_a(an, kn);
       __builtin_amdgcn_sched_barrier(0);
@@ -175,25 +185,25 @@ __global__ __launch_bounds__(256, 2) void fwd32_kernel(
       store_x(xr, (int)((st + 1) & 1));
       __syncthreads();
       ac = an;
-      if (++it == 4) {  // fold every 4 stages (64 MFMA K-steps)
+      if (++it == 128 / KST) {  // fold every 64 MFMA K-steps
         it = 0;
         fold();
       }
     }
   }
-  // tail stage (fewer than F3_KST columns left): masked loads
-  const int64_t kt = kbeg + nfull * F3_KST;
+  // tail stage (fewer than KST columns left): masked loads
+  const int64_t kt = kbeg + nfull * KST;
   if (kt < kend) {
     AStage at;
 #pragma unroll
-    for (int q = 0; q < F3_KST / 8; ++q) at.a[q] = ld4_masked(arow, kt + 8 * q + 4 * kh, kend);
+    for (int q = 0; q < KST / 8; ++q) at.a[q] = ld4_masked(arow, kt + 8 * q + 4 * kh, kend);
     const int buf = (int)(nfull & 1);
-    const floatx4 x0 = ld4_masked(xsrc, kt + 8 * xq, kend);
-    const floatx4 x1 = ld4_masked(xsrc, kt + 8 * xq + 4, kend);
-    const floatx4 sv = ld4_masked(shift, kt + 4 * (tid & 7), kend);
-    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq]) = x0;
-    *reinterpret_cast<floatx4*>(&Xs[buf][xc][8 * xq + 4]) = x1;
-    if (tid < 8) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = sv;
+#pragma unroll
+    for (int v = 0; v < XV; ++v)
+      *reinterpret_cast<floatx4*>(&Xs[buf][xc][(KST / 4) * xq + 4 * v]) =
+          ld4_masked(xsrc, kt + (KST / 4) * xq + 4 * v, kend);
+    const floatx4 sv = ld4_masked(shift, kt + 4 * (tid & (SV - 1)), kend);
+    if (tid < SV) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = sv;
     __syncthreads();
     compute(at, buf);
   }
@@ -246,16 +256,19 @@ RPCA_DEV int64_t xcd_remap(int64_t b, int64_t total) {
   return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
 }
 
-constexpr int ADJ_RS = 16;  // rows of A per LDS stage of the adjoint kernel
+constexpr int ADJ_RS = 16;  // rows of A per LDS stage of the launched configuration
 
-template <int NT, bool VEC>
-__global__ __launch_bounds__(256, 2) void adj_f32_kernel(
+// RS: rows of A per LDS stage (16 or 32); MINB: workgroups per CU the
+// register budget is sized for
+template <int NT, bool VEC, int RS = ADJ_RS, int MINB = 2>
+__global__ __launch_bounds__(256, MINB) void adj_f32_kernel(
     const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
     const float* __restrict__ Z, int64_t ldz, int ncols, int64_t rows_per_split, int nsplit,
     int jtiles, int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride, int ones) {
   // Z rows staged per block, interleaved so that lane (p, kk) finds its NT
   // B-operand values (columns p, 16+p, 32+p, 48+p) in one 16-byte word.
-  __shared__ float Zs[2][ADJ_RS][16][4];
+  constexpr int ZQ = RS / 4;  // Z elements per thread per stage
+  __shared__ float Zs[2][RS][16][4];
   const int64_t total = (int64_t)jtiles * ctiles * nsplit;
   const int64_t logical = xcd_remap(blockIdx.x, total);
   const int jt = (int)(logical % jtiles);
@@ -275,13 +288,13 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
   const int64_t rbeg = (int64_t)sp * rows_per_split;
   const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
   const floatx4 sh = VEC ? ld4<true>(shift + clc) : ld4_masked(shift, cl, n);
-  // cooperative Z loader: 4 elements per thread per stage, element e = tid + 256 q
+  // cooperative Z loader: ZQ elements per thread per stage, element e = tid + 256 q
   // -> row e / 64, column e % 64 (clamped to the last real column)
   // with `ones`, column ncols of Z is an implicit column of ones (its product is the column sums)
-  int zcol[4], zrow[4], zslot[4];
-  bool zone[4];
+  int zcol[ZQ], zrow[ZQ], zslot[ZQ];
+  bool zone[ZQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < ZQ; ++q) {
     const int e = tid + 256 * q;
     const int cc = e & 63;
     zrow[q] = e >> 6;
@@ -308,30 +321,30 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
       }
   };
   struct AStage {
-    floatx4 a[ADJ_RS / 4];
+    floatx4 a[RS / 4];
   };
   struct ZStage {
-    float z[4];
+    float z[ZQ];
   };
   auto load_a = [&](AStage& b, int64_t rb) {
 #pragma unroll
-    for (int q = 0; q < ADJ_RS / 4; ++q) {
+    for (int q = 0; q < RS / 4; ++q) {
       const float* arow = A + (rb + 4 * q + kk) * lda;
       b.a[q] = VEC ? ld4<true>(arow + clc) : ld4_masked(arow, cl, n);
     }
   };
   auto load_z = [&](ZStage& b, int64_t rb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) b.z[q] = zone[q] ? 1.f : Z[(rb + zrow[q]) * ldz + zcol[q]];
+    for (int q = 0; q < ZQ; ++q) b.z[q] = zone[q] ? 1.f : Z[(rb + zrow[q]) * ldz + zcol[q]];
   };
   auto store_z = [&](const ZStage& b, int buf) {
     float* base = &Zs[buf][0][0][0];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) base[zrow[q] * 64 + zslot[q]] = b.z[q];
+    for (int q = 0; q < ZQ; ++q) base[zrow[q] * 64 + zslot[q]] = b.z[q];
   };
   auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
-    for (int q = 0; q < ADJ_RS / 4; ++q) {
+    for (int q = 0; q < RS / 4; ++q) {
       const floatx4 zz = *reinterpret_cast<const floatx4*>(&Zs[buf][4 * q + kk][p][0]);
       const floatx4 a = b.a[q] - sh;
 #pragma unroll
@@ -342,7 +355,7 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
     }
   };
 
-  const int64_t nfull = (rend - rbeg) / ADJ_RS;
+  const int64_t nfull = (rend - rbeg) / RS;
   int it = 0;
   if (nfull > 0) {
     AStage ac, an;
@@ -352,7 +365,7 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
     store_z(zr, 0);
     __syncthreads();
     for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t rn = rbeg + (st + 1 < nfull ? st + 1 : st) * ADJ_RS;
+      const int64_t rn = rbeg + (st + 1 < nfull ? st + 1 : st) * RS;
       load_z(zr, rn);
       load_a(an, rn);
       __builtin_amdgcn_sched_barrier(0);
@@ -360,25 +373,25 @@ __global__ __launch_bounds__(256, 2) void adj_f32_kernel(
       store_z(zr, (int)((st + 1) & 1));
       __syncthreads();
       ac = an;
-      if (++it == 16) {  // fold every 16 stages (64 MFMA K-steps, 256 rows)
+      if (++it == 256 / RS) {  // fold every 64 MFMA K-steps (256 rows)
         it = 0;
         fold();
       }
     }
   }
   // tail rows (fewer than a stage): masked by row, zeros beyond rend
-  const int64_t rt = rbeg + nfull * ADJ_RS;
+  const int64_t rt = rbeg + nfull * RS;
   if (rt < rend) {
     const int buf = (int)(nfull & 1);
     float* base = &Zs[buf][0][0][0];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ZQ; ++q) {
       const int64_t r = rt + zrow[q];
       base[zrow[q] * 64 + zslot[q]] = r < rend ? (zone[q] ? 1.f : Z[r * ldz + zcol[q]]) : 0.f;
     }
     AStage at;
 #pragma unroll
-    for (int q = 0; q < ADJ_RS / 4; ++q) {
+    for (int q = 0; q < RS / 4; ++q) {
       const int64_t r = rt + 4 * q + kk;
       at.a[q] = floatx4{0.f, 0.f, 0.f, 0.f};
       if (r < rend) {

@@ -418,9 +418,216 @@ __global__ __launch_bounds__(1024) void cholinv_kernel(double* __restrict__ W, i
 static size_t cholinv_lds(int L) { return sizeof(double) * (4 * (size_t)L + (size_t)L * (L + 1) / 2); }
 
 // the triangle must fit 16 entries per thread (L <= 180) and R packed must fit in LDS
-bool cholinv_fits(int L) { return (int64_t)L * (L + 1) / 2 <= 16 * 1024 && cholinv_lds(L) <= g_max_lds; }
+// ---------------------------------------------------------------- blocked
+// Cholesky and triangular inverse in LDS for L <= 192, by 16 x 16 blocks on
+// FP64 matrix cores (v_mfma_f64_16x16x4f64).  The matrix is padded to
+// Lp = 16 ceil(L / 16) with an identity block, which leaves the leading
+// L x L factor and inverse unchanged, and kept as its packed upper triangle
+// (row i holds columns i .. Lp-1).
+//   Cholesky W = R^T R (right-looking, block column k): the diagonal block is
+//   factored by one wave, column c of the block in the registers of lane c;
+//   the block row R_kj = R_kk^-T W_kj by forward substitution, one thread per
+//   column; the trailing upper blocks W_jl -= R_kj^T R_kl with MFMAs.  A
+//   pivot at or below rel_tol times the original diagonal entry is breakdown
+//   (flag = first bad column + 1) and is replaced by a unit pivot.
+//   Inverse X = R^-1 (left to right, block column j): X_jj = R_jj^-1 by back
+//   substitution in one wave; Y_k = R_kj X_jj, then X_ij = -sum_{k>=i} X_ik Y_k
+//   for i < j, both with MFMAs, the results held in registers until every
+//   wave has read its operands, then written in place.
+// W (L x L, row-major) receives R with zeros below the diagonal (CHOL) or is
+// read as R (inverse only); Rinv receives R^-1 with zeros below.
+// f64 16x16x4 operands: lane m + 16 k holds A[m][k] and B[k][m]; D: lane
+// n + 16 g, register v holds D[4 v + g][n].
+constexpr int CB = 16;
+
+static int blk_lp(int L) { return (L + CB - 1) / CB * CB; }
+
+static size_t chol_blk_lds(int L) {
+  const size_t lp = (size_t)blk_lp(L);
+  return sizeof(double) * (lp * (lp + 1) / 2 + (size_t)L + CB * CB + CB + 8);
+}
+
+bool chol_blk_fits(int L) { return L >= 1 && blk_lp(L) <= 192 && chol_blk_lds(L) <= g_max_lds; }
+
+template <bool CHOL>
+__global__ __launch_bounds__(1024) void chol_blk_kernel(double* __restrict__ W, int L, double rel_tol,
+                                                        int* __restrict__ flag, double* __restrict__ Rinv) {
+  extern __shared__ double smem[];
+  const int Lp = (L + CB - 1) / CB * CB, NB = Lp / CB;
+  const int64_t np = (int64_t)Lp * (Lp + 1) / 2;
+  double* P = smem;         // packed upper, np
+  double* d0 = P + np;      // L original diagonal entries
+  double* Tm = d0 + L;      // 16 x 16 diagonal-block inverse, row-major
+  double* rinv = Tm + CB * CB;  // 1 / R(t, t) of the current diagonal block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  auto off = [&](int i) { return i * Lp - (i * (i - 1)) / 2; };
+  auto at = [&](int i, int j) -> double& { return P[off(i) + j - i]; };  // j >= i
+
+  for (int i = wave; i < Lp; i += 16)
+    for (int j = i + lane; j < Lp; j += 64) at(i, j) = (i < L && j < L) ? W[(int64_t)i * L + j] : (i == j ? 1.0 : 0.0);
+  if (CHOL)
+    for (int i = tid; i < L; i += 1024) d0[i] = W[(int64_t)i * L + i];
+  __syncthreads();
+
+  if (CHOL) {
+    for (int kb = 0; kb < NB; ++kb) {
+      const int k0 = kb * CB;
+      if (wave == 0) {  // diagonal block: lane c holds column c
+        const int c = c16;
+        double w[CB];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) w[t] = t <= c ? at(k0 + t, k0 + c) : 0.0;
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          double p = __shfl(w[t], t, 64);
+          const int col = k0 + t;
+          const bool ok = col >= L || (isfinite(p) && p > 0.0 && p > rel_tol * d0[col]);
+          if (!ok) {
+            p = 1.0;
+            if (lane == 0) atomicCAS(flag, 0, col + 1);
+          }
+          const double r = sqrt(p), ir = 1.0 / r;
+          if (c == t) w[t] = r;
+          else if (c > t) w[t] *= ir;
+#pragma unroll
+          for (int u = t + 1; u < CB; ++u) {
+            const double rtu = __shfl(w[t], u, 64);
+            if (c >= u) w[u] -= rtu * w[t];
+          }
+        }
+        if (lane < CB) {
+#pragma unroll
+          for (int t = 0; t < CB; ++t) {
+            if (t <= c) at(k0 + t, k0 + c) = w[t];
+            if (t == c) rinv[t] = 1.0 / w[t];
+          }
+        }
+      }
+      __syncthreads();
+      // block row: R_kj = R_kk^-T W_kj, one thread per column
+      const int c = k0 + CB + tid;
+      if (c < Lp) {
+        double x[CB];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) x[t] = at(k0 + t, c);
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          double sacc = x[t];
+#pragma unroll
+          for (int q = 0; q < t; ++q) sacc -= at(k0 + q, k0 + t) * x[q];
+          x[t] = sacc * rinv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < CB; ++t) at(k0 + t, c) = x[t];
+      }
+      __syncthreads();
+      // trailing upper blocks (jb, lb), kb < jb <= lb
+      const int nrem = NB - kb - 1;
+      const int ntile = nrem * (nrem + 1) / 2;
+      for (int q = wave; q < ntile; q += 16) {
+        int rem = q, jb = kb + 1;
+        while (rem >= NB - jb) {
+          rem -= NB - jb;
+          ++jb;
+        }
+        const int lb = jb + rem;
+        const int j0 = jb * CB, l0 = lb * CB;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double a = at(k0 + 4 * s + g, j0 + c16);
+          const double b = at(k0 + 4 * s + g, l0 + c16);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = j0 + 4 * v + g, col = l0 + c16;
+          if (jb < lb || col >= row) at(row, col) -= acc[v];
+        }
+      }
+      __syncthreads();
+    }
+    for (int i = wave; i < L; i += 16)
+      for (int j = lane; j < L; j += 64) W[(int64_t)i * L + j] = j >= i ? at(i, j) : 0.0;
+  }
+
+  for (int jb = 0; jb < NB; ++jb) {
+    const int j0 = jb * CB;
+    if (wave == 0) {  // X_jj = R_jj^-1, lane c computes column c
+      const int c = c16;
+      double x[CB];
+#pragma unroll
+      for (int i = CB - 1; i >= 0; --i) {
+        const double rii = at(j0 + i, j0 + i);
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = i + 1; q < CB; ++q) sacc += at(j0 + i, j0 + q) * x[q];
+        x[i] = i > c ? 0.0 : (i == c ? 1.0 / rii : -sacc / rii);
+      }
+      if (lane < CB) {
+#pragma unroll
+        for (int i = 0; i < CB; ++i) Tm[i * CB + c] = x[i];
+      }
+    }
+    __syncthreads();
+    // Y_w = R_wj X_jj for block rows w < jb
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (wave < jb) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double a = at(CB * wave + c16, j0 + 4 * s + g);
+        const double b = Tm[(4 * s + g) * CB + c16];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    if (wave < jb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) at(CB * wave + 4 * v + g, j0 + c16) = acc[v];
+    }
+    __syncthreads();
+    // X_ij = -sum_{k = i}^{jb-1} X_ik Y_k for block rows i < jb
+    acc = doublex4{0.0, 0.0, 0.0, 0.0};
+    if (wave < jb) {
+      const int row = CB * wave + c16;
+      for (int kb = wave; kb < jb; ++kb) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int col = CB * kb + 4 * s + g;
+          const double a = col >= row ? at(row, col) : 0.0;
+          const double b = at(CB * kb + 4 * s + g, j0 + c16);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    if (wave < jb) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) at(CB * wave + 4 * v + g, j0 + c16) = -acc[v];
+    }
+    if (wave == 15) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, r = e >> 4, cc = e & 15;
+        if (cc >= r) at(j0 + r, j0 + cc) = Tm[e];
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = wave; i < L; i += 16)
+    for (int j = lane; j < L; j += 64) Rinv[(int64_t)i * L + j] = j >= i ? at(i, j) : 0.0;
+}
+
+bool cholinv_fits(int L) {
+  return chol_blk_fits(L) || ((int64_t)L * (L + 1) / 2 <= 16 * 1024 && cholinv_lds(L) <= g_max_lds);
+}
 
 hipError_t launch_cholinv(double* W, int L, double rel_tol, int* flag, double* Rinv, hipStream_t st) {
+  if (chol_blk_fits(L)) {
+    hipLaunchKernelGGL((chol_blk_kernel<true>), dim3(1), dim3(1024), chol_blk_lds(L), st, W, L, rel_tol, flag, Rinv);
+    return hipGetLastError();
+  }
   if (!cholinv_fits(L)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((cholinv_kernel<16, false>), dim3(1), dim3(1024), cholinv_lds(L), st, W, L, rel_tol, flag,
                      Rinv);
@@ -430,6 +637,11 @@ hipError_t launch_cholinv(double* W, int L, double rel_tol, int* flag, double* R
 }
 
 hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st) {
+  if (chol_blk_fits(L)) {
+    hipLaunchKernelGGL((chol_blk_kernel<false>), dim3(1), dim3(1024), chol_blk_lds(L), st, const_cast<double*>(R), L,
+                       0.0, nullptr, Rinv);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(1024), (size_t)L * sizeof(double), st, R, L, Rinv);
   return hipGetLastError();
 }

@@ -14,9 +14,10 @@
 //      counts, one wave per eigenvalue evaluating 64 points per step.
 //   3. inviter_kernel: eigenvectors of T_d for the wanted (largest)
 //      eigenvalues by inverse iteration on the LU factors of T_d - lambda I
-//      with partial pivoting, one thread per eigenvector; eigenvalues closer
-//      than 1e-7 ||T_d|| form a cluster whose vectors the first member
-//      computes in turn, orthogonalising each against the earlier ones.
+//      with partial pivoting, one thread per eigenvector with its arrays in
+//      LDS; eigenvalues closer than 1e-7 ||T_d|| form a cluster whose vectors
+//      the first member computes in turn, orthogonalising each against the
+//      earlier ones.
 //   4. backtrans_kernel: W = H Y, one wave per eigenvector, reflectors
 //      staged in LDS when they fit.
 //
@@ -137,11 +138,10 @@ RPCA_DEV double start_entry(int i, int r) {
 }
 
 // Scratch layout (doubles): packed reflectors, d, e, tau, ascending
-// eigenvalues, two scalars (||T_d||, pivmin), then per-eigenvector arrays
-// with entry i of vector r at [i * kk + r] (eigenvectors Y, then the five
-// LU arrays of the inverse iteration).
+// eigenvalues, two scalars (||T_d||, pivmin), then the eigenvectors of T_d
+// with entry i of vector r at [i * kk + r].
 struct EigWork {
-  double *P, *d, *e, *tau, *lam, *scal, *Y, *iw;
+  double *P, *d, *e, *tau, *lam, *scal, *Y;
 };
 
 size_t packed_size(int L) { return ((size_t)L * (L + 1) / 2 + 7) / 8 * 8; }
@@ -155,7 +155,6 @@ EigWork eig_layout(double* work, int L, int kk) {
   w.lam = w.tau + L;
   w.scal = w.lam + L;
   w.Y = w.scal + 8;
-  w.iw = w.Y + (size_t)L * kk;
   return w;
 }
 
@@ -336,11 +335,23 @@ __global__ __launch_bounds__(256) void bisect_kernel(const double* __restrict__ 
   }
 }
 
-// ---- 3. inverse iteration, one thread per wanted eigenvector r (descending)
+// ---- 3. inverse iteration, one thread per wanted eigenvector r (descending).
+// A workgroup of tpb threads keeps d, e and, per thread, the LU factors and
+// the iterate in LDS (entry i of array a of thread t at [(a L + i) tpb + t]),
+// so the sequential sweeps run at LDS latency.
 __global__ __launch_bounds__(64) void inviter_kernel(const double* __restrict__ dg, const double* __restrict__ eg,
                                                      const double* __restrict__ lam, const double* __restrict__ scal,
-                                                     int L, int kk, double* __restrict__ Y, double* __restrict__ iw) {
-  const int r = blockIdx.x * 64 + threadIdx.x;
+                                                     int L, int kk, double* __restrict__ Y) {
+  extern __shared__ double smem[];
+  double* d = smem;
+  double* e = smem + L;  // e[L-1] = 0
+  for (int i = threadIdx.x; i < L; i += blockDim.x) {
+    d[i] = dg[i];
+    e[i] = eg[i];
+  }
+  __syncthreads();
+  const int tpb = blockDim.x, t = threadIdx.x;
+  const int r = blockIdx.x * tpb + t;
   if (r >= kk) return;
   const double tnorm = scal[0], pivmin = scal[1];
   const double ctol = 1e-7 * fmax(tnorm, 1e-300);
@@ -348,23 +359,24 @@ __global__ __launch_bounds__(64) void inviter_kernel(const double* __restrict__ 
   if (r > 0 && fabs(lam[ia + 1] - lam[ia]) <= ctol) return;  // computed by the cluster's first member
   int cend = r;
   while (cend + 1 < kk && fabs(lam[L - 1 - cend] - lam[L - 2 - cend]) <= ctol) ++cend;
-  const int64_t S = kk;
-  const int64_t LS = (int64_t)L * kk;
-  double* dl = iw;        // multipliers
-  double* u1 = iw + LS;   // first super-diagonal of U
-  double* u2 = u1 + LS;   // second super-diagonal (fill-in)
-  double* ru0 = u2 + LS;  // 1 / diagonal of U
-  double* pv = ru0 + LS;  // pivot flags
+  double* base = smem + 2 * L + t;
+  const int64_t LT = (int64_t)L * tpb;
+  double* dl = base;           // multipliers
+  double* u1 = base + LT;      // first super-diagonal of U
+  double* u2 = base + 2 * LT;  // second super-diagonal (fill-in)
+  double* ru0 = base + 3 * LT; // 1 / diagonal of U
+  double* pv = base + 4 * LT;  // pivot flags
+  double* y = base + 5 * LT;   // iterate
   const double tiny = EPS * tnorm + pivmin;
   for (int rr = r; rr <= cend; ++rr) {
     // perturb inside a cluster so the shifted matrices differ
     const double lambda = lam[L - 1 - rr] + (double)(rr - r) * 4.0 * EPS * tnorm;
     // LU of T_d - lambda I with partial pivoting (rows i, i+1)
-    double diag = dg[0] - lambda, sup = L > 1 ? eg[0] : 0.0;
+    double diag = d[0] - lambda, sup = L > 1 ? e[0] : 0.0;
     for (int i = 0; i < L - 1; ++i) {
-      const double sub = eg[i];
-      const double nd = dg[i + 1] - lambda;
-      const double nsup = (i + 2 < L) ? eg[i + 1] : 0.0;
+      const double sub = e[i];
+      const double nd = d[i + 1] - lambda;
+      const double nsup = e[i + 1];
       double mlt, u0v, u1v, u2v, pvv;
       if (fabs(diag) >= fabs(sub)) {  // no swap
         mlt = diag != 0.0 ? sub / diag : 0.0;
@@ -384,49 +396,50 @@ __global__ __launch_bounds__(64) void inviter_kernel(const double* __restrict__ 
         sup = -mlt * nsup;
       }
       if (u0v == 0.0) u0v = tiny;
-      dl[i * S + rr] = mlt;
-      pv[i * S + rr] = pvv;
-      ru0[i * S + rr] = 1.0 / u0v;
-      u1[i * S + rr] = u1v;
-      u2[i * S + rr] = u2v;
+      dl[i * tpb] = mlt;
+      pv[i * tpb] = pvv;
+      ru0[i * tpb] = 1.0 / u0v;
+      u1[i * tpb] = u1v;
+      u2[i * tpb] = u2v;
     }
-    ru0[(L - 1) * S + rr] = 1.0 / (diag != 0.0 ? diag : tiny);
-    u1[(L - 1) * S + rr] = 0.0;
-    u2[(L - 1) * S + rr] = 0.0;
-    if (L >= 2) u2[(L - 2) * S + rr] = 0.0;
-    for (int i = 0; i < L; ++i) Y[i * S + rr] = start_entry(i, rr);
+    ru0[(L - 1) * tpb] = 1.0 / (diag != 0.0 ? diag : tiny);
+    u1[(L - 1) * tpb] = 0.0;
+    u2[(L - 1) * tpb] = 0.0;
+    if (L >= 2) u2[(L - 2) * tpb] = 0.0;
+    for (int i = 0; i < L; ++i) y[i * tpb] = start_entry(i, rr);
     for (int iter = 0; iter < 3; ++iter) {
       // forward: the row swaps and multipliers, the running entry in a register
-      double cur = Y[rr];
+      double cur = y[0];
 #pragma unroll 4
       for (int i = 0; i < L - 1; ++i) {
-        const double nxt = Y[(i + 1) * S + rr];
-        const bool sw = pv[i * S + rr] != 0.0;
+        const double nxt = y[(i + 1) * tpb];
+        const bool sw = pv[i * tpb] != 0.0;
         const double a = sw ? nxt : cur, b = sw ? cur : nxt;
-        Y[i * S + rr] = a;
-        cur = b - dl[i * S + rr] * a;
+        y[i * tpb] = a;
+        cur = b - dl[i * tpb] * a;
       }
-      Y[(L - 1) * S + rr] = cur;
+      y[(L - 1) * tpb] = cur;
       // backward substitution with U (three diagonals)
       double y1 = 0.0, y2 = 0.0;
 #pragma unroll 4
       for (int i = L - 1; i >= 0; --i) {
-        const double s = (Y[i * S + rr] - u1[i * S + rr] * y1 - u2[i * S + rr] * y2) * ru0[i * S + rr];
-        Y[i * S + rr] = s;
+        const double s = (y[i * tpb] - u1[i * tpb] * y1 - u2[i * tpb] * y2) * ru0[i * tpb];
+        y[i * tpb] = s;
         y2 = y1;
         y1 = s;
       }
-      // orthogonalise against the earlier members of the cluster
+      // orthogonalise against the earlier members of the cluster (already in Y)
       for (int q = r; q < rr; ++q) {
         double dot = 0.0;
-        for (int i = 0; i < L; ++i) dot = fma(Y[i * S + q], Y[i * S + rr], dot);
-        for (int i = 0; i < L; ++i) Y[i * S + rr] -= dot * Y[i * S + q];
+        for (int i = 0; i < L; ++i) dot = fma(Y[(int64_t)i * kk + q], y[i * tpb], dot);
+        for (int i = 0; i < L; ++i) y[i * tpb] -= dot * Y[(int64_t)i * kk + q];
       }
       double nrm = 0.0;
-      for (int i = 0; i < L; ++i) nrm = fma(Y[i * S + rr], Y[i * S + rr], nrm);
+      for (int i = 0; i < L; ++i) nrm = fma(y[i * tpb], y[i * tpb], nrm);
       const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
-      for (int i = 0; i < L; ++i) Y[i * S + rr] *= inv;
+      for (int i = 0; i < L; ++i) y[i * tpb] *= inv;
     }
+    for (int i = 0; i < L; ++i) Y[(int64_t)i * kk + rr] = y[i * tpb];
   }
 }
 
@@ -477,7 +490,7 @@ __global__ __launch_bounds__(64 * BT_WAVES) void backtrans_kernel(const double* 
 
 }  // namespace
 
-size_t syev_small_work(int L, int kk) { return packed_size(L) + 4 * (size_t)L + 8 + 6 * (size_t)L * kk + 64; }
+size_t syev_small_work(int L, int kk) { return packed_size(L) + 4 * (size_t)L + 8 + (size_t)L * kk + 64; }
 
 hipError_t launch_syev_small(const double* M, int L, int kk, double* work, double* lam_desc, double* sig_desc,
                              double* W, int ldw, size_t max_lds, hipStream_t st) {
@@ -497,8 +510,12 @@ hipError_t launch_syev_small(const double* M, int L, int kk, double* work, doubl
                      w.e, L, w.lam, lam_desc, sig_desc, w.scal);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)((kk + 63) / 64)), dim3(64), 0, st, w.d, w.e, w.lam, w.scal, L,
-                     kk, w.Y, w.iw);
+  // threads per inverse-iteration workgroup: as many as fit 6 L doubles each in LDS (at most 64)
+  const int64_t tpb_fit = ((int64_t)(max_lds / sizeof(double)) - 2 * L) / (6 * (int64_t)L);
+  if (tpb_fit < 1) return hipErrorInvalidValue;
+  const int tpb = (int)(tpb_fit < 64 ? tpb_fit : 64);
+  hipLaunchKernelGGL(inviter_kernel, dim3((unsigned)((kk + tpb - 1) / tpb)), dim3(tpb),
+                     (2 * (size_t)L + 6 * (size_t)L * tpb) * sizeof(double), st, w.d, w.e, w.lam, w.scal, L, kk, w.Y);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const dim3 bt_grid((unsigned)((kk + BT_WAVES - 1) / BT_WAVES)), bt_block(64 * BT_WAVES);
