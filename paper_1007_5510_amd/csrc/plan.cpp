@@ -296,8 +296,8 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   }
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
   choose_rows(m, 512, 1024, &plan->ns_cn, &plan->rps_cn);
-  choose_rows(m, 1024, 512, &plan->ns_g, &plan->rps_g);
-  choose_rows(n, 256, 256, &plan->ns_gt, &plan->rps_gt);
+  choose_rows(m, 512, 256, &plan->ns_g, &plan->rps_g);
+  choose_rows(n, 80, 256, &plan->ns_gt, &plan->rps_gt);
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
   plan->streamed = desc->source != RPCA_SRC_DEVICE;
   if (plan->streamed) {
@@ -565,7 +565,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     sx.a_bytes_read += m * n * bpe;
   } else if (fuse0) {
     // shift of pass 0: the column means of the first row panel
-    const int64_t rows0 = m < 16384 ? m : 16384;
+    const int64_t rows0 = m < 4096 ? m : 4096;
     int ns0 = 1;
     int64_t rps0 = 0;
     choose_rows(rows0, 1024, 64, &ns0, &rps0);

@@ -84,17 +84,22 @@ static int gram_lp(int L) {
   return lp % 32 == 16 ? lp : lp + 16;
 }
 
-template <typename TX>
+// GQ >= GM_ROWS * Lp / 512: staged elements per thread (a stage buffer holds
+// 512 GQ doubles, the part past GM_ROWS * Lp being padding that every thread
+// may write, so the staging has no branches)
+template <typename TX, int GQ>
 __global__ __launch_bounds__(512) void gram_mfma_kernel(const TX* __restrict__ X, int64_t ldx, int64_t rows, int L,
                                                         int Lp, int64_t rps, int T, int NT,
                                                         double* __restrict__ part) {
-  extern __shared__ double gs[];  // [2][GM_ROWS][Lp]
+  extern __shared__ double gs[];  // [2][512 GQ]
+  constexpr int SB = 512 * GQ;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = blockIdx.x;
   const int grp = blockIdx.y;
   const int64_t rb = (int64_t)s * rps;
   const int64_t re = rb + rps < rows ? rb + rps : rows;
-  // this wave's tiles: t = grp * GM_TILES + q * GM_WAVES + wave, upper triangle in row-major order
+  // this wave's tiles: t = grp * GM_TILES + q * GM_WAVES + wave, upper triangle in row-major order;
+  // slots past the last tile compute tile (0, 0) and are not written
   int ta[GM_PER_WAVE], tb[GM_PER_WAVE];
   bool ok[GM_PER_WAVE];
 #pragma unroll
@@ -102,39 +107,66 @@ __global__ __launch_bounds__(512) void gram_mfma_kernel(const TX* __restrict__ X
     int t = grp * GM_TILES + q * GM_WAVES + wave;
     ok[q] = t < NT;
     int a = 0;
-    while (ok[q] && t >= T - a) {
+    if (!ok[q]) t = 0;
+    while (t >= T - a) {
       t -= T - a;
       ++a;
     }
     ta[q] = a;
     tb[q] = a + t;
   }
+  // staging: element e = tid + 512 q -> (row e / Lp, column e % Lp) when e < GM_ROWS * Lp
+  int srow[GQ], scol[GQ];
+#pragma unroll
+  for (int q = 0; q < GQ; ++q) {
+    const int e = tid + 512 * q;
+    srow[q] = e < GM_ROWS * Lp ? e / Lp : GM_ROWS;  // GM_ROWS marks padding
+    scol[q] = e < GM_ROWS * Lp ? e % Lp : Lp;
+  }
+  // raw loads from clamped addresses, masked when stored so that they stay in flight meanwhile
+  TX pre[GQ];
+  auto load = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < GQ; ++q) {
+      const int64_t r = r0 + srow[q];
+      pre[q] = X[(r < re ? r : re - 1) * ldx + (scol[q] < L ? scol[q] : L - 1)];
+    }
+  };
+  auto store = [&](double* xs, int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < GQ; ++q)
+      xs[tid + 512 * q] = (r0 + srow[q] < re && scol[q] < L) ? (double)pre[q] : 0.0;
+  };
   doublex4 acc[GM_PER_WAVE];
 #pragma unroll
   for (int q = 0; q < GM_PER_WAVE; ++q) acc[q] = doublex4{0.0, 0.0, 0.0, 0.0};
   const int kr = lane >> 4, jc = lane & 15;
+  if (rb < re) {
+    load(rb);
+    store(gs, rb);
+  }
+  __syncthreads();
   int buf = 0;
   for (int64_t r0 = rb; r0 < re; r0 += GM_ROWS) {
-    double* xs = gs + buf * GM_ROWS * Lp;
-    for (int e = tid; e < GM_ROWS * Lp; e += 512) {
-      const int rr = e / Lp, cc = e % Lp;
-      const int64_t r = r0 + rr;
-      xs[e] = (r < re && cc < L) ? (double)X[r * ldx + cc] : 0.0;
-    }
-    __syncthreads();
+    const bool more = r0 + GM_ROWS < re;
+    if (more) load(r0 + GM_ROWS);  // next stage in flight during this one
+    const double* xs = gs + buf * SB;
 #pragma unroll
     for (int kk = 0; kk < GM_ROWS / 4; ++kk) {
       const double* row = xs + (4 * kk + kr) * Lp + jc;
+      double av[GM_PER_WAVE], bv[GM_PER_WAVE];
 #pragma unroll
       for (int q = 0; q < GM_PER_WAVE; ++q) {
-        if (ok[q]) {
-          const double a = row[16 * ta[q]];
-          const double b = row[16 * tb[q]];
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
-        }
+        av[q] = row[16 * ta[q]];
+        bv[q] = row[16 * tb[q]];
       }
+#pragma unroll
+      for (int q = 0; q < GM_PER_WAVE; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[q], bv[q], acc[q], 0, 0, 0);
     }
-    buf ^= 1;  // the other buffer is rewritten only after the next barrier
+    // the other buffer was last read before the previous barrier
+    if (more) store(gs + (buf ^ 1) * SB, r0 + GM_ROWS);
+    __syncthreads();
+    buf ^= 1;
   }
   double* out = part + (int64_t)s * L * L;
 #pragma unroll
@@ -157,15 +189,26 @@ hipError_t launch_gram(bool x_is_f64, const void* X, int64_t ldx, int64_t rows, 
   const int T = (L + 15) / 16;
   const int NT = T * (T + 1) / 2;
   const int Lp = gram_lp(L);
-  const size_t lds = sizeof(double) * 2 * GM_ROWS * (size_t)Lp;
-  if (lds <= g_max_lds_gram()) {
+  const int gq = Lp <= 224 ? 7 : (Lp <= 416 ? 13 : 21);
+  const size_t lds = sizeof(double) * 2 * 512 * (size_t)gq;
+  if (Lp <= 656 && lds <= g_max_lds_gram()) {
     dim3 grid((unsigned)nsplit, (unsigned)((NT + GM_TILES - 1) / GM_TILES));
-    if (x_is_f64)
-      hipLaunchKernelGGL(gram_mfma_kernel<double>, grid, dim3(512), lds, st, (const double*)X, ldx, rows, L, Lp,
-                         rows_per_split, T, NT, part);
+#define RPCA_GRAM(GQ)                                                                                           \
+  do {                                                                                                          \
+    if (x_is_f64)                                                                                               \
+      hipLaunchKernelGGL((gram_mfma_kernel<double, GQ>), grid, dim3(512), lds, st, (const double*)X, ldx, rows, L, \
+                         Lp, rows_per_split, T, NT, part);                                                      \
+    else                                                                                                        \
+      hipLaunchKernelGGL((gram_mfma_kernel<float, GQ>), grid, dim3(512), lds, st, (const float*)X, ldx, rows, L,  \
+                         Lp, rows_per_split, T, NT, part);                                                      \
+  } while (0)
+    if (Lp <= 224)
+      RPCA_GRAM(7);
+    else if (Lp <= 416)
+      RPCA_GRAM(13);
     else
-      hipLaunchKernelGGL(gram_mfma_kernel<float>, grid, dim3(512), lds, st, (const float*)X, ldx, rows, L, Lp,
-                         rows_per_split, T, NT, part);
+      RPCA_GRAM(21);
+#undef RPCA_GRAM
     return hipGetLastError();
   }
   const int tiles = (L + 63) / 64;
@@ -179,13 +222,19 @@ hipError_t launch_gram(bool x_is_f64, const void* X, int64_t ldx, int64_t rows, 
   return hipGetLastError();
 }
 
-__global__ void gram_reduce_kernel(const double* __restrict__ part, int nsplit, int L, double* __restrict__ W) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// 64 elements per block, 4 groups of threads each summing every 4th split, combined in a fixed order
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int nsplit, int L,
+                                                          double* __restrict__ W) {
+  __shared__ double sh[4][64];
+  const int t = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t LL = (int64_t)L * L;
-  if (e >= LL) return;
+  const int64_t e = (int64_t)blockIdx.x * 64 + t;
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * LL + e];
-  W[e] = s;
+  if (e < LL)
+    for (int k = g; k < nsplit; k += 4) s += part[(int64_t)k * LL + e];
+  sh[g][t] = s;
+  __syncthreads();
+  if (g == 0 && e < LL) W[e] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
 }
 
 // diag += coef * trace(W)  (shift of the shifted Cholesky QR)
@@ -206,7 +255,7 @@ __global__ __launch_bounds__(256) void add_trace_shift_kernel(double* __restrict
 hipError_t launch_gram_reduce(const double* part, int nsplit, int L, double* W, double shift_coef,
                               hipStream_t st) {
   const int64_t LL = (int64_t)L * L;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((LL + 255) / 256)), dim3(256), 0, st, part, nsplit, L, W);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((LL + 63) / 64)), dim3(256), 0, st, part, nsplit, L, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || shift_coef == 0.0) return e;
   hipLaunchKernelGGL(add_trace_shift_kernel, dim3(1), dim3(256), 0, st, W, L, shift_coef);
@@ -725,10 +774,156 @@ __global__ __launch_bounds__(256) void gemm64_kernel(const TA* __restrict__ A, i
   }
 }
 
+// C[M x N] = A[M x K] B[K x N] on FP64 matrix cores: a workgroup (4 waves)
+// takes 64 rows and 16 NT columns, K in stages of 16 staged in LDS (A
+// transposed, both with a row stride of 16 (mod 32) doubles so the 4 x 16
+// operand reads of a wave hit distinct banks), the next stage loaded into
+// registers during the current one.  With b_upper the stages and tiles that
+// only meet zeros of B are skipped.
+template <typename TA, int NT>
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(const TA* __restrict__ A, int64_t lda,
+                                                        const double* __restrict__ B, int64_t ldb, int64_t M, int N,
+                                                        int K, int b_upper, const double* __restrict__ colscale,
+                                                        const double* Cin, int64_t ldcin, double* C, int64_t ldc,
+                                                        float* __restrict__ C32, int64_t ldc32) {
+  constexpr int NP = 16 * NT;   // columns per workgroup
+  constexpr int BST = NP + 16;  // B stage row stride
+  constexpr int AST = 64 + 16;  // A^T stage row stride
+  __shared__ double Bs[2][16][BST];
+  __shared__ double At[2][16][AST];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, n16 = lane & 15;
+  const int64_t R0 = (int64_t)blockIdx.x * 64;
+  const int J0 = blockIdx.y * NP;
+  const int kend = b_upper ? (J0 + NP < K ? J0 + NP : K) : K;
+  // loaders: A row ar, K quad aq; B row br, columns bc + 16 q (consecutive lanes, consecutive columns)
+  const int ar = tid >> 2, aq = (tid & 3) * 4;
+  const int64_t arow = R0 + ar < M ? R0 + ar : M - 1;
+  const int br = tid >> 4, bc = tid & 15;
+  // two register sets: the stage two ahead is loaded while the next one is stored
+  struct Regs {
+    TA a[4];
+    double b[NT];
+  };
+  Regs r0, r1;
+  // unconditional loads from clamped addresses; the values outside the
+  // ranges are zeroed when stored, so the loads stay in flight meanwhile
+  auto load = [&](Regs& r, int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = k0 + aq + q;
+      r.a[q] = A[arow * lda + (k < kend ? k : kend - 1)];
+    }
+    const int k = k0 + br;
+    const int64_t kr = k < kend ? k : kend - 1;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int c = J0 + bc + 16 * q;
+      r.b[q] = B[kr * ldb + (c < N ? c : N - 1)];
+    }
+  };
+  auto store = [&](const Regs& r, int buf, int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) At[buf][aq + q][ar] = k0 + aq + q < kend ? (double)r.a[q] : 0.0;
+    const bool kin = k0 + br < kend;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) Bs[buf][br][bc + 16 * q] = (kin && J0 + bc + 16 * q < N) ? r.b[q] : 0.0;
+  };
+  doublex4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  auto compute = [&](int buf, int k0) {
+    double a4[4], bcur[4], bnext[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      a4[s4] = At[buf][4 * s4 + g][16 * wave + n16];
+      bcur[s4] = Bs[buf][4 * s4 + g][n16];
+    }
+    // tile by tile, the B operands of the next tile read during this one's MFMAs
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (t + 1 < NT) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) bnext[s4] = Bs[buf][4 * s4 + g][16 * (t + 1) + n16];
+      }
+      if (!b_upper || J0 + 16 * t + 15 >= k0) {  // tile t meets nonzero rows of B in this stage
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[s4], bcur[s4], acc[t], 0, 0, 0);
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) bcur[s4] = bnext[s4];
+    }
+  };
+  const int nst = (kend + 15) / 16;
+  if (nst > 0) {
+    load(r0, 0);
+    store(r0, 0, 0);
+  }
+  if (nst > 1) load(r1, 16);
+  __syncthreads();
+  // stage st in buffer st & 1; a buffer is rewritten only after the barrier that ends its last reads
+  for (int st = 0; st < nst; st += 2) {
+    if (st + 2 < nst) load(r0, (st + 2) * 16);
+    compute(0, st * 16);
+    if (st + 1 < nst) store(r1, 1, (st + 1) * 16);
+    __syncthreads();
+    if (st + 1 >= nst) break;
+    if (st + 3 < nst) load(r1, (st + 3) * 16);
+    compute(1, (st + 1) * 16);
+    if (st + 2 < nst) store(r0, 0, (st + 2) * 16);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = J0 + 16 * t + n16;
+    if (c >= N) continue;
+    const double sc = colscale != nullptr ? colscale[c] : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = R0 + 16 * wave + 4 * v + g;
+      if (r >= M) continue;
+      double val = acc[t][v] * sc;
+      if (Cin != nullptr) val += Cin[r * ldcin + c];
+      if (C != nullptr) C[r * ldc + c] = val;
+      if (C32 != nullptr) C32[r * ldc32 + c] = (float)val;
+    }
+  }
+}
+
+template <typename TA, int NT>
+static void launch_gemm_mfma(const TA* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int N, int K,
+                             bool b_upper, const double* colscale, double* C, int64_t ldc, float* C32, int64_t ldc32,
+                             hipStream_t st, const double* Cin, int64_t ldcin) {
+  dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 16 * NT - 1) / (16 * NT)));
+  hipLaunchKernelGGL((gemm_mfma_kernel<TA, NT>), grid, dim3(256), 0, st, A, lda, B, ldb, M, N, K, b_upper ? 1 : 0,
+                     colscale, Cin, ldcin, C, ldc, C32, ldc32);
+}
+
+template <typename TA>
+static void launch_gemm_mfma_any(const TA* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int N, int K,
+                                 bool b_upper, const double* colscale, double* C, int64_t ldc, float* C32,
+                                 int64_t ldc32, hipStream_t st, const double* Cin, int64_t ldcin) {
+  if (N <= 64)
+    launch_gemm_mfma<TA, 4>(A, lda, B, ldb, M, N, K, b_upper, colscale, C, ldc, C32, ldc32, st, Cin, ldcin);
+  else if (N <= 128)
+    launch_gemm_mfma<TA, 8>(A, lda, B, ldb, M, N, K, b_upper, colscale, C, ldc, C32, ldc32, st, Cin, ldcin);
+  else
+    launch_gemm_mfma<TA, 12>(A, lda, B, ldb, M, N, K, b_upper, colscale, C, ldc, C32, ldc32, st, Cin, ldcin);
+}
+
 hipError_t launch_gemm64(bool a_is_f64, const void* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int N,
                          int K, bool b_upper, const double* colscale, double* C, int64_t ldc, float* C32,
                          int64_t ldc32, hipStream_t st, const double* Cin, int64_t ldcin) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (K >= 1) {
+    if (a_is_f64)
+      launch_gemm_mfma_any<double>((const double*)A, lda, B, ldb, M, N, K, b_upper, colscale, C, ldc, C32, ldc32, st,
+                                   Cin, ldcin);
+    else
+      launch_gemm_mfma_any<float>((const float*)A, lda, B, ldb, M, N, K, b_upper, colscale, C, ldc, C32, ldc32, st,
+                                  Cin, ldcin);
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
   if (a_is_f64)
     hipLaunchKernelGGL(gemm64_kernel<double>, grid, dim3(256), 0, st, (const double*)A, lda, B, ldb, M, N, K,
