@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--l", type=int, default=60)
     ap.add_argument("--i", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2020)
-    ap.add_argument("--cpu-rows", type=int, default=40000)
+    ap.add_argument("--cpu-rows", type=int, default=80000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8_e4m3", "bf16_hilo"],
