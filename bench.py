@@ -10,7 +10,9 @@ G drawn from the seed inside the call) with A already resident in HBM.
 
 Prints one JSON line.  value = effective A-read throughput (i+2) m n 4 B /
 t_PCA in GB/s, i.e. the bytes of the minimum-pass schedule (one fused pass
-per power step, one forward pass, one T pass) over the whole-call time.
+per power step, one forward pass, one T pass) over the whole-call time;
+a_reads_actual is the number of full reads of A the kernels make per step
+(a power step here is a forward launch and an adjoint launch, each reading A).
 """
 from __future__ import annotations
 
@@ -372,6 +374,7 @@ def main():
                    "m": m, "n": n, "k": k, "l": l, "i": i, "storage": storage, "center": True},
         "frac_of_hbm_peak": round(value / PEAK_HBM_GBS, 4),
         "a_passes_actual": plan.stats()["passes"],
+        "a_reads_actual": round((nf + na) / max(args.steps, 1), 2),
         "roofline": roof,
         "gate": gate,
         "cpu_baseline": cpu,
