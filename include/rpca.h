@@ -80,7 +80,16 @@ enum {
   RPCA_FLAG_KEEP_STATE = 1u << 0,  /* keep H, Q, R, T, W, ... for rpca_backward / rpca_get_state */
   RPCA_FLAG_PROFILE = 1u << 1,     /* time every stage with HIP events (rpca_stats.ms_*) */
   RPCA_FLAG_FORCE_FALLBACK = 1u << 2, /* take the shifted Cholesky-QR fallback for Step 2 */
-  RPCA_FLAG_NO_RESCALE = 1u << 3   /* do not rescale the power iterates (Section 3, overflow remark) */
+  RPCA_FLAG_NO_RESCALE = 1u << 3,  /* do not rescale the power iterates (Section 3, overflow remark) */
+  /* float32 A only, DEVICE source, n even: form the float32 products of the
+   * passes over A (Steps 1 and 3) on bfloat16 matrix cores, each float32
+   * operand split by round-to-nearest into three bfloat16 parts and the six
+   * products of combined order <= 2 accumulated in float32 (dropped terms and
+   * split residuals below 2^-22 of each product, the rounding level of a
+   * float32 product).  UNSUPPORTED for other storage, sources or odd n.  A
+   * matrix that is not 16-byte aligned with lda % 4 == 0 uses the float32
+   * matrix-core kernels instead.                                              */
+  RPCA_FLAG_SPLIT_BF16 = 1u << 4
 };
 
 typedef struct {

@@ -33,6 +33,10 @@ struct FwdArgs {              // Z = alpha ((A - 1 s^T) Xt^T - 1 corr^T)
   const uint16_t* Xl = nullptr;
   int64_t ldxs = 0;
   int64_t plane = 0;  // BF16_HILO: elements between the hi and lo planes
+  // float32 A on bfloat16 matrix cores: X split into three bfloat16 planes
+  // (cpad x ldxs3 each, xplane3 elements apart)
+  const uint16_t* X3 = nullptr;
+  int64_t ldxs3 = 0, xplane3 = 0;
 };
 
 struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
@@ -55,6 +59,10 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
   const uint16_t* Zl = nullptr;
   int64_t ldzs = 0;
   int64_t plane = 0;
+  // float32 A on bfloat16 matrix cores: Z transposed and split into three
+  // bfloat16 planes (cpad x ldzs3 each, zplane3 elements apart)
+  const uint16_t* Z3 = nullptr;
+  int64_t ldzs3 = 0, zplane3 = 0;
 };
 
 hipError_t launch_fwd_f32(const FwdArgs& a, hipStream_t st);
@@ -64,6 +72,15 @@ int adj_nt_for(int ncols);  // 16-column tiles per wave used by the adjoint kern
 // row split of the adjoint product over `slots` concurrent blocks
 void adj_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st);
+// float64 reduction of the forward K-split partials into Z (with alpha and corr)
+hipError_t launch_fwd_reduce(const FwdArgs& a, int ksplit, hipStream_t st);
+// float32 products on bfloat16 matrix cores with a three-way operand split (panel_x6.hip)
+hipError_t launch_split3_x(const float* Xt, int64_t ldx, int64_t n, int ncols, int cpad, uint16_t* Xp, int64_t ldxs,
+                           int64_t plane, hipStream_t st);
+hipError_t launch_split3_zt(const float* Z, int64_t ldz, int64_t m, int ncols, bool ones, int cpad, uint16_t* Zp,
+                            int64_t ldzs, int64_t plane, hipStream_t st);
+hipError_t launch_fwd_x6(const FwdArgs& a, hipStream_t st);
+hipError_t launch_adj_x6(const AdjArgs& a, hipStream_t st);
 hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st);
 hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st);
 void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);

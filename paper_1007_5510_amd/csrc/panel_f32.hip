@@ -453,8 +453,12 @@ static hipError_t launch_fwd32(const FwdArgs& a, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
   if (e != hipSuccess || direct) return e;
+  return launch_fwd_reduce(a, ns, st);
+}
+
+hipError_t launch_fwd_reduce(const FwdArgs& a, int ksplit, hipStream_t st) {
   const int64_t tot = a.m * a.ncols;
-  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a.P, ns,
+  hipLaunchKernelGGL(fwd_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a.P, ksplit,
                      a.split_stride, a.ldp, a.m, a.ncols, a.corr, a.alpha, a.Z, a.ldz);
   return hipGetLastError();
 }

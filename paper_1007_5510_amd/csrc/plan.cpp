@@ -124,6 +124,15 @@ struct rpca_plan_s {
   uint16_t* Xl = nullptr;
   uint16_t* Zh = nullptr;
   uint16_t* Zl = nullptr;
+  // float32 products on bfloat16 matrix cores (RPCA_FLAG_SPLIT_BF16): three-way
+  // operand planes and the row splits of the adjoint in multiples of 32
+  bool x6 = false;
+  uint16_t* Xp3 = nullptr;
+  uint16_t* Zp3 = nullptr;
+  int64_t ldxs3 = 0, xplane3 = 0, ldzs3 = 0, zplane3 = 0;
+  int cpadx3 = 0, cpadz3 = 0;
+  int ns_y6 = 1, ns_t6 = 1;
+  int64_t rps_y6 = 0, rps_t6 = 0;
   int64_t sqp_cap = 0;
 
   bool have_state = false;
@@ -298,6 +307,21 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   choose_rows(m, 512, 1024, &plan->ns_cn, &plan->rps_cn);
   choose_rows(m, 512, 256, &plan->ns_g, &plan->rps_g);
   choose_rows(n, 80, 256, &plan->ns_gt, &plan->rps_gt);
+  if (desc->flags & RPCA_FLAG_SPLIT_BF16) {
+    // the split products read A in float pairs from device memory
+    if (desc->storage != RPCA_A_F32 || desc->source != RPCA_SRC_DEVICE || n % 2 != 0) return fail(RPCA_ERR_UNSUPPORTED);
+    plan->x6 = true;
+    plan->ldxs3 = round_up(n + 64, 64);
+    plan->cpadx3 = (int)round_up(l, 64);
+    plan->xplane3 = (int64_t)plan->cpadx3 * plan->ldxs3;
+    plan->ldzs3 = round_up(m, 64);
+    plan->cpadz3 = (int)round_up(std::max(L, l + 1), 64);
+    plan->zplane3 = (int64_t)plan->cpadz3 * plan->ldzs3;
+    plan->rps_y6 = round_up(plan->rps_y, 32);
+    plan->ns_y6 = (int)((m + plan->rps_y6 - 1) / plan->rps_y6);
+    plan->rps_t6 = round_up(plan->rps_t, 32);
+    plan->ns_t6 = (int)((m + plan->rps_t6 - 1) / plan->rps_t6);
+  }
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
   plan->streamed = desc->source != RPCA_SRC_DEVICE;
   if (plan->streamed) {
@@ -382,6 +406,10 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
       if (hipEventCreateWithFlags(&plan->ev_ready[q], hipEventDisableTiming) != hipSuccess ||
           hipEventCreateWithFlags(&plan->ev_free[q], hipEventDisableTiming) != hipSuccess)
         return fail(RPCA_ERR_HIP);
+  }
+  if (plan->x6) {
+    ALLOC(Xp3, 3 * plan->xplane3);
+    ALLOC(Zp3, 3 * plan->zplane3);
   }
   if (lowp) {
     ALLOC(Xh, (int64_t)plan->cpad_x * plan->ldxs);
@@ -529,6 +557,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const bool rescale = !(plan->d.flags & RPCA_FLAG_NO_RESCALE);
   // streamed panels sit in 16-byte aligned device buffers with ldb % 4 == 0
   const bool vec = streamed || (((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 4 == 0));
+  // split products on bfloat16 matrix cores when planned and A is 16-byte aligned with lda % 4 == 0
+  const bool x6 = plan->x6 && !streamed && plan->storage == RPCA_A_F32 && vec;
+  const int ns_y = x6 ? plan->ns_y6 : plan->ns_y;
   const int64_t ldx = plan->ldx;
   const int storage = plan->storage;
   const bool lowp = storage != RPCA_A_F32;
@@ -695,6 +726,12 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       fa.ldxs = plan->ldxs;
       fa.plane = plane;
       RPCA_TRY(launch_fwd_lowp(storage, fa, st));
+    } else if (x6) {
+      RPCA_TRY(launch_split3_x(Xj, ldx, n, l, plan->cpadx3, plan->Xp3, plan->ldxs3, plan->xplane3, st));
+      fa.X3 = plan->Xp3;
+      fa.ldxs3 = plan->ldxs3;
+      fa.xplane3 = plan->xplane3;
+      RPCA_TRY(launch_fwd_x6(fa, st));
     } else {
       RPCA_TRY(launch_fwd_f32(fa, st));
     }
@@ -715,8 +752,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     aa.Z = plan->H + (int64_t)j * l;
     aa.ldz = L;
     aa.ncols = l;
-    aa.rows_per_split = plan->rps_y;
-    aa.nsplit = plan->ns_y;
+    aa.rows_per_split = x6 ? plan->rps_y6 : plan->rps_y;
+    aa.nsplit = ns_y;
     aa.P = plan->P;
     aa.ldp = plan->ldp;
     aa.split_stride = (int64_t)(p0 ? l + 1 : l) * plan->ldp;
@@ -733,19 +770,26 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.ldzs = plan->ldzs;
       aa.plane = plane;
       RPCA_TRY(launch_adj_lowp(storage, aa, st));
+    } else if (x6) {
+      RPCA_TRY(launch_split3_zt(aa.Z, L, m, l, p0, (int)round_up(l + 1, 64), plan->Zp3, plan->ldzs3, plan->zplane3,
+                                st));
+      aa.Z3 = plan->Zp3;
+      aa.ldzs3 = plan->ldzs3;
+      aa.zplane3 = plan->zplane3;
+      RPCA_TRY(launch_adj_x6(aa, st));
     } else {
       RPCA_TRY(launch_adj_f32(aa, st));
     }
     if (p0) {
       // d0 = colsum(A - 1 s0^T)/m; the later passes shift by fl32(s0 + d0)
-      RPCA_TRY(launch_pass0_center(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, m, plan->shift, plan->d0,
+      RPCA_TRY(launch_pass0_center(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, m, plan->shift, plan->d0,
                                    plan->mu, plan->dres, st));
       dres = plan->dres;
     }
     float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
     int npart = 0;
     // X_1 = (A - 1 s0^T)^T Z - d0 (1^T Z)^T with Z the uncorrected block (exact: colsum(A - 1 s0^T) = m d0)
-    RPCA_TRY(launch_reduce_y(plan->P, plan->ns_y, aa.split_stride, plan->ldp, l, n, cs, p0 ? plan->d0 : dres,
+    RPCA_TRY(launch_reduce_y(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, cs, p0 ? plan->d0 : dres,
                              center ? plan->zsum : nullptr, Xn, ldx, plan->sqp, &npart, st));
     if (p0) {  // H^(0) = (A - 1 s0^T) G - 1 (d0^T G)  (block scale 1)
       RPCA_TRY(launch_dot_rows(plan->d0, Xj, ldx, n, l, plan->corr, st));
@@ -845,8 +889,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     aa.Z = plan->Q32;
     aa.ldz = L;
     aa.ncols = L;
-    aa.rows_per_split = plan->rps_t;
-    aa.nsplit = plan->ns_t;
+    aa.rows_per_split = x6 ? plan->rps_t6 : plan->rps_t;
+    aa.nsplit = x6 ? plan->ns_t6 : plan->ns_t;
     aa.P = plan->P;
     aa.ldp = plan->ldp;
     aa.split_stride = (int64_t)L * plan->ldp;
@@ -862,10 +906,16 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.ldzs = plan->ldzs;
       aa.plane = plane;
       RPCA_TRY(launch_adj_lowp(storage, aa, st));
+    } else if (x6) {
+      RPCA_TRY(launch_split3_zt(plan->Q32, L, m, L, false, plan->cpadz3, plan->Zp3, plan->ldzs3, plan->zplane3, st));
+      aa.Z3 = plan->Zp3;
+      aa.ldzs3 = plan->ldzs3;
+      aa.zplane3 = plan->zplane3;
+      RPCA_TRY(launch_adj_x6(aa, st));
     } else {
       RPCA_TRY(launch_adj_f32(aa, st));
     }
-    RPCA_TRY(launch_reduce_t(plan->P, plan->ns_t, aa.split_stride, plan->ldp, L, n, cs, dres,
+    RPCA_TRY(launch_reduce_t(plan->P, aa.nsplit, aa.split_stride, plan->ldp, L, n, cs, dres,
                              center ? plan->zsum : nullptr, plan->T, L, st));
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
