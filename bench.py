@@ -156,6 +156,111 @@ def cpu_baseline(A, k, l, i, rows, seed):
                       f"{dt:.1f} s for one factorisation"}
 
 
+# Rows of the paper's Tables 1a (first example) and 2a (second example): m, n, k, t_gen and t_PCA in
+# seconds, eps_0, eps.  Those runs stored A on a USB 2.0 disk in IEEE single precision and computed in
+# Matlab double precision on a single-core 32-bit 2 GHz Pentium M laptop with 1.5 GB of RAM.
+PAPER_TABLES = {
+    1: [(200000, 200000, 16, 2.7e4, 6.6e4, 4.3e-4, 4.3e-4),
+        (200000, 200000, 20, 2.7e4, 6.6e4, 1.0e-4, 1.0e-4),
+        (200000, 200000, 24, 2.7e4, 6.9e4, 1.0e-4, 1.0e-4)],
+    2: [(200000, 200000, 12, 2.7e4, 6.3e4, 1.0e-2, 1.0e-2),
+        (200000, 20000, 12, 1.9e3, 6.1e3, 1.0e-2, 1.0e-2),
+        (500000, 80000, 12, 2.2e4, 6.5e4, 1.0e-2, 1.0e-2)],
+}
+
+
+def run_paper_example(args):
+    """The paper's first or second example (Section 5.1): A = E S F with unitary DCT-II matrices E, F and
+    the example's diagonal S, at the sizes of Tables 1a / 2a, A resident in HBM as float32 (the paper
+    stores A in single precision); l = k + 2, i = 3, no centring.  A is built on the device outside the
+    timed region.  For each table row: t_PCA (one factorisation, averaged over --steps), the Appendix
+    estimate eps = p_{6,k}(A - U S V^T), and eps_0 = S_{k+1,k+1} (the spectral norm of A minus its best
+    rank-k approximation); one JSON line per row."""
+    import numpy as np
+    import torch
+    from synth import fixtures as F
+    from synth import gpu as SG
+    from paper_1007_5510_amd import rpca, _lib
+
+    which = 1 if args.workload == "paper-ex1" else 2
+    flags = _lib.FLAG_PROFILE | {"f32": 0, "split-bf16": _lib.FLAG_SPLIT_BF16,
+                                 "f64-step1": _lib.FLAG_FP64_STEP1}[args.compute]
+    dtype = {"f32": "f32", "split-bf16": "f32 as 3 x bf16 parts (6 bf16 products, f32 accumulate)",
+             "f64-step1": "f64 Step 1 (f32 A exact in f64, FP64 matrix cores), f32 Step 3"}[args.compute]
+    table = PAPER_TABLES[which]
+    rows = list(range(len(table))) if args.paper_row < 0 else [args.paper_row]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    A, shape = None, None
+    for r in rows:
+        m, n, k, p_gen, p_pca, p_eps0, p_eps = table[r]
+        l, i = k + 2, 3
+        if shape != (m, n):
+            A = None
+            torch.cuda.empty_cache()
+            A = torch.empty((m, n), dtype=torch.float32, device=dev)
+            t = time.perf_counter()
+            sigma = SG.example_dct_rows(which, m, n, A)
+            torch.cuda.synchronize()
+            t_gen = time.perf_counter() - t
+            shape = (m, n)
+            log(f"[bench] example {which}: A {m}x{n} float32 built in {t_gen:.1f}s")
+            torch.cuda.empty_cache()
+        G = torch.from_numpy(F.gaussian_G(1000 * which + r, n, l).astype(np.float32)).to(dev)
+        plan = rpca.Plan(m, n, k, l, i, flags=flags, device=0)
+        U = torch.empty((m, k), dtype=torch.float32, device=dev)
+        S = torch.empty((k,), dtype=torch.float32, device=dev)
+        V = torch.empty((n, k), dtype=torch.float32, device=dev)
+        for _ in range(args.warmup):
+            plan.factor(A, G=G, out=(U, S, V))
+        torch.cuda.synchronize()
+        stage = {"ms_power": 0.0, "ms_qr": 0.0, "ms_tpass": 0.0, "ms_small_svd": 0.0, "ms_assemble": 0.0}
+        fwd_ms, nf = 0.0, 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.factor(A, G=G, out=(U, S, V))
+            st = plan.stats()
+            fwd_ms += st["ms_fwd_kernel"]
+            nf += st["fwd_launches"]
+            for key in stage:
+                stage[key] += st[key]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        fwd_avg = fwd_ms / max(nf, 1)
+        fwd_tf = 2.0 * m * n * l / (fwd_avg * 1e-3) / 1e12
+        fwd_gbs = m * n * 4 / (fwd_avg * 1e-3) / 1e9
+        t1 = time.perf_counter()
+        eps = plan.residual(A, U, S, V, j=6, q=k, seed=1000 * which + r)
+        torch.cuda.synchronize()
+        t_est = time.perf_counter() - t1
+        # the same estimator run to j = 30: how far the Appendix's j = 6 sits below ||A - U S V^T||
+        eps30 = plan.residual(A, U, S, V, j=30, q=k, seed=1000 * which + r)
+        eps0 = float(sigma[k])
+        s_err = float(np.max(np.abs(S.cpu().double().numpy() - sigma[:k]) / sigma[:k]))
+        plan.close()
+        log(f"[bench] example {which} row {r} ({args.compute}): t_PCA {ms:.2f} ms, eps {eps:.4e} (j=30: {eps30:.4e}), "
+            f"eps_0 {eps0:.4e} (eps/eps_0 {eps / eps0:.4f}), max rel error of S_1..S_k {s_err:.2e}; forward kernel "
+            f"{fwd_avg:.3f} ms = {fwd_tf:.1f} TFLOP/s, {fwd_gbs:.0f} GB/s of A; stages " +
+            " ".join(f"{key}={v / args.steps:.2f}" for key, v in stage.items()))
+        out = {
+            "metric": "t_PCA (one rank-k factorisation) with the error estimate eps beside eps_0",
+            "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+            "dtype": dtype, "data": "synthetic (the example's closed form)",
+            "config": {"workload": f"paper example {which} (Table {which}a row {r + 1}): A = E S F, DCT-II E and F, "
+                                   f"{m} x {n} float32 in HBM, k={k} l={l} i={i}, no centring",
+                       "m": m, "n": n, "k": k, "l": l, "i": i},
+            "eps": eps, "eps0": eps0, "eps_over_eps0": round(eps / eps0, 6), "eps_j30": eps30,
+            "eps_j30_over_eps0": round(eps30 / eps0, 6), "sigma_max_rel_err": s_err,
+            "forward_kernel": {"avg_launch_ms": round(fwd_avg, 4), "tflops": round(fwd_tf, 2),
+                               "gbs_of_A": round(fwd_gbs, 1)},
+            "stages_ms": {key: round(v / args.steps, 3) for key, v in stage.items()},
+            "t_gen_s": round(t_gen, 2), "t_estimate_s": round(t_est, 3),
+            "paper": {"table": f"{which}a", "t_gen_s": p_gen, "t_pca_s": p_pca, "eps0": p_eps0, "eps": p_eps},
+        }
+        print(json.dumps(out), flush=True)
+
+
 def run_stream(args):
     """Streamed workload: A (m x 25000 float32, rank 100, sigma_j = exp(-j/20), noise 1e-4) in pinned
     host memory, moved over the host link in 16384-row panels once per pass; k=100, l=120, i=2."""
@@ -251,13 +356,16 @@ def main():
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8_e4m3", "bf16_hilo"],
                     help="stored format of A (low-precision copies are made from the float32 matrix with "
                          "its column means subtracted before conversion)")
-    ap.add_argument("--workload", default="incore", choices=["incore", "stream"],
+    ap.add_argument("--paper-row", type=int, default=-1,
+                    help="paper-ex1/paper-ex2: the row of Table 1a/2a to run (0-based; -1: every row)")
+    ap.add_argument("--workload", default="incore", choices=["incore", "stream", "paper-ex1", "paper-ex2"],
                     help="incore: A resident in HBM (default); stream: A in pinned host memory, panels over the "
-                         "host link")
+                         "host link; paper-ex1 / paper-ex2: the paper's first / second example at its table sizes")
     ap.add_argument("--stream-m", type=int, default=500000, help="rows of the streamed matrix (n = 25000)")
-    ap.add_argument("--compute", default="f32", choices=["f32", "split-bf16"],
+    ap.add_argument("--compute", default="f32", choices=["f32", "split-bf16", "f64-step1"],
                     help="float32 products on float32 matrix cores, or with each operand split into three bfloat16 "
-                         "parts on the bfloat16 matrix cores (float32 storage only)")
+                         "parts on the bfloat16 matrix cores (float32 storage only), or Step 1 in float64 on the "
+                         "FP64 matrix cores (paper-example workloads only: they are not centred)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -270,6 +378,9 @@ def main():
 
     if args.workload == "stream":
         run_stream(args)
+        return
+    if args.workload in ("paper-ex1", "paper-ex2"):
+        run_paper_example(args)
         return
 
     import torch
@@ -287,6 +398,8 @@ def main():
         log(f"[bench] stored A as {storage}: {Ain.data.numel() * Ain.data.element_size() / 1e9:.2f} GB")
     bpe = {"f32": 4, "bf16": 2, "fp8_e4m3": 1, "bf16_hilo": 4}[storage]
     split = args.compute == "split-bf16"
+    if args.compute == "f64-step1":
+        raise SystemExit("--compute f64-step1 needs an uncentred workload (paper-ex1 / paper-ex2)")
     if split and storage != "f32":
         raise SystemExit("--compute split-bf16 applies to float32 storage only")
     plan = rpca.Plan(m, n, k, l, i, storage=storage, center=True, seed=args.seed,

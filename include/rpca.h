@@ -89,7 +89,19 @@ enum {
    * float32 product).  UNSUPPORTED for other storage, sources or odd n.  A
    * matrix that is not 16-byte aligned with lda % 4 == 0 uses the float32
    * matrix-core kernels instead.                                              */
-  RPCA_FLAG_SPLIT_BF16 = 1u << 4
+  RPCA_FLAG_SPLIT_BF16 = 1u << 4,
+  /* float32 A only, DEVICE source, no centring: carry Step 1 (the blocks
+   * H^(0..i) of eqs. first_prod .. last_prod and the products A^T H^(j)) in
+   * float64 on the FP64 matrix cores, each float32 entry of A exact in
+   * float64, and keep H in float64 for Step 2 -- the arithmetic of the
+   * paper's experiments (A stored in single precision, computations in
+   * double, Section 5).  Needed when the spectrum spans a wide range above
+   * sigma_{k+1} and has a long, heavy tail, as in the paper's first example:
+   * float32 products then lose the directions that the later blocks carry
+   * below ~1e-7 of the leading ones.  Step 3 stays on the float32 kernels.
+   * UNSUPPORTED with centring, other storage or sources, SPLIT_BF16 or
+   * KEEP_STATE.                                                            */
+  RPCA_FLAG_FP64_STEP1 = 1u << 5
 };
 
 typedef struct {
@@ -132,7 +144,8 @@ typedef struct {
   int64_t adj_launches;  /* number of A^T Z kernel launches timed above */
   int64_t a_bytes_read;  /* bytes of A read by the panel kernels (algorithmic) */
   int64_t h2d_bytes;     /* bytes of A moved host -> device (streamed sources) */
-  int32_t qr_fallback;   /* 1 when Step 2 took the shifted Cholesky-QR path */
+  int32_t qr_fallback;   /* Step 2: 0 Cholesky QR twice; 1 shifted Cholesky QR three times;
+                            2 shifted rounds repeated until plain Cholesky QR applies */
   int32_t eig_vectors;   /* eigenvectors computed in Step 4 (k, or L when state is kept) */
   int32_t hip_error;     /* raw hipError_t of the last RPCA_ERR_HIP */
   int32_t passes;        /* full passes over A performed */
@@ -229,6 +242,8 @@ rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A,
  *   RPCA_STATE_W      L x L doubles, W of Step 4 (columns in S~ order; only the
  *                     first k columns are computed unless KEEP_STATE was set)
  *   RPCA_STATE_MU     n doubles, column means (centering)
+ *   RPCA_STATE_H64    m x L doubles, the float64 blocks of an FP64_STEP1 plan
+ *                     (scaled as RPCA_STATE_H; RPCA_STATE_H is then NO_STATE)
  * ld is the destination leading dimension in elements (>= column count).   */
 enum {
   RPCA_STATE_H = 0,
@@ -237,7 +252,8 @@ enum {
   RPCA_STATE_T = 3,
   RPCA_STATE_SIGMA = 4,
   RPCA_STATE_W = 5,
-  RPCA_STATE_MU = 6
+  RPCA_STATE_MU = 6,
+  RPCA_STATE_H64 = 7
 };
 rpca_status rpca_get_state(rpca_plan_t plan, int32_t which, void* dst, int64_t ld);
 

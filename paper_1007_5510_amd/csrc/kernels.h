@@ -97,6 +97,51 @@ hipError_t launch_quantize(int storage, int64_t m, int64_t n, const float* A, in
                            void* out, int64_t ldo, float* col_scale, float* amax_part, int nsplit,
                            int64_t rows_per_split, hipStream_t st);
 
+// ---------------------------------------------------------------- float64 Step 1 (panel_f64.hip)
+constexpr int F64_RT = 4;    // forward: 16-row tiles per wave (a block of 4 waves takes 256 rows)
+constexpr int F64_KST = 32;  // forward: K per LDS stage
+constexpr int F64_RS = 32;   // adjoint: rows per stage
+
+struct Fwd64Args {             // Z = alpha A Xt^T, float32 A, float64 X and Z
+  const float* A = nullptr;    // m x n row-major (lda)
+  int64_t lda = 0, m = 0, n = 0;
+  const double* Xt = nullptr;  // ncols x ldx, ldx even and >= n + F64_KST, zero past n
+  int64_t ldx = 0;
+  int ncols = 0;
+  const double* alpha = nullptr;  // device scalar or null
+  double* Z = nullptr;
+  int64_t ldz = 0;
+  bool vec = false;            // A 16-byte aligned and lda % 4 == 0
+  int ksplit = 1;              // > 1: partials P[s][r][c] (ldp >= ncols), kchunk % F64_KST == 0
+  int64_t kchunk = 0;
+  double* P = nullptr;
+  int64_t ldp = 0, split_stride = 0;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+
+struct Adj64Args {             // P_s = (A_s^T Z_s)^T, float32 A, float64 Z and P
+  const float* A = nullptr;
+  int64_t lda = 0, m = 0, n = 0;
+  const double* Z = nullptr;   // m x ncols (ldz)
+  int64_t ldz = 0;
+  int ncols = 0;
+  int64_t rows_per_split = 0;
+  int nsplit = 0;
+  double* P = nullptr;         // [nsplit][ncols][ldp], 32-byte aligned, ldp % 4 == 0
+  int64_t ldp = 0, split_stride = 0;
+  bool vec = false;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+
+hipError_t launch_fwd64(const Fwd64Args& a, hipStream_t st);
+hipError_t launch_adj64(const Adj64Args& a, hipStream_t st);
+// Xt[j][c] = sum_s P[s][j][c] in float64; per-block sums of squares into sq_part
+hipError_t launch_reduce_x64(const double* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
+                             double* Xt, int64_t ldx, double* sq_part, int* n_sq_part, hipStream_t st);
+hipError_t launch_check_finite_f64(const double* X, int64_t rows, int cols, int64_t ld, int* flag, hipStream_t st);
+void fwd64_split(int64_t m, int64_t n, int ncols, int64_t slots, int* ksplit, int64_t* kchunk);
+void adj64_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);
+
 // ---------------------------------------------------------------- auxiliary
 // FP64 column sums of a row-major matrix in a given storage: part[s][c] over row splits.
 hipError_t launch_colsum(int storage, const void* X, int64_t ld, int64_t rows, int64_t cols,

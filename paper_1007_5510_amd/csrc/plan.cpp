@@ -134,6 +134,16 @@ struct rpca_plan_s {
   int ns_y6 = 1, ns_t6 = 1;
   int64_t rps_y6 = 0, rps_t6 = 0;
   int64_t sqp_cap = 0;
+  // Step 1 in float64 (RPCA_FLAG_FP64_STEP1): float64 blocks X_j and H, their
+  // split partial sums, and the split configuration of those kernels
+  bool f64s1 = false;
+  int64_t ldx64 = 0, ldp64 = 0;
+  double* X64 = nullptr;   // (i+1) blocks of l x ldx64 (zero past n)
+  double* H64 = nullptr;   // m x L
+  double* P64 = nullptr;   // adjoint partials [ns_y64][l][ldp64]
+  double* Pf64 = nullptr;  // forward partials [fwd_ks64][m][l]
+  int ns_y64 = 1, fwd_ks64 = 1;
+  int64_t rps_y64 = 0, fwd_kchunk64 = 0;
 
   bool have_state = false;
   bool Qfinal_is_Q1 = false;
@@ -322,6 +332,18 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     plan->rps_t6 = round_up(plan->rps_t, 32);
     plan->ns_t6 = (int)((m + plan->rps_t6 - 1) / plan->rps_t6);
   }
+  if (desc->flags & RPCA_FLAG_FP64_STEP1) {
+    // float64 Step 1 reads float32 A from device memory, without centring, and
+    // keeps no state for the reverse sweep
+    if (desc->storage != RPCA_A_F32 || desc->source != RPCA_SRC_DEVICE || desc->center != 0 ||
+        (desc->flags & (RPCA_FLAG_SPLIT_BF16 | RPCA_FLAG_KEEP_STATE)) != 0)
+      return fail(RPCA_ERR_UNSUPPORTED);
+    plan->f64s1 = true;
+    plan->ldx64 = round_up(n + F64_KST, 4);
+    plan->ldp64 = round_up(n, 4);
+    adj64_split(m, n, l, slots, &plan->ns_y64, &plan->rps_y64);
+    fwd64_split(m, n, l, slots, &plan->fwd_ks64, &plan->fwd_kchunk64);
+  }
   plan->ldpf = ((int64_t)l + 63) / 64 * 64;
   plan->streamed = desc->source != RPCA_SRC_DEVICE;
   if (plan->streamed) {
@@ -407,6 +429,14 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
           hipEventCreateWithFlags(&plan->ev_free[q], hipEventDisableTiming) != hipSuccess)
         return fail(RPCA_ERR_HIP);
   }
+  if (plan->f64s1) {
+    ALLOC(X64, (int64_t)(i + 1) * l * plan->ldx64);
+    ALLOC(H64, m * L);
+    ALLOC(P64, (int64_t)plan->ns_y64 * l * plan->ldp64);
+    ALLOC(Pf64, plan->fwd_ks64 > 1 ? (int64_t)plan->fwd_ks64 * m * l : 1);
+    if (hipMemset(plan->X64, 0, sizeof(double) * (size_t)((int64_t)(i + 1) * l * plan->ldx64)) != hipSuccess)
+      return fail(RPCA_ERR_HIP);
+  }
   if (plan->x6) {
     ALLOC(Xp3, 3 * plan->xplane3);
     ALLOC(Zp3, 3 * plan->zplane3);
@@ -470,6 +500,65 @@ rpca_status cholqr_round(rpca_plan_s* plan, bool x_f64, const void* X, double* X
   }
   RPCA_TRY(launch_gemm64(x_f64, X, L, plan->Rinv, L, m, L, L, true, nullptr, Xout, L, Xout32, L, st));
   return RPCA_OK;
+}
+
+// Step 2 of last resort, for a basis that is numerically rank deficient beyond
+// what one shifted round repairs (condition of H above ~1/u, as the Krylov
+// blocks of a spectrum spanning many orders of magnitude are): shifted
+// Cholesky QR rounds repeated until the Gram matrix of the current basis has a
+// plain Cholesky factorisation, then two plain rounds.  Every round
+// right-multiplies by an upper-triangular matrix, so the span is kept up to
+// rounding, and each shifted round lifts the directions at rounding level
+// towards full rank; they end as an orthonormal completion, the part that the
+// trailing columns of a pivoted QR (Step 2) play for such an H.  The product of
+// the round factors is kept in Rfull (H = Q Rfull) for the reverse sweep.
+rpca_status cholqr_repeated(rpca_plan_s* plan, bool x_f64, const void* H, double** Qout) {
+  const int L = plan->L;
+  const int64_t m = plan->m, LL = (int64_t)L * L;
+  hipStream_t st = plan->stream;
+  const double u = 1.1102230246251565e-16;
+  const double coef = 11.0 * ((double)m * L + (double)L * (L + 1)) * u;
+  const void* X = H;
+  bool xf = x_f64;
+  double* bufs[2] = {plan->Q1, plan->Q};
+  int nb = 0, plain = 0;
+  for (int r = 0; r < 12; ++r) {
+    RPCA_TRY(launch_gram(xf, X, L, m, L, plan->rps_g, plan->ns_g, plan->gp, st));
+    RPCA_TRY(launch_gram_reduce(plan->gp, plan->ns_g, L, plan->R1, 0.0, st));
+    RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 2 * sizeof(int), st));
+    RPCA_TRY(launch_cholinv(plan->R1, L, 1e-14, plan->flags + 1, plan->Rinv, st));
+    int hf[2] = {0, 0};
+    RPCA_TRY(hipMemcpyAsync(hf, plan->flags + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    RPCA_TRY(hipStreamSynchronize(st));
+    if (hf[0] != 0) {
+      // W + s I, s = coef trace(W): positive definite in floating point
+      RPCA_TRY(launch_gram_reduce(plan->gp, plan->ns_g, L, plan->R1, coef, st));
+      RPCA_TRY(launch_cholinv(plan->R1, L, 1e-14, plan->flags + 2, plan->Rinv, st));
+      RPCA_TRY(hipMemcpyAsync(hf + 1, plan->flags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+      RPCA_TRY(hipStreamSynchronize(st));
+      if (hf[1] != 0) return RPCA_ERR_QR_BREAKDOWN;
+      plain = 0;
+    } else {
+      ++plain;
+    }
+    double* Xn = bufs[nb];
+    nb ^= 1;
+    RPCA_TRY(launch_gemm64(xf, X, L, plan->Rinv, L, m, L, L, true, nullptr, Xn, L, plain == 2 ? plan->Q32 : nullptr,
+                           L, st));
+    if (r == 0) {
+      RPCA_TRY(hipMemcpyAsync(plan->Rfull, plan->R1, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+    } else {
+      RPCA_TRY(launch_trmm_upper(plan->R1, plan->Rfull, L, plan->Rtmp, st));
+      RPCA_TRY(hipMemcpyAsync(plan->Rfull, plan->Rtmp, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+    }
+    X = Xn;
+    xf = true;
+    if (plain == 2) {
+      *Qout = Xn;
+      return RPCA_OK;
+    }
+  }
+  return RPCA_ERR_QR_BREAKDOWN;
 }
 
 }  // namespace
@@ -625,6 +714,65 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_gen_G(plan->d.seed, n, l, X0, ldx, st));
   RPCA_TRY(launch_fill_f64(plan->alpha, i + 1, 1.0, st));
 
+  // float64 Step 1: H^(j) = alpha_j A X_j and X_{j+1} = A^T H^(j) on the FP64
+  // matrix cores, X_0 = G widened exactly; alpha_{j+1} = 1/||X_{j+1}||_F
+  const bool f64s1 = plan->f64s1;
+  if (f64s1) {
+    const int64_t ldx64 = plan->ldx64;
+    RPCA_TRY(launch_widen(X0, ldx, l, n, plan->X64, ldx64, st));
+    for (int j = 0; j <= i; ++j) {
+      Fwd64Args fa;
+      fa.A = static_cast<const float*>(A);
+      fa.lda = lda;
+      fa.m = m;
+      fa.n = n;
+      fa.Xt = plan->X64 + (int64_t)j * l * ldx64;
+      fa.ldx = ldx64;
+      fa.ncols = l;
+      fa.alpha = plan->alpha + j;
+      fa.Z = plan->H64 + (int64_t)j * l;
+      fa.ldz = L;
+      fa.vec = vec;
+      fa.ksplit = plan->fwd_ks64;
+      fa.kchunk = plan->fwd_kchunk64;
+      fa.P = plan->Pf64;
+      fa.ldp = l;
+      fa.split_stride = m * l;
+      if (EventPair* ev = next_fwd_events(plan)) {
+        fa.ev_begin = ev->a;
+        fa.ev_end = ev->b;
+      }
+      RPCA_TRY(launch_fwd64(fa, st));
+      sx.passes += 1;
+      sx.a_bytes_read += m * n * bpe;
+      if (j == i) break;
+      Adj64Args aa;
+      aa.A = static_cast<const float*>(A);
+      aa.lda = lda;
+      aa.m = m;
+      aa.n = n;
+      aa.Z = fa.Z;
+      aa.ldz = L;
+      aa.ncols = l;
+      aa.rows_per_split = plan->rps_y64;
+      aa.nsplit = plan->ns_y64;
+      aa.P = plan->P64;
+      aa.ldp = plan->ldp64;
+      aa.split_stride = (int64_t)l * plan->ldp64;
+      aa.vec = vec;
+      if (EventPair* ev = next_adj_events(plan)) {
+        aa.ev_begin = ev->a;
+        aa.ev_end = ev->b;
+      }
+      RPCA_TRY(launch_adj64(aa, st));
+      int npart = 0;
+      RPCA_TRY(launch_reduce_x64(plan->P64, plan->ns_y64, aa.split_stride, plan->ldp64, l, n,
+                                 plan->X64 + (int64_t)(j + 1) * l * ldx64, ldx64, plan->sqp, &npart, st));
+      RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
+    }
+    RPCA_TRY(launch_check_finite_f64(plan->H64, m, L, L, plan->flags, st));
+  }
+
   // streamed: one host-link transfer per pass; each panel runs the forward
   // product and the adjoint of its own rows while it is resident in HBM
   for (int j = 0; streamed && j <= i; ++j) {
@@ -691,7 +839,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
 
-  for (int j = 0; !streamed && j <= i; ++j) {
+  for (int j = 0; !streamed && !f64s1 && j <= i; ++j) {
     float* Xj = plan->X + (int64_t)j * l * ldx;
     // with fused centring, pass 0 writes the uncorrected product (A - 1 s0^T) G and corrects it below
     const bool p0 = fuse0 && j == 0;
@@ -797,19 +945,21 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     }
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
-  RPCA_TRY(launch_check_finite_f32(plan->H, m, L, L, plan->flags, st));
+  if (!f64s1) RPCA_TRY(launch_check_finite_f32(plan->H, m, L, L, plan->flags, st));
   const auto t_power = std::chrono::steady_clock::now();
 
-  // Step 2: Cholesky QR twice (shifted Cholesky QR three times as fallback)
-  bool fallback = (plan->d.flags & RPCA_FLAG_FORCE_FALLBACK) != 0;
+  // Step 2: Cholesky QR twice; shifted Cholesky QR three times as the first
+  // fallback, repeated shifted rounds as the second
+  int level = (plan->d.flags & RPCA_FLAG_FORCE_FALLBACK) != 0 ? 1 : 0;
   double* Qfinal = nullptr;
   // With centring every exact block A~ X_j has zero column sums; the float32
   // rounding of H leaves a component along 1 that the conditioning of H would
   // amplify inside span(Q), so it is removed in float64 before the QR (a no-op
   // in exact arithmetic).
-  const bool x_f64 = center;
-  const void* Hqr = center ? static_cast<const void*>(plan->Q) : static_cast<const void*>(plan->H);
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  const bool x_f64 = center || f64s1;
+  const void* Hqr = f64s1 ? static_cast<const void*>(plan->H64)
+                          : center ? static_cast<const void*>(plan->Q) : static_cast<const void*>(plan->H);
+  for (int attempt = 0; attempt < 3; ++attempt) {
     RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 3 * sizeof(int), st));
     if (center) {
       RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
@@ -817,7 +967,16 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       RPCA_TRY(launch_center_cols(plan->H, L, m, L, plan->zsum, 1.0 / (double)m, plan->Q, L, st));
     }
     rpca_status s;
-    if (!fallback) {
+    if (level == 2) {
+      s = cholqr_repeated(plan, x_f64, Hqr, &Qfinal);
+      if (s != RPCA_OK) return s;
+      int hf0 = 0;
+      RPCA_TRY(hipMemcpyAsync(&hf0, plan->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      RPCA_TRY(hipStreamSynchronize(st));
+      if (hf0 != 0) return RPCA_ERR_NONFINITE;
+      break;
+    }
+    if (level == 0) {
       s = cholqr_round(plan, x_f64, Hqr, plan->Q1, nullptr, plan->R1, 0.0, plan->flags + 1);
       if (s != RPCA_OK) return s;
       s = cholqr_round(plan, true, plan->Q1, plan->Q, plan->Q32, plan->R2, 0.0, plan->flags + 2);
@@ -841,10 +1000,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     if (hf[0] != 0) return RPCA_ERR_NONFINITE;
     const bool broke = hf[1] != 0 || hf[2] != 0 || hf[3] != 0;
     if (!broke) break;
-    if (fallback) return RPCA_ERR_QR_BREAKDOWN;
-    fallback = true;
+    ++level;
   }
-  sx.qr_fallback = fallback ? 1 : 0;
+  sx.qr_fallback = level;
   const auto t_qr = std::chrono::steady_clock::now();
 
   // Step 3: T = A~^T Q  (n x L, FP64 after the ordered split reduction)
@@ -979,7 +1137,12 @@ extern "C" rpca_status rpca_get_state(rpca_plan_t plan, int32_t which, void* dst
   const void* src = nullptr;
   int64_t rows = 0, cols = 0, lds = 0, esz = 0;
   switch (which) {
-    case RPCA_STATE_H: src = plan->H; rows = m; cols = L; lds = L; esz = 4; break;
+    case RPCA_STATE_H:
+      if (plan->f64s1) return RPCA_ERR_NO_STATE;
+      src = plan->H; rows = m; cols = L; lds = L; esz = 4; break;
+    case RPCA_STATE_H64:
+      if (!plan->f64s1) return RPCA_ERR_NO_STATE;
+      src = plan->H64; rows = m; cols = L; lds = L; esz = 8; break;
     case RPCA_STATE_HSCALE: src = plan->alpha; rows = 1; cols = plan->i + 1; lds = cols; esz = 8; break;
     case RPCA_STATE_Q: src = plan->Qfinal_is_Q1 ? plan->Q1 : plan->Q; rows = m; cols = L; lds = L; esz = 8; break;
     case RPCA_STATE_T: src = plan->T; rows = n; cols = L; lds = L; esz = 8; break;
@@ -1134,10 +1297,14 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   RPCA_TRY(launch_xty(true, b.Qbar, L, L, true, Q, L, L, m, plan->rps_g, plan->ns_g, nullptr, plan->gp, b.M2, st));
   RPCA_TRY(launch_copyltu_neg(b.M2, L, b.Smat, st));
   RPCA_TRY(launch_gemm64(true, Q, L, b.Smat, L, m, L, L, false, nullptr, b.Qbar, L, nullptr, 0, st, b.Qbar, L));
-  RPCA_TRY(launch_trmm_upper(plan->R2, plan->R1, L, b.Rf, st));
-  if (plan->stats.qr_fallback) {
-    RPCA_TRY(launch_trmm_upper(plan->R3, b.Rf, L, b.Rt, st));
-    RPCA_TRY(hipMemcpyAsync(b.Rf, b.Rt, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+  if (plan->stats.qr_fallback == 2) {
+    RPCA_TRY(hipMemcpyAsync(b.Rf, plan->Rfull, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+  } else {
+    RPCA_TRY(launch_trmm_upper(plan->R2, plan->R1, L, b.Rf, st));
+    if (plan->stats.qr_fallback) {
+      RPCA_TRY(launch_trmm_upper(plan->R3, b.Rf, L, b.Rt, st));
+      RPCA_TRY(hipMemcpyAsync(b.Rf, b.Rt, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+    }
   }
   RPCA_TRY(launch_triinv(b.Rf, L, b.RfInv, st));
   RPCA_TRY(launch_transpose_sq(b.RfInv, L, true, b.RinvT, st));

@@ -188,7 +188,7 @@ class Plan:
 
     def state(self, which: str):
         m, n, L = self.m, self.n, self.L
-        shapes = {"H": ((m, L), torch.float32), "HSCALE": ((self.i + 1,), torch.float64),
+        shapes = {"H": ((m, L), torch.float32), "H64": ((m, L), torch.float64), "HSCALE": ((self.i + 1,), torch.float64),
                   "Q": ((m, L), torch.float64), "T": ((n, L), torch.float64),
                   "SIGMA": ((L,), torch.float64), "W": ((L, L), torch.float64), "MU": ((n,), torch.float64)}
         shape, dt = shapes[which]

@@ -7,6 +7,7 @@ The functions take torch tensors for device memory and mirror
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -67,3 +68,40 @@ def normals(out, seed, stream_id, start):
                               _stream())
     if rc != 0:
         raise RuntimeError(f"synth_normals failed ({rc})")
+
+
+def example_dct_rows(which: int, m: int, n: int, out, chunk_bytes: int = 1 << 32):
+    """Fill ``out`` (an m x n float32 tensor, any device) with A = E S F of the paper's first or second
+    example (Section 5.1): E, F unitary DCT-II of orders m and n (first n columns of E), S the
+    example's diagonal.  Matches ``synth.fixtures.example_dct(which, m, n)["A"]``.
+
+    A row of A is the inverse DCT (DCT-III) of sigma o E[r, :n], done in float64 as one complex FFT of
+    length 2n per row, so the cost is O(m n log n) rather than the O(m n^2) of forming E S F.
+    """
+    import torch
+    from .fixtures import example1_sigma, example2_sigma
+
+    if m < n:
+        raise ValueError("the examples have m >= n")
+    dev = out.device
+    sigma = example1_sigma(n) if which == 1 else example2_sigma(n)
+    j = torch.arange(n, dtype=torch.float64, device=dev)
+    # F[j][c] = sqrt(2/n) a_j cos(pi (2c+1) j / (2n)): row r of A is Re(sum_j w_j x_j e^{2 pi i j c / (2n)})
+    # with x = sigma o E[r, :] and w_j = sqrt(2/n) a_j e^{i pi j / (2n)}
+    w = torch.polar(torch.full((n,), math.sqrt(2.0 / n), dtype=torch.float64, device=dev), math.pi * j / (2.0 * n))
+    w[0] = w[0] / math.sqrt(2.0)
+    w = w * torch.from_numpy(sigma).to(dev)
+    twoj1 = 2.0 * j + 1.0
+    rows = max(1, min(m, chunk_bytes // (16 * 2 * n * 3)))
+    for r0 in range(0, m, rows):
+        r1 = min(m, r0 + rows)
+        r = torch.arange(r0, r1, dtype=torch.float64, device=dev)
+        # E[r][j] = sqrt(2/m) a_r cos(pi (2j+1) r / (2m)); (2j+1) r mod 4m is exact in float64
+        ph = torch.remainder(torch.outer(r, twoj1), 4.0 * m)
+        E = torch.cos(ph * (math.pi / (2.0 * m))) * math.sqrt(2.0 / m)
+        if r0 == 0:
+            E[0] /= math.sqrt(2.0)
+        Z = torch.fft.ifft(E * w, n=2 * n, dim=1)
+        out[r0:r1] = (Z[:, :n].real * (2.0 * n)).to(out.dtype)
+        del E, Z, ph
+    return sigma

@@ -59,6 +59,19 @@ def test_dct_examples_are_orthogonal():
     assert np.max(np.abs(np.sort(s)[::-1] - np.sort(ex["sigma"])[::-1])) < 1e-13
 
 
+
+@pytest.mark.parametrize("which,m,n", [(1, 300, 120), (2, 257, 255), (2, 1000, 999)])
+def test_fft_example_builder_matches_dense_product(which, m, n):
+    # the per-row inverse-DCT builder used for the paper-size examples against E S F formed densely
+    import torch
+    from synth import gpu as SG
+    out = torch.empty((m, n), dtype=torch.float64)
+    sigma = SG.example_dct_rows(which, m, n, out, chunk_bytes=1 << 20)
+    ex = F.example_dct(which, m, n)
+    assert np.array_equal(sigma, ex["sigma"])
+    assert np.max(np.abs(out.numpy() - ex["A64"])) < 1e-14 * max(1.0, np.abs(ex["A64"]).max() * 10)
+
+
 # ---------------------------------------------------------------- the algorithm
 def _exact_problem(seed=3, m=400, n=150, r=150, decay=0.9, k=6, l=8, i=2):
     sigma = decay ** np.arange(r, dtype=np.float64)
