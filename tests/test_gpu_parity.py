@@ -153,7 +153,7 @@ def test_centered_parity():
     compare(g, orc, k, n_vec=4)
     U, S, V, plan = g
     # the column means are folded into pass 0: mu = s0 + colsum(A - 1 s0^T) / m, the deviation sums
-    # accumulated on float32 matrix cores (folded every 256 rows) and in float64 across splits
+    # accumulated on float32 matrix cores (one float32 chain per row split) and in float64 across splits
     mu = plan.state("MU").cpu().numpy()
     assert np.abs(mu - orc.mu).max() < 1e-9 * np.abs(p["A"]).max()
     assert np.abs(np.ones(m) @ U).max() < 1e-4
