@@ -67,13 +67,19 @@ typedef enum {
 } rpca_storage;
 
 /* Where A lives (Section 4: storage on disk vs. on-the-fly evaluation).
- *   DEVICE       A resident in HBM
- *   HOST_PINNED  A in pinned host memory, streamed by row panels
- *   CALLBACK     rows produced on demand by an rpca_panel_cb (Section 4.1)  */
+ *   DEVICE           A resident in HBM
+ *   HOST_PINNED      A in pinned host memory, streamed by row panels
+ *   CALLBACK         rows produced on demand on the host by an rpca_panel_cb
+ *                    (Section 4.1), copied to the device panel by panel
+ *   DEVICE_CALLBACK  rows produced on demand on the device by an
+ *                    rpca_device_panel_cb registered with
+ *                    rpca_set_device_panel_cb (Section 4.1 without a host
+ *                    link: every pass regenerates the rows it reads)      */
 typedef enum {
   RPCA_SRC_DEVICE = 0,
   RPCA_SRC_HOST_PINNED = 1,
-  RPCA_SRC_CALLBACK = 2
+  RPCA_SRC_CALLBACK = 2,
+  RPCA_SRC_DEVICE_CALLBACK = 3
 } rpca_source;
 
 enum {
@@ -112,7 +118,7 @@ typedef struct {
   int32_t storage;     /* rpca_storage */
   int32_t source;      /* rpca_source */
   int32_t center;      /* 1: factor A - 1 mu^T with mu the column means of A (Introduction) */
-  int64_t panel_rows;  /* rows per streamed panel for HOST_PINNED / CALLBACK; 0 = automatic */
+  int64_t panel_rows;  /* rows per streamed panel for HOST_PINNED / CALLBACK / DEVICE_CALLBACK; 0 = automatic */
   uint64_t seed;       /* G from Philox4x32-10 + Box-Muller when rpca_factor gets G == NULL */
   uint32_t flags;      /* RPCA_FLAG_* */
   int32_t device;      /* HIP device ordinal the plan runs on */
@@ -129,6 +135,18 @@ typedef int (*rpca_panel_cb)(void* user, int64_t row0, int64_t nrows, void* dst,
 
 typedef struct rpca_plan_s* rpca_plan_t;
 
+/* Enqueues, on hip_stream (a hipStream_t owned by the plan), device work that
+ * writes rows [row0, row0+nrows) of A as float32 into dst (device memory owned
+ * by the plan, nrows x ld, ld >= n), and returns 0; any other value aborts
+ * rpca_factor with RPCA_ERR_CALLBACK.  The callback runs on the thread that
+ * called rpca_factor; it must only enqueue work on hip_stream (no device-wide
+ * synchronisation, no work on other streams that dst depends on).  It is
+ * called once per panel per pass, panels in row order, and the same rows must
+ * come back identical in every pass (Section 4.1: rows evaluated on demand,
+ * every contribution of a row made at once; Section 5.3: regenerated rows
+ * restart their generator from the same seed).                              */
+typedef int (*rpca_device_panel_cb)(void* user, int64_t row0, int64_t nrows, float* dst, int64_t ld,
+                                    void* hip_stream);
 /* Timing and counters of the last rpca_factor call (PROFILE adds the ms_* stages). */
 typedef struct {
   double ms_total;       /* entry to results ready, host clock */
@@ -162,11 +180,13 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
 
 /* Computes U (m x k), S (k, non-increasing, >= 0) and V (n x k) of Steps 1-6.
  *   A          DEVICE: device pointer; HOST_PINNED: pinned host pointer;
- *              CALLBACK: ignored (may be NULL).  Format per desc->storage.
+ *              CALLBACK, DEVICE_CALLBACK: ignored (may be NULL).  Format per
+ *              desc->storage.
  *   lda        leading dimension of A in elements (>= n).
  *   col_scale  FP8_E4M3 only: n device floats (DEVICE) or host floats
  *              (HOST_PINNED); NULL otherwise.
- *   cb, user   CALLBACK source only.
+ *   cb, user   CALLBACK source only (DEVICE_CALLBACK plans use the generator
+ *              registered by rpca_set_device_panel_cb; INVALID_ARG without one).
  *   G          n x l device floats (row-major, leading dimension l), the
  *              Gaussian test matrix of Step 1; NULL = generate from desc->seed
  *              with Philox4x32-10 (counter = element index r*l+c >> 1, stream 1,
@@ -262,6 +282,12 @@ rpca_status rpca_get_stats(rpca_plan_t plan, rpca_stats* out);
 
 /* Static description of a status code (never NULL). */
 const char* rpca_status_str(rpca_status s);
+
+/* Registers the row generator of a DEVICE_CALLBACK plan (replacing any earlier
+ * one); user is passed back unchanged.  The plan's panel buffers are filled on
+ * a second stream of the plan, double-buffered against the panel kernels.
+ * Errors: INVALID_ARG (NULL plan or cb), UNSUPPORTED (plan of another source). */
+rpca_status rpca_set_device_panel_cb(rpca_plan_t plan, rpca_device_panel_cb cb, void* user);
 
 /* Frees the plan and its workspace; NULL is ignored. */
 void rpca_destroy(rpca_plan_t plan);

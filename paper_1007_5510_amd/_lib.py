@@ -19,7 +19,7 @@ STATUS_NAMES = {
     8: "RPCA_ERR_NO_STATE",
 }
 STORAGE = {"f32": 0, "bf16": 1, "fp8_e4m3": 2, "bf16_hilo": 3}
-SOURCE = {"device": 0, "host_pinned": 1, "callback": 2}
+SOURCE = {"device": 0, "host_pinned": 1, "callback": 2, "device_callback": 3}
 FLAG_KEEP_STATE = 1 << 0
 FLAG_PROFILE = 1 << 1
 FLAG_FORCE_FALLBACK = 1 << 2
@@ -56,6 +56,9 @@ class Stats(ctypes.Structure):
 PANEL_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                             ctypes.c_int64, ctypes.c_void_p)
 
+DEVICE_PANEL_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_int64, ctypes.c_void_p)
+
 _lib = None
 
 
@@ -89,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.rpca_get_stats.restype = i32
     lib.rpca_status_str.argtypes = [i32]
     lib.rpca_status_str.restype = ctypes.c_char_p
+    lib.rpca_set_device_panel_cb.argtypes = [vp, DEVICE_PANEL_CB, vp]
+    lib.rpca_set_device_panel_cb.restype = i32
     lib.rpca_destroy.argtypes = [vp]
     lib.rpca_destroy.restype = None
     _lib = lib

@@ -78,6 +78,8 @@ struct rpca_plan_s {
   int fwd_ks_p = 1;
   int64_t fwd_kchunk_p = 0;
   double* acc = nullptr;        // float64 accumulator of the adjoint products (L x ldp) or column sums
+  rpca_device_panel_cb dcb = nullptr;  // DEVICE_CALLBACK source: row generator and its argument
+  void* dcb_user = nullptr;
   // low-precision storage: bfloat16 hi/lo planes of the float operand
   int64_t ldxs = 0;  // X planes: cpad_x rows of ldxs (n rounded up to 64)
   int cpad_x = 0;
@@ -224,7 +226,7 @@ rpca_status validate_desc(const rpca_desc* d) {
   if (d->l < d->k || d->i < 0) return RPCA_ERR_INVALID_ARG;
   if ((int64_t)(d->i + 1) * d->l > d->n - d->k) return RPCA_ERR_INVALID_ARG;
   if (d->storage < RPCA_A_F32 || d->storage > RPCA_A_BF16_HILO) return RPCA_ERR_UNSUPPORTED;
-  if (d->source < RPCA_SRC_DEVICE || d->source > RPCA_SRC_CALLBACK) return RPCA_ERR_UNSUPPORTED;
+  if (d->source < RPCA_SRC_DEVICE || d->source > RPCA_SRC_DEVICE_CALLBACK) return RPCA_ERR_UNSUPPORTED;
   if ((int64_t)(d->i + 1) * d->l > 1024) return RPCA_ERR_UNSUPPORTED;
   return RPCA_OK;
 }
@@ -463,6 +465,14 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   return RPCA_OK;
 }
 
+rpca_status rpca_set_device_panel_cb(rpca_plan_t plan, rpca_device_panel_cb cb, void* user) {
+  if (plan == nullptr || cb == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (plan->d.source != RPCA_SRC_DEVICE_CALLBACK) return RPCA_ERR_UNSUPPORTED;
+  plan->dcb = cb;
+  plan->dcb_user = user;
+  return RPCA_OK;
+}
+
 rpca_status rpca_get_stats(rpca_plan_t plan, rpca_stats* out) {
   if (plan == nullptr || out == nullptr) return RPCA_ERR_INVALID_ARG;
   *out = plan->stats;
@@ -580,6 +590,7 @@ rpca_status stream_panels(rpca_plan_s* plan, const float* Ahost, int64_t lda, rp
   RPCA_TRY(hipStreamWaitEvent(cs, plan->ev_free[0], 0));
   // the staging buffers may still be read by the last copies of the previous pass
   if (cb != nullptr) RPCA_TRY(hipStreamSynchronize(cs));
+  const bool on_device = plan->d.source == RPCA_SRC_DEVICE_CALLBACK;
   for (int64_t b = 0; b < np; ++b) {
     const int s = (int)(b & 1);
     const int64_t row0 = b * pr;
@@ -587,7 +598,14 @@ rpca_status stream_panels(rpca_plan_s* plan, const float* Ahost, int64_t lda, rp
     if (b >= 2) RPCA_TRY(hipStreamWaitEvent(cs, plan->ev_free[s], 0));
     const float* src = nullptr;
     int64_t sld = lda;
-    if (cb != nullptr) {
+    if (on_device) {
+      // rows generated in place on the fill stream, after panel b - 2 has released the buffer
+      if (plan->dcb(plan->dcb_user, row0, rows, plan->dbuf[s], ldb, reinterpret_cast<void*>(cs)) != 0) {
+        (void)hipStreamSynchronize(cs);
+        (void)hipStreamSynchronize(st);
+        return RPCA_ERR_CALLBACK;
+      }
+    } else if (cb != nullptr) {
       // the staging buffer's previous copy must be done before the callback refills it
       if (b >= 2) RPCA_TRY(hipEventSynchronize(plan->ev_ready[s]));
       if (cb(user, row0, rows, plan->staging[s], ldb, nullptr) != 0) {
@@ -600,17 +618,19 @@ rpca_status stream_panels(rpca_plan_s* plan, const float* Ahost, int64_t lda, rp
     } else {
       src = Ahost + row0 * lda;
     }
-    if (sld == ldb)
+    if (on_device) {
+    } else if (sld == ldb) {
       RPCA_TRY(hipMemcpyAsync(plan->dbuf[s], src, sizeof(float) * (size_t)(rows * ldb), hipMemcpyHostToDevice, cs));
-    else
+    } else {
       RPCA_TRY(hipMemcpy2DAsync(plan->dbuf[s], sizeof(float) * (size_t)ldb, src, sizeof(float) * (size_t)sld,
                                 sizeof(float) * (size_t)n, (size_t)rows, hipMemcpyHostToDevice, cs));
+    }
     RPCA_TRY(hipEventRecord(plan->ev_ready[s], cs));
     RPCA_TRY(hipStreamWaitEvent(st, plan->ev_ready[s], 0));
     rpca_status r = fn(plan->dbuf[s], ldb, row0, rows);
     if (r != RPCA_OK) return r;
     RPCA_TRY(hipEventRecord(plan->ev_free[s], st));
-    plan->stats.h2d_bytes += rows * n * (int64_t)sizeof(float);
+    if (!on_device) plan->stats.h2d_bytes += rows * n * (int64_t)sizeof(float);
   }
   return RPCA_OK;
 }
@@ -627,6 +647,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   if (U == nullptr || S == nullptr || V == nullptr || ldu < k || ldv < k) return RPCA_ERR_INVALID_ARG;
   if (source == RPCA_SRC_CALLBACK) {
     if (cb == nullptr) return RPCA_ERR_INVALID_ARG;
+  } else if (source == RPCA_SRC_DEVICE_CALLBACK) {
+    if (plan->dcb == nullptr) return RPCA_ERR_INVALID_ARG;
+    cb = nullptr;
   } else {
     if (A == nullptr || lda < n) return RPCA_ERR_INVALID_ARG;
     cb = nullptr;

@@ -11,7 +11,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import check, load, Desc, Stats, STORAGE, SOURCE, STATE, PANEL_CB
+from ._lib import check, load, Desc, Stats, STORAGE, SOURCE, STATE, PANEL_CB, DEVICE_PANEL_CB
 
 _STATE_DTYPE = {"H": torch.float32}
 _STORED_DTYPE = {"bf16": torch.int16, "bf16_hilo": torch.int16, "fp8_e4m3": torch.uint8}
@@ -115,12 +115,26 @@ class Plan:
         source "host_pinned": A is a pinned CPU float32 tensor.  source "callback": A is None and
         panel_fn(row0, nrows, buf) fills buf[:, :n] (a float32 NumPy view of nrows x ld, pinned host
         memory) with rows row0 .. row0 + nrows - 1 and returns nothing (an exception is reported as
-        RPCA_ERR_CALLBACK).
+        RPCA_ERR_CALLBACK).  source "device_callback": A is None and panel_fn(row0, nrows, dst, ld,
+        stream) enqueues on the HIP stream `stream` (an integer handle) device work writing those rows
+        as float32 to the device address `dst` (leading dimension ld) and returns nothing.
         """
         m, n, k = self.m, self.n, self.k
         cb = PANEL_CB()
         data, lda = None, 0
-        if self.source == "callback":
+        if self.source == "device_callback":
+            if panel_fn is None:
+                raise ValueError("a device_callback plan needs panel_fn")
+
+            def _dcb(user, row0, nrows, dst, ld, stream):
+                try:
+                    panel_fn(int(row0), int(nrows), int(dst), int(ld), int(stream or 0))
+                    return 0
+                except Exception:
+                    return 1
+            self._dcb = DEVICE_PANEL_CB(_dcb)  # kept alive with the plan
+            check(self.lib.rpca_set_device_panel_cb(self.handle, self._dcb, None), "rpca_set_device_panel_cb")
+        elif self.source == "callback":
             if panel_fn is None:
                 raise ValueError("a callback plan needs panel_fn")
             import numpy as np

@@ -72,7 +72,27 @@ __global__ void normals_kernel(double* __restrict__ out, uint64_t seed, uint32_t
   if (e < count) out[e] = gauss(seed, stream, start + (uint64_t)e);
 }
 
+// dst[r][c] = src[r][c] for r < rows, c < n
+__global__ __launch_bounds__(256) void copy_rows_kernel(float* __restrict__ dst, int64_t ldd,
+                                                        const float* __restrict__ src, int64_t lds, int64_t rows,
+                                                        int64_t n) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t r = blockIdx.y + (int64_t)blockIdx.z * 65535;
+  if (c >= n || r >= rows) return;
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
 }  // namespace
+
+extern "C" int synth_copy_rows(float* dst, int64_t ldd, const float* src, int64_t lds, int64_t rows, int64_t n,
+                               void* stream) {
+  if (rows <= 0 || n <= 0) return 0;
+  const int64_t gy = rows < 65535 ? rows : 65535;
+  const int64_t gz = (rows + 65534) / 65535;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)gy, (unsigned)gz);
+  hipLaunchKernelGGL(copy_rows_kernel, grid, dim3(256), 0, (hipStream_t)stream, dst, ldd, src, lds, rows, n);
+  return (int)hipGetLastError();
+}
 
 extern "C" int synth_lowrank_noise(float* A, int64_t lda, int64_t rows, int64_t n, int64_t row0, const double* Ur,
                                    int rank, const double* sigma, const double* Vr, double noise, const double* off,

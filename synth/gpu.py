@@ -42,6 +42,8 @@ def load():
         lib.synth_lowrank_noise.restype = i32
         lib.synth_normals.argtypes = [vp, u64, u32, u64, i64, vp]
         lib.synth_normals.restype = i32
+        lib.synth_copy_rows.argtypes = [vp, i64, vp, i64, i64, i64, vp]
+        lib.synth_copy_rows.restype = i32
         _lib = lib
     return _lib
 
@@ -61,6 +63,26 @@ def lowrank_noise_into(A, row0, Ur, sigma, Vr, noise, offsets, seed, noise_strea
         int(noise_stream), _stream())
     if rc != 0:
         raise RuntimeError(f"synth_lowrank_noise failed ({rc})")
+
+
+def lowrank_noise_at(dst, ld, rows, n, row0, Ur, sigma, Vr, noise, offsets, seed, stream, noise_stream=4):
+    """As lowrank_noise_into, for a raw device address `dst` (leading dimension ld) on HIP stream `stream`."""
+    rc = load().synth_lowrank_noise(
+        ctypes.c_void_p(dst), ld, rows, n, row0, ctypes.c_void_p(Ur.data_ptr()), Ur.shape[1],
+        ctypes.c_void_p(sigma.data_ptr()), ctypes.c_void_p(Vr.data_ptr()), float(noise),
+        ctypes.c_void_p(offsets.data_ptr()) if offsets is not None else ctypes.c_void_p(0), int(seed),
+        int(noise_stream), ctypes.c_void_p(stream))
+    if rc != 0:
+        raise RuntimeError(f"synth_lowrank_noise failed ({rc})")
+
+
+def copy_rows_at(dst, ld, src, row0, rows, stream):
+    """Rows [row0, row0+rows) of the device float32 tensor src into the raw device address dst (ld) on `stream`."""
+    n = src.shape[1]
+    rc = load().synth_copy_rows(ctypes.c_void_p(dst), ld, ctypes.c_void_p(src[row0:row0 + rows].data_ptr()),
+                                src.stride(0), rows, n, ctypes.c_void_p(stream))
+    if rc != 0:
+        raise RuntimeError(f"synth_copy_rows failed ({rc})")
 
 
 def normals(out, seed, stream_id, start):

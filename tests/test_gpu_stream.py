@@ -1,5 +1,6 @@
 """Streamed sources (Section 4): A in pinned host memory or produced by a callback, moved to the
-GPU in row panels, one host-link transfer per pass, against the oracle and the in-core path."""
+GPU in row panels, one host-link transfer per pass, or generated on the device panel by panel in
+every pass (Section 4.1), against the oracle and the in-core path."""
 import os
 
 import numpy as np
@@ -48,6 +49,14 @@ def _run(A, k, l, i, G, center, source, panel_rows, ld=None):
         def fill(row0, nrows, buf):
             buf[:, :n] = A[row0:row0 + nrows]
         U, S, V = p.factor(None, G=Gd, panel_fn=fill)
+    elif source == "device_callback":
+        from synth import gpu as SG
+        Ad = torch.from_numpy(A).cuda()
+        torch.cuda.synchronize()
+
+        def fill_dev(row0, nrows, dst, ld, stream):
+            SG.copy_rows_at(dst, ld, Ad, row0, nrows, stream)
+        U, S, V = p.factor(None, G=Gd, panel_fn=fill_dev)
     else:
         U, S, V = p.factor(torch.from_numpy(A).cuda(), G=Gd)
     torch.cuda.synchronize()
@@ -60,6 +69,8 @@ def _run(A, k, l, i, G, center, source, panel_rows, ld=None):
     ("host_pinned", False, 4096, 1040),    # lda > n: pitched copies
     ("callback", False, 8192, None),
     ("callback", True, 16384, None),
+    ("device_callback", False, 8192, None),
+    ("device_callback", True, 16384, None),
 ])
 def test_streamed_parity(source, center, panel_rows, ld):
     _need_gpu()
@@ -77,7 +88,7 @@ def test_streamed_parity(source, center, panel_rows, ld):
     assert du < 1e-4 and dv < 1e-4
     passes = i + 2 + (1 if center else 0)
     assert st["passes"] == passes
-    assert st["h2d_bytes"] == passes * m * n * 4
+    assert st["h2d_bytes"] == (0 if source == "device_callback" else passes * m * n * 4)
 
 
 def test_streamed_matches_in_core():
@@ -105,3 +116,67 @@ def test_callback_error_is_reported():
     with pytest.raises(_lib.RPCAError) as e:
         p.factor(None, panel_fn=fill)
     assert e.value.code == 5  # RPCA_ERR_CALLBACK
+
+
+def test_device_callback_matches_host_pinned():
+    """Rows generated on the device and rows copied from pinned host memory go through the same
+    panel kernels with the same panel boundaries: the results are identical."""
+    _need_gpu()
+    m, n, k, l, i = 30000, 700, 8, 10, 2
+    A = _problem(4200, m, n, False)
+    G = F.gaussian_G(4200, n, l)
+    a = _run(A, k, l, i, G, False, "host_pinned", 5000)
+    b = _run(A, k, l, i, G, False, "device_callback", 5000)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert b[3]["h2d_bytes"] == 0 and b[3]["passes"] == a[3]["passes"]
+
+
+def test_device_regenerated_rows_match_in_core():
+    """Rows regenerated by the seeded device generator in every pass (the on-the-fly mode) against the
+    same matrix generated once and factored in core."""
+    _need_gpu()
+    from synth import gpu as SG
+    from paper_1007_5510_amd import rpca, _lib
+    m, n, r, k, l, i, seed = 40000, 1200, 30, 20, 24, 2, 4300
+    Ur, Vr = F.lowrank_factors(seed, m, n, r)
+    sig = np.exp(-np.arange(1, r + 1, dtype=np.float64) / 10.0)
+    Ur_d = torch.from_numpy(np.ascontiguousarray(Ur)).cuda()
+    Vr_d = torch.from_numpy(np.ascontiguousarray(Vr)).cuda()
+    s_d = torch.from_numpy(sig).cuda()
+    A = torch.empty((m, n), dtype=torch.float32, device="cuda")
+    SG.lowrank_noise_into(A, 0, Ur_d, s_d, Vr_d, 1e-4, None, seed)
+    torch.cuda.synchronize()
+    G = torch.from_numpy(F.gaussian_G(seed, n, l).astype(np.float32)).cuda()
+    p0 = rpca.Plan(m, n, k, l, i)
+    U0, S0, V0 = p0.factor(A, G=G)
+    calls = []
+
+    def gen(row0, nrows, dst, ld, stream):
+        calls.append(row0)
+        SG.lowrank_noise_at(dst, ld, nrows, n, row0, Ur_d, s_d, Vr_d, 1e-4, None, seed, stream)
+    p1 = rpca.Plan(m, n, k, l, i, source="device_callback", panel_rows=6000, flags=_lib.FLAG_PROFILE)
+    U1, S1, V1 = p1.factor(None, G=G, panel_fn=gen)
+    torch.cuda.synchronize()
+    assert len(calls) == (i + 2) * ((m + 5999) // 6000)  # every pass regenerates every panel
+    S0, S1 = S0.cpu().double().numpy(), S1.cpu().double().numpy()
+    assert np.abs(S0 - S1).max() / S0[0] < 1e-6
+    V0, V1 = V0.cpu().double().numpy(), V1.cpu().double().numpy()
+    assert np.linalg.norm(V0 - V1, axis=0).max() < 1e-5
+
+
+def test_device_callback_error_is_reported():
+    _need_gpu()
+    from synth import gpu as SG
+    from paper_1007_5510_amd import rpca, _lib
+    m, n = 20000, 300
+    Ad = torch.ones((m, n), dtype=torch.float32, device="cuda")
+    p = rpca.Plan(m, n, 4, 6, 1, source="device_callback", panel_rows=4096)
+
+    def fill(row0, nrows, dst, ld, stream):
+        if row0 >= 8192:
+            raise RuntimeError("generator failed")
+        SG.copy_rows_at(dst, ld, Ad, row0, nrows, stream)
+    with pytest.raises(_lib.RPCAError) as e:
+        p.factor(None, panel_fn=fill)
+    assert e.value.code == 5  # RPCA_ERR_CALLBACK
+    torch.cuda.synchronize()
