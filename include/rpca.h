@@ -107,7 +107,11 @@ enum {
    * below ~1e-7 of the leading ones.  Step 3 stays on the float32 kernels.
    * UNSUPPORTED with centring, other storage or sources, SPLIT_BF16 or
    * KEEP_STATE.                                                            */
-  RPCA_FLAG_FP64_STEP1 = 1u << 5
+  RPCA_FLAG_FP64_STEP1 = 1u << 5,
+  /* Step 2 by Householder QR (a TSQR reduction tree over row blocks, Q formed
+   * from the reflectors) instead of Cholesky QR; it is otherwise the last
+   * fallback.  Needs L = (i+1) l <= 256 (QR_BREAKDOWN beyond).              */
+  RPCA_FLAG_FORCE_HOUSEHOLDER = 1u << 6
 };
 
 typedef struct {
@@ -163,7 +167,8 @@ typedef struct {
   int64_t a_bytes_read;  /* bytes of A read by the panel kernels (algorithmic) */
   int64_t h2d_bytes;     /* bytes of A moved host -> device (streamed sources) */
   int32_t qr_fallback;   /* Step 2: 0 Cholesky QR twice; 1 shifted Cholesky QR three times;
-                            2 shifted rounds repeated until plain Cholesky QR applies */
+                            2 shifted rounds repeated until plain Cholesky QR applies;
+                            3 Householder TSQR */
   int32_t eig_vectors;   /* eigenvectors computed in Step 4 (k, or L when state is kept) */
   int32_t hip_error;     /* raw hipError_t of the last RPCA_ERR_HIP */
   int32_t passes;        /* full passes over A performed */

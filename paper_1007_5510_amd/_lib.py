@@ -26,6 +26,7 @@ FLAG_FORCE_FALLBACK = 1 << 2
 FLAG_NO_RESCALE = 1 << 3
 FLAG_SPLIT_BF16 = 1 << 4
 FLAG_FP64_STEP1 = 1 << 5
+FLAG_FORCE_HOUSEHOLDER = 1 << 6
 STATE = {"H": 0, "HSCALE": 1, "Q": 2, "T": 3, "SIGMA": 4, "W": 5, "MU": 6, "H64": 7}
 
 

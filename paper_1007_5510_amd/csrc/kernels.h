@@ -142,6 +142,16 @@ hipError_t launch_check_finite_f64(const double* X, int64_t rows, int cols, int6
 void fwd64_split(int64_t m, int64_t n, int ncols, int64_t slots, int* ksplit, int64_t* kchunk);
 void adj64_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);
 
+// ---------------------------------------------------------------- Householder TSQR (qr_householder.hip)
+// Level of the reduction tree: rows_total rows of X (ld L) in nb blocks of bu rows (the last block takes
+// the remainder; every block has >= L rows).  factor: reflectors in place, tau[k L + j], R of block k to
+// Rout + k L L.  apply: Yout rows of block k = Q_k [C_k; 0], C_k = rows [k L, (k+1) L) of Cin (identity
+// when Cin is null).
+hipError_t launch_hh_factor(double* X, int64_t rows_total, int64_t bu, int nb, int L, double* tau, double* Rout,
+                            hipStream_t st);
+hipError_t launch_hh_apply(const double* X, int64_t rows_total, int64_t bu, int nb, int L, const double* tau,
+                           const double* Cin, double* Yout, hipStream_t st);
+
 // ---------------------------------------------------------------- auxiliary
 // FP64 column sums of a row-major matrix in a given storage: part[s][c] over row splits.
 hipError_t launch_colsum(int storage, const void* X, int64_t ld, int64_t rows, int64_t cols,

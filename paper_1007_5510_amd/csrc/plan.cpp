@@ -152,6 +152,19 @@ struct rpca_plan_s {
   const void* A_last = nullptr;  // matrix of the last factorisation (for the backward passes)
   int64_t lda_last = 0;
 
+  // Householder TSQR workspace of Step 2, allocated on first use: per level of
+  // the tree the stacked triangles of the level below (levels >= 1; level 0
+  // works in place on Q1), the reflector scalars, two buffers for the top-down
+  // formation of Q, and the final triangle
+  struct Tsqr {
+    bool ready = false;
+    std::vector<int64_t> rows, bu;
+    std::vector<int> nb;
+    std::vector<double*> X, tau;
+    double* O[2] = {nullptr, nullptr};
+    double* Rtop = nullptr;
+  } tsqr;
+
   // reverse-mode workspace, allocated by the first rpca_backward
   struct Backward {
     bool ready = false;
@@ -571,6 +584,68 @@ rpca_status cholqr_repeated(rpca_plan_s* plan, bool x_f64, const void* H, double
   return RPCA_ERR_QR_BREAKDOWN;
 }
 
+// Step 2 by Householder TSQR (qr_householder.hip): orthonormal to rounding for
+// any H.  Level 0 takes blocks of at least 2L rows (at most 2048 blocks); each
+// higher level stacks the triangles of the level below in pairs.  Supported
+// for L <= 256 (one workgroup per block keeps the block's reflector in LDS).
+rpca_status householder_qr(rpca_plan_s* plan, bool x_f64, const void* H, double** Qout) {
+  const int L = plan->L;
+  const int64_t m = plan->m, LL = (int64_t)L * L;
+  hipStream_t st = plan->stream;
+  auto& t = plan->tsqr;
+  if (L > 256) return RPCA_ERR_QR_BREAKDOWN;
+  if (!t.ready) {
+    int64_t bu0 = (m + 2047) / 2048;
+    if (bu0 < 2 * L) bu0 = 2 * L;
+    int nb0 = (int)(m / bu0);
+    if (nb0 < 1) nb0 = 1;
+    const int64_t last0 = m - (int64_t)(nb0 - 1) * bu0;
+    if ((last0 > bu0 ? last0 : bu0) + 4 * L + 8 > 8192) return RPCA_ERR_QR_BREAKDOWN;  // LDS of one block
+    t.rows.push_back(m);
+    t.bu.push_back(bu0);
+    t.nb.push_back(nb0);
+    while (t.nb.back() > 1) {
+      const int prev = t.nb.back();
+      t.rows.push_back((int64_t)prev * L);
+      t.bu.push_back(2 * (int64_t)L);
+      t.nb.push_back(prev / 2 > 1 ? prev / 2 : 1);
+    }
+    const size_t nl = t.rows.size();
+    t.X.assign(nl, nullptr);
+    t.tau.assign(nl, nullptr);
+    for (size_t q = 0; q < nl; ++q) {
+      if (q > 0 && plan->alloc(&t.X[q], t.rows[q] * L) != hipSuccess) return RPCA_ERR_OUT_OF_MEMORY;
+      if (plan->alloc(&t.tau[q], (int64_t)t.nb[q] * L) != hipSuccess) return RPCA_ERR_OUT_OF_MEMORY;
+    }
+    const int64_t orows = nl > 1 ? t.rows[1] : L;
+    if (plan->alloc(&t.O[0], orows * L) != hipSuccess || plan->alloc(&t.O[1], orows * L) != hipSuccess ||
+        plan->alloc(&t.Rtop, LL) != hipSuccess)
+      return RPCA_ERR_OUT_OF_MEMORY;
+    t.ready = true;
+  }
+  const size_t nl = t.rows.size();
+  // level 0 works on a float64 copy of H in Q1
+  if (x_f64)
+    RPCA_TRY(hipMemcpyAsync(plan->Q1, H, sizeof(double) * (size_t)(m * L), hipMemcpyDeviceToDevice, st));
+  else
+    RPCA_TRY(launch_widen(static_cast<const float*>(H), L, (int)std::min<int64_t>(m, 1 << 30), L, plan->Q1, L, st));
+  t.X[0] = plan->Q1;
+  for (size_t q = 0; q < nl; ++q)
+    RPCA_TRY(launch_hh_factor(t.X[q], t.rows[q], t.bu[q], t.nb[q], L, t.tau[q], q + 1 < nl ? t.X[q + 1] : t.Rtop,
+                              st));
+  // Q = Q_0 (Q_1 (... Q_top [I; 0])), one level at a time from the top
+  const double* C = nullptr;
+  for (size_t q = nl; q-- > 0;) {
+    double* Y = q == 0 ? plan->Q : t.O[q & 1];
+    RPCA_TRY(launch_hh_apply(t.X[q], t.rows[q], t.bu[q], t.nb[q], L, t.tau[q], C, Y, st));
+    C = Y;
+  }
+  RPCA_TRY(launch_to_f32(plan->Q, m, L, L, nullptr, plan->Q32, L, st));
+  RPCA_TRY(hipMemcpyAsync(plan->Rfull, t.Rtop, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
+  *Qout = plan->Q;
+  return RPCA_OK;
+}
+
 }  // namespace
 
 namespace {
@@ -972,8 +1047,10 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const auto t_power = std::chrono::steady_clock::now();
 
   // Step 2: Cholesky QR twice; shifted Cholesky QR three times as the first
-  // fallback, repeated shifted rounds as the second
-  int level = (plan->d.flags & RPCA_FLAG_FORCE_FALLBACK) != 0 ? 1 : 0;
+  // fallback, repeated shifted rounds as the second, Householder TSQR as the
+  // third
+  int level = (plan->d.flags & RPCA_FLAG_FORCE_HOUSEHOLDER) != 0 ? 3
+              : (plan->d.flags & RPCA_FLAG_FORCE_FALLBACK) != 0 ? 1 : 0;
   double* Qfinal = nullptr;
   // With centring every exact block A~ X_j has zero column sums; the float32
   // rounding of H leaves a component along 1 that the conditioning of H would
@@ -982,7 +1059,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const bool x_f64 = center || f64s1;
   const void* Hqr = f64s1 ? static_cast<const void*>(plan->H64)
                           : center ? static_cast<const void*>(plan->Q) : static_cast<const void*>(plan->H);
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  for (int attempt = 0; attempt < 4; ++attempt) {
     RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 3 * sizeof(int), st));
     if (center) {
       RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
@@ -990,8 +1067,21 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       RPCA_TRY(launch_center_cols(plan->H, L, m, L, plan->zsum, 1.0 / (double)m, plan->Q, L, st));
     }
     rpca_status s;
+    if (level == 3) {
+      s = householder_qr(plan, x_f64, Hqr, &Qfinal);
+      if (s != RPCA_OK) return s;
+      int hf0 = 0;
+      RPCA_TRY(hipMemcpyAsync(&hf0, plan->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      RPCA_TRY(hipStreamSynchronize(st));
+      if (hf0 != 0) return RPCA_ERR_NONFINITE;
+      break;
+    }
     if (level == 2) {
       s = cholqr_repeated(plan, x_f64, Hqr, &Qfinal);
+      if (s == RPCA_ERR_QR_BREAKDOWN) {
+        level = 3;
+        continue;
+      }
       if (s != RPCA_OK) return s;
       int hf0 = 0;
       RPCA_TRY(hipMemcpyAsync(&hf0, plan->flags, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1320,7 +1410,7 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   RPCA_TRY(launch_xty(true, b.Qbar, L, L, true, Q, L, L, m, plan->rps_g, plan->ns_g, nullptr, plan->gp, b.M2, st));
   RPCA_TRY(launch_copyltu_neg(b.M2, L, b.Smat, st));
   RPCA_TRY(launch_gemm64(true, Q, L, b.Smat, L, m, L, L, false, nullptr, b.Qbar, L, nullptr, 0, st, b.Qbar, L));
-  if (plan->stats.qr_fallback == 2) {
+  if (plan->stats.qr_fallback >= 2) {
     RPCA_TRY(hipMemcpyAsync(b.Rf, plan->Rfull, sizeof(double) * (size_t)LL, hipMemcpyDeviceToDevice, st));
   } else {
     RPCA_TRY(launch_trmm_upper(plan->R2, plan->R1, L, b.Rf, st));

@@ -171,3 +171,27 @@ def test_backward_full_size_fd():
         print(f"    direction {t}: fd(h) {f1:.9e} fd(h/2) {f2:.9e} extrapolated {fd:.9e} gpu {an:.9e} "
               f"rel {abs(fd - an) / abs(fd):.2e} ({time.time() - t0:.1f}s)", flush=True)
         assert abs(fd - an) <= 1e-4 * abs(fd)
+
+
+def test_backward_after_householder_step2():
+    """The reverse sweep takes Step 2's triangle from whichever QR ran: forcing the Householder TSQR
+    gives the gradient of the Cholesky QR run (same span, same outputs) to 1e-6."""
+    _need_gpu()
+    from paper_1007_5510_amd import rpca, _lib
+    m, n, k, l, i = 2000, 800, 16, 24, 1
+    sigma = 2.0 * 0.95 ** np.arange(n, dtype=np.float64)
+    A32 = F.svd_problem(5160, m, n, sigma)["A"].astype(np.float32)
+    G = F.gaussian_G(5160, n, l)
+    gS, gU, gV = _cotangents(5161, m, n, k)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    out = []
+    for flags in (0, _lib.FLAG_FORCE_HOUSEHOLDER):
+        p = rpca.Plan(m, n, k, l, i, flags=_lib.FLAG_KEEP_STATE | flags)
+        p.factor(t(A32), G=t(G))
+        dA = p.backward(gS=t(gS), gU=t(gU), gV=t(gV))
+        torch.cuda.synchronize()
+        out.append((dA.cpu().double().numpy(), p.stats()["qr_fallback"]))
+    assert out[0][1] == 0 and out[1][1] == 3
+    rel = np.linalg.norm(out[1][0] - out[0][0]) / np.linalg.norm(out[0][0])
+    print(f"  householder vs cholesky QR gradient: {rel:.2e}")
+    assert rel < 1e-6

@@ -114,6 +114,15 @@ def test_f64_reaches_eps0_on_reduced_first_example():
             assert plan.stats()["qr_fallback"] == 2
     assert out["f64"][0] <= 1.1
     assert out["f64"][1] <= 1e-4
+    # Step 2 by the Householder TSQR on the same float64 blocks: the same quality
+    from paper_1007_5510_amd import _lib
+    U, S, V, plan = run_f64(Ah, k, l, i, G, flags=_flag() | _lib.FLAG_FORCE_HOUSEHOLDER)
+    assert plan.stats()["qr_fallback"] == 3
+    eps = plan.residual(A, torch.from_numpy(U.astype(np.float32)).cuda(), torch.from_numpy(S.astype(np.float32)).cuda(),
+                        torch.from_numpy(V.astype(np.float32)).cuda(), j=20, q=k, seed=3)
+    print(f"  f64 + Householder: eps / sigma_(k+1) = {eps / sigma[k]:.4f}")
+    assert eps / sigma[k] <= 1.1
+    assert np.max(np.abs(S - sigma[:k]) / sigma[:k]) <= 1e-4
     # the same matrix through the oracle (float64 throughout)
     orc = O.rpca(Ah, k, l, i, G)
     assert np.max(np.abs(orc.S - sigma[:k]) / sigma[:k]) <= 1e-4

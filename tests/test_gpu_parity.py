@@ -225,3 +225,46 @@ def test_invalid_arguments_on_device():
     with rpca.Plan(500, 200, 5, 6, 1) as p:
         with pytest.raises(_lib.RPCAError):
             p.state("H")  # nothing kept yet
+
+
+def test_householder_step2_parity():
+    """Step 2 by the Householder TSQR (forced): the same factorisation as the oracle, Q orthonormal to
+    float64 rounding, Q R = H with the returned triangle (through the reverse sweep's use of R below)."""
+    from paper_1007_5510_amd import _lib
+    p = F.plain_small(seed=8, m=3000, n=900)
+    k, l, i = 10, 14, 2
+    G = F.gaussian_G(8, 900, l)
+    orc = O.rpca(p["A"], k, l, i, G)
+    g = run_gpu(p["A"], k, l, i, G=G, flags=_lib.FLAG_FORCE_HOUSEHOLDER)
+    compare(g, orc, k)
+    plan = g[3]
+    assert plan.stats()["qr_fallback"] == 3
+    Q = plan.state("Q").cpu().numpy()
+    L = (i + 1) * l
+    assert np.abs(Q.T @ Q - np.eye(L)).max() < 1e-13
+    H = plan.state("H").cpu().double().numpy()
+    Pq = Q @ (Q.T @ H)  # span(Q) = span(H)
+    assert np.linalg.norm(Pq - H) < 1e-12 * np.linalg.norm(H)
+
+
+def test_householder_step2_centered_and_rank_deficient():
+    from paper_1007_5510_amd import _lib
+    m, n, r = 6000, 800, 12
+    sig = 1.0 / np.arange(1, r + 1)
+    p = F.lowrank_noise(31, m, n, r, sig, 1e-3, True)
+    k, l, i = 10, 14, 2
+    G = F.gaussian_G(31, n, l)
+    orc = O.rpca(p["A"], k, l, i, G, center=True)
+    g = run_gpu(p["A"], k, l, i, G=G, center=True, flags=_lib.FLAG_FORCE_HOUSEHOLDER)
+    compare(g, orc, k, n_vec=4)
+    assert g[3].stats()["qr_fallback"] == 3
+    # rank(A) = 5 < L = 12: H numerically rank deficient, Householder completes Q
+    m, n = 800, 300
+    sigma = np.array([5.0, 3.0, 2.0, 1.0, 0.5])
+    U0 = F.haar(9, F.STREAM_U, m, 5)
+    V0 = F.haar(9, F.STREAM_V, n, 5)
+    A = F.to_f32((U0 * sigma) @ V0.T)
+    U, S, V, plan = run_gpu(A, 4, 6, 1, G=F.gaussian_G(9, n, 6), flags=_lib.FLAG_FORCE_HOUSEHOLDER)
+    assert plan.stats()["qr_fallback"] == 3
+    assert np.abs(S - sigma[:4]).max() / 5.0 < 1e-5
+    assert abs(O.residual_exact(A, U, S, V) - 0.5) < 1e-5
