@@ -58,6 +58,7 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
   const uint16_t* Zh = nullptr;
   const uint16_t* Zl = nullptr;
   int64_t ldzs = 0;
+  int cpad_z = 0;  // rows of the Z planes (>= every Z column the kernel's tiles read)
   int64_t plane = 0;
   // float32 A on bfloat16 matrix cores: Z transposed and split into three
   // bfloat16 planes (cpad x ldzs3 each, zplane3 elements apart)

@@ -447,8 +447,9 @@ __global__ __launch_bounds__(256) void fwd_lp_reduce_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// adjoint: a wave owns 32 columns of A and 64 columns of Z (two tiles); a
-// workgroup of W waves 32 W columns of A.  Stage = 64 rows (two 32-row
+// adjoint: a wave owns 32 columns of A and 32 ZT columns of Z (ZT tiles: 2 for
+// the power steps, 6 for a wide Z such as the T pass, so that A is read once
+// for up to 192 Z columns); a workgroup of W waves 32 W columns of A.  Stage = 64 rows (two 32-row
 // halves).  Lane i + 32 g loads columns 16 g .. 16 g + 15 of row i of a half;
 // after the transposing MFMAs lane j + 32 h holds tile column
 //   cmap(j) = 16 ((j % 16) / 8) + 8 (j / 16) + j % 8
@@ -458,15 +459,33 @@ __global__ __launch_bounds__(256) void fwd_lp_reduce_kernel(const float* __restr
 // ---------------------------------------------------------------------------
 constexpr int LA_RS = 64;
 
-template <int ST>
+// Z tiles per wave for a product with ncols columns of Z, and the ring depth:
+// six tiles leave LDS for two stages only (their loads then wait a full stage)
+constexpr int lp_zt(int ncols) { return ncols > 64 ? 6 : 2; }
+template <int ST, int ZT>
+struct LpAdjCfg {
+  static constexpr int NB = ZT == 2 ? LpCfg<ST>::NB : 2;
+  static constexpr int SX = ZT * 8192;                        // Z bytes per stage (2 planes x 32 ZT x 64 rows)
+  static constexpr int XQ = 8 * ZT / LpCfg<ST>::W;            // Z loads per lane per stage
+  static constexpr int P = LpCfg<ST>::AQ + XQ;
+  static constexpr int LDS = NB * (SX + LpCfg<ST>::W * LpCfg<ST>::SA);
+  static constexpr bool FOLD = ZT == 2;                       // second float32 level (registers allow it)
+  static_assert((8 * ZT) % LpCfg<ST>::W == 0, "Z loads must divide evenly over the waves");
+  static_assert(LDS <= 163840, "ring exceeds the LDS of a workgroup");
+};
+
+template <int ST, int ZT>
 __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
     const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, int64_t plane,
     const uint16_t* __restrict__ Zh, const uint16_t* __restrict__ Zl, int64_t ldzs, int ncols,
     int64_t rows_per_split, int jtiles, int ctiles, int nsplit, float* __restrict__ P, int64_t ldp,
     int64_t split_stride) {
   using C = LpCfg<ST>;
-  constexpr int ES = C::ES, W = C::W, NB = C::NB, SA = C::SA, AQ = C::AQ, XQ = C::XQ, PQ = C::P, SX = C::SX;
-  constexpr int HQ = AQ / 2;  // A loads per 32-row half
+  using D = LpAdjCfg<ST, ZT>;
+  constexpr int ES = C::ES, W = C::W, SA = C::SA, AQ = C::AQ;
+  constexpr int NB = D::NB, XQ = D::XQ, PQ = D::P, SX = D::SX;
+  constexpr int ZPL = SX / 2;  // bytes of one Z plane in a stage
+  constexpr int HQ = AQ / 2;   // A loads per 32-row half
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const int64_t total = (int64_t)jtiles * ctiles * nsplit;
   const int64_t logical = xcd_remap_lp(blockIdx.x, total);
@@ -479,7 +498,7 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, g = lane >> 5;
   const int64_t cw = (int64_t)ct * (32 * W) + wave * 32;
-  const int j0 = jt * 64;
+  const int j0 = jt * 32 * ZT;
   const int64_t rbeg = (int64_t)sp * rows_per_split;
   const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
   const int64_t plane_bytes = plane * ES;
@@ -502,14 +521,15 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
         E2[e >> 1] = one;
     }
   }
-  // shared Z loads of this wave: instruction j covers plane j/8, Z columns 8 (j%8) .. +7
+  // shared Z loads of this wave: instruction j covers plane j / (4 ZT), Z columns
+  // 8 (j % (4 ZT)) .. +7
   const uint16_t* zsrc[XQ];
 #pragma unroll
   for (int q = 0; q < XQ; ++q) {
     const int j = wave * XQ + q;
-    const int col = 8 * (j & 7) + (lane >> 3);
+    const int col = 8 * (j % (4 * ZT)) + (lane >> 3);
     const int c = (lane & 7) ^ (col & 7);
-    zsrc[q] = ((j >> 3) ? Zl : Zh) + (int64_t)(j0 + col) * ldzs + 8 * c;
+    zsrc[q] = ((j / (4 * ZT)) ? Zl : Zh) + (int64_t)(j0 + col) * ldzs + 8 * c;
   }
   // rows past m read row m-1 (finite) against zero Z rows
   const int64_t nfull = rend > rbeg ? (rend - rbeg + LA_RS - 1) / LA_RS : 0;
@@ -537,17 +557,18 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
     }
   };
 
-  floatx16 acc[2], acc2[2];
+  floatx16 acc[ZT], acc2[D::FOLD ? ZT : 1];
 #pragma unroll
-  for (int zt = 0; zt < 2; ++zt)
+  for (int zt = 0; zt < ZT; ++zt)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       acc[zt][v] = 0.f;
-      acc2[zt][v] = 0.f;
+      if (D::FOLD) acc2[zt][v] = 0.f;
     }
   auto fold = [&]() {
+    if (!D::FOLD) return;
 #pragma unroll
-    for (int zt = 0; zt < 2; ++zt) {
+    for (int zt = 0; zt < ZT; ++zt) {
       acc2[zt] += acc[zt];
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[zt][v] = 0.f;
@@ -583,12 +604,12 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
 #pragma unroll
-      for (int zt = 0; zt < 2; ++zt) {
+      for (int zt = 0; zt < ZT; ++zt) {
         const int col = 32 * zt + li;
         const u32x4 zah = ld16(zs + swz(col, 4 * h + g));
         const u32x4 zbh = ld16(zs + swz(col, 4 * h + 2 + g));
-        const u32x4 zal = ld16(zs + 8192 + swz(col, 4 * h + g));
-        const u32x4 zbl = ld16(zs + 8192 + swz(col, 4 * h + 2 + g));
+        const u32x4 zal = ld16(zs + ZPL + swz(col, 4 * h + g));
+        const u32x4 zbl = ld16(zs + ZPL + swz(col, 4 * h + 2 + g));
         acc[zt] = mfma_bf16(oa[h], zah, acc[zt]);
         acc[zt] = mfma_bf16(ob[h], zbh, acc[zt]);
         acc[zt] = mfma_bf16(oa[h], zal, acc[zt]);
@@ -632,14 +653,15 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
 
   float* __restrict__ Ps = P + (int64_t)sp * split_stride;
 #pragma unroll
-  for (int zt = 0; zt < 2; ++zt) {
+  for (int zt = 0; zt < ZT; ++zt) {
     const int j = j0 + 32 * zt + li;
     if (j >= ncols) continue;
     float* __restrict__ prow = Ps + (int64_t)j * ldp;
+    const floatx16& r = D::FOLD ? acc2[D::FOLD ? zt : 0] : acc[zt];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t c = cw + 16 * (q & 1) + 8 * (q >> 1) + 4 * g;
-      const floatx4 o = {acc2[zt][4 * q], acc2[zt][4 * q + 1], acc2[zt][4 * q + 2], acc2[zt][4 * q + 3]};
+      const floatx4 o = {r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
       if (c + 3 < n) {
         *reinterpret_cast<floatx4*>(prow + c) = o;
       } else {
@@ -713,14 +735,16 @@ hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int ST>
+template <int ST, int ZT>
 static void launch_adj_lp_t(const AdjArgs& a, int jtiles, hipStream_t st) {
   using C = LpCfg<ST>;
   const int ctiles = (int)((a.n + 32 * C::W - 1) / (32 * C::W));
   const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
-  hipLaunchKernelGGL((adj_lp_kernel<ST>), dim3((unsigned)total), dim3(64 * C::W), C::LDS, st, a.A, a.lda, a.m, a.n,
-                     a.plane, a.Zh, a.Zl, a.ldzs, a.ncols, a.rows_per_split, jtiles, ctiles, a.nsplit, a.P, a.ldp,
-                     a.split_stride);
+  using D = LpAdjCfg<ST, ZT>;
+  constexpr size_t lds = D::LDS;
+  hipLaunchKernelGGL((adj_lp_kernel<ST, ZT>), dim3((unsigned)total), dim3(64 * C::W), lds, st,
+                     a.A, a.lda, a.m, a.n, a.plane, a.Zh, a.Zl, a.ldzs, a.ncols, a.rows_per_split, jtiles, ctiles,
+                     a.nsplit, a.P, a.ldp, a.split_stride);
 }
 
 hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st) {
@@ -731,12 +755,18 @@ hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st) {
   if ((int64_t)a.nsplit * a.rows_per_split < a.m || a.ldzs % LA_RS != 0 || a.ldzs < a.m)
     return hipErrorInvalidValue;
   if (storage == ST_HILO && a.plane < a.m * a.lda) return hipErrorInvalidValue;
-  const int jtiles = (a.ncols + 63) / 64;
+  const int zt = lp_zt(a.ncols);
+  const int jtiles = (a.ncols + 32 * zt - 1) / (32 * zt);
+  // the Z planes must hold every column the tiles read
+  if (a.cpad_z < jtiles * 32 * zt) return hipErrorInvalidValue;
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
-  switch (storage) {
-    case ST_BF16: launch_adj_lp_t<ST_BF16>(a, jtiles, st); break;
-    case ST_FP8: launch_adj_lp_t<ST_FP8>(a, jtiles, st); break;
-    case ST_HILO: launch_adj_lp_t<ST_HILO>(a, jtiles, st); break;
+  switch (storage * 8 + zt) {
+    case ST_BF16 * 8 + 2: launch_adj_lp_t<ST_BF16, 2>(a, jtiles, st); break;
+    case ST_BF16 * 8 + 6: launch_adj_lp_t<ST_BF16, 6>(a, jtiles, st); break;
+    case ST_FP8 * 8 + 2: launch_adj_lp_t<ST_FP8, 2>(a, jtiles, st); break;
+    case ST_FP8 * 8 + 6: launch_adj_lp_t<ST_FP8, 6>(a, jtiles, st); break;
+    case ST_HILO * 8 + 2: launch_adj_lp_t<ST_HILO, 2>(a, jtiles, st); break;
+    case ST_HILO * 8 + 6: launch_adj_lp_t<ST_HILO, 6>(a, jtiles, st); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -774,7 +804,8 @@ void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit,
 void adj_split_lp(int storage, int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit,
                   int64_t* rows_per_split) {
   const int64_t cols = 32 * lp_waves(storage);
-  const int64_t per = (int64_t)((ncols + 63) / 64) * ((n + cols - 1) / cols);
+  const int ztc = 32 * lp_zt(ncols);
+  const int64_t per = (int64_t)((ncols + ztc - 1) / ztc) * ((n + cols - 1) / cols);
   int64_t lo = (2 * slots + per - 1) / per;
   int64_t hi = lo * 4 + 8;
   const int64_t maxs = m / 128 > 0 ? m / 128 : 1;

@@ -322,7 +322,7 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     plan->ldxs = round_up(n, 64);
     plan->cpad_x = (int)round_up(l, 64);
     plan->ldzs = round_up(m, 64);
-    plan->cpad_z = (int)round_up(L, 64);
+    plan->cpad_z = (int)round_up(L, L > 64 ? 192 : 64);  // whole Z tiles of the adjoint
   } else {
     adj_split(m, n, l, slots, &plan->ns_y, &plan->rps_y);
     adj_split(m, n, L, slots, &plan->ns_t, &plan->rps_t);
@@ -1014,6 +1014,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.Zh = plan->Zh;
       aa.Zl = plan->Zl;
       aa.ldzs = plan->ldzs;
+      aa.cpad_z = plan->cpad_z;
       aa.plane = plane;
       RPCA_TRY(launch_adj_lowp(storage, aa, st));
     } else if (x6) {
@@ -1175,6 +1176,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.Zh = plan->Zh;
       aa.Zl = plan->Zl;
       aa.ldzs = plan->ldzs;
+      aa.cpad_z = plan->cpad_z;
       aa.plane = plane;
       RPCA_TRY(launch_adj_lowp(storage, aa, st));
     } else if (x6) {
