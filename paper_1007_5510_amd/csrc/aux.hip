@@ -296,6 +296,26 @@ hipError_t launch_pass0_center(const float* P, int nsplit, int64_t split_stride,
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void pass0_mean_lp_kernel(const float* __restrict__ P, int nsplit,
+                                                            int64_t split_stride, int64_t ldp, int row, int64_t n,
+                                                            double inv_m, const float* __restrict__ cs,
+                                                            double* __restrict__ mu) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  double v = 0.0;
+  const float* p = P + (int64_t)row * ldp + c;
+  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  if (cs != nullptr) v *= (double)cs[c];
+  mu[c] = v * inv_m;
+}
+
+hipError_t launch_pass0_mean_lp(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int row, int64_t n,
+                                int64_t m, const float* cs, double* mu, hipStream_t st) {
+  hipLaunchKernelGGL(pass0_mean_lp_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, P, nsplit,
+                     split_stride, ldp, row, n, 1.0 / (double)m, cs, mu);
+  return hipGetLastError();
+}
+
 // X[r][c] -= corr[c] (float32, rows x cols)
 __global__ void sub_cols_kernel(float* __restrict__ X, int64_t ldx, int64_t rows, int cols,
                                 const float* __restrict__ corr) {

@@ -92,7 +92,7 @@ hipError_t launch_split_x(const float* Xt, int64_t ldx, int64_t n, int ncols, co
                           uint16_t* Xh, uint16_t* Xl, int64_t ldxs, int cpad, hipStream_t st);
 // transposed, row-permuted hi/lo bfloat16 planes of Z: cpad x ldzs (ldzs % 32 == 0)
 hipError_t launch_split_zt(const float* Z, int64_t ldz, int64_t m, int ncols, uint16_t* Zh, uint16_t* Zl,
-                           int64_t ldzs, int cpad, hipStream_t st);
+                           int64_t ldzs, int cpad, hipStream_t st, bool ones = false);
 // quantisers of the stored formats (see rpca_quantize)
 hipError_t launch_quantize(int storage, int64_t m, int64_t n, const float* A, int64_t lda, const float* shift,
                            void* out, int64_t ldo, float* col_scale, float* amax_part, int nsplit,
@@ -190,6 +190,10 @@ hipError_t launch_accumulate_parts(bool f64, const void* part, int nsplit, int64
                                    int64_t cols, int64_t ld, double* acc, hipStream_t st);
 // centring fused into pass 0: d0 = colsum(A - 1 s0^T)/m from row `row` of the adjoint partials,
 // mu = s0 + d0, shift <- fl32(mu), dres = mu - fl32(mu)
+// low-precision storage: mu[c] = cs[c] (cs null: 1) * sum_s P[s][row][c] / m, the column means of
+// the stored matrix from the column sums an implicit ones column left in row `row` of the partials
+hipError_t launch_pass0_mean_lp(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int row, int64_t n,
+                                int64_t m, const float* cs, double* mu, hipStream_t st);
 hipError_t launch_pass0_center(const float* P, int nsplit, int64_t split_stride, int64_t ldp, int row, int64_t n,
                                int64_t m, float* shift, double* d0, double* mu, double* dres, hipStream_t st);
 // X[r][c] -= corr[c]

@@ -130,9 +130,11 @@ RPCA_DEV int zperm_row(int p) {
   return 16 * (u >> 1) + 8 * (e >> 2) + 4 * (u & 1) + (e & 3);
 }
 
-// Zh/Zl[j][32 b + p] = hi/lo of Z[32 b + zperm_row(p)][j] (0 outside m x ncols)
+// Zh/Zl[j][32 b + p] = hi/lo of Z[32 b + zperm_row(p)][j] (0 outside m x ncols);
+// with `ones`, column ncols is an implicit column of ones (its product gives the
+// column sums of A)
 __global__ __launch_bounds__(256) void split_zt_kernel(const float* __restrict__ Z, int64_t ldz, int64_t m,
-                                                       int ncols, uint16_t* __restrict__ Zh,
+                                                       int ncols, int ones, uint16_t* __restrict__ Zh,
                                                        uint16_t* __restrict__ Zl, int64_t ldzs) {
   __shared__ float tile[32][65];
   const int tid = threadIdx.x;
@@ -144,6 +146,7 @@ __global__ __launch_bounds__(256) void split_zt_kernel(const float* __restrict__
     const int r = e >> 6, c = e & 63;
     float v = 0.f;
     if (rb + r < m && j0 + c < ncols) v = Z[(rb + r) * ldz + j0 + c];
+    if (rb + r < m && ones && j0 + c == ncols) v = 1.f;
     tile[r][c] = v;
   }
   __syncthreads();
@@ -689,10 +692,10 @@ hipError_t launch_split_x(const float* Xt, int64_t ldx, int64_t n, int ncols, co
 }
 
 hipError_t launch_split_zt(const float* Z, int64_t ldz, int64_t m, int ncols, uint16_t* Zh, uint16_t* Zl,
-                           int64_t ldzs, int cpad, hipStream_t st) {
-  if (ldzs % 32 != 0 || ldzs < m || cpad % 64 != 0 || cpad < ncols) return hipErrorInvalidValue;
+                           int64_t ldzs, int cpad, hipStream_t st, bool ones) {
+  if (ldzs % 32 != 0 || ldzs < m || cpad % 64 != 0 || cpad < ncols + (ones ? 1 : 0)) return hipErrorInvalidValue;
   dim3 grid((unsigned)(ldzs / 32), (unsigned)(cpad / 64));
-  hipLaunchKernelGGL(split_zt_kernel, grid, dim3(256), 0, st, Z, ldz, m, ncols, Zh, Zl, ldzs);
+  hipLaunchKernelGGL(split_zt_kernel, grid, dim3(256), 0, st, Z, ldz, m, ncols, ones ? 1 : 0, Zh, Zl, ldzs);
   return hipGetLastError();
 }
 

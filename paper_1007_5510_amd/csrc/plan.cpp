@@ -766,8 +766,9 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const float* shift = plan->shift;
   const double* dres = nullptr;
   // Low-precision storage has no in-register shift: d is the whole mean.
-  // In-core float32 folds the column means into pass 0 (no separate pass).
-  const bool fuse0 = center && !streamed && !lowp && i >= 1;
+  // In-core storage folds the column sums into pass 0's adjoint (no separate
+  // pass over A).
+  const bool fuse0 = center && !streamed && i >= 1;
   if (center && streamed) {
     // a streamed pass of column sums (float64, accumulated over the panels)
     RPCA_TRY(launch_fill_f64(plan->acc, n, 0.0, st));
@@ -782,14 +783,16 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
   } else if (fuse0) {
-    // shift of pass 0: the column means of the first row panel
-    const int64_t rows0 = m < 4096 ? m : 4096;
-    int ns0 = 1;
-    int64_t rps0 = 0;
-    choose_rows(rows0, 1024, 64, &ns0, &rps0);
-    RPCA_TRY(launch_colsum(ST_F32, A, lda, rows0, n, nullptr, 0, rps0, ns0, plan->csp, st));
-    RPCA_TRY(launch_colsum_reduce(plan->csp, ns0, n, 1.0 / (double)rows0, plan->mu, plan->shift, nullptr, st));
-    sx.a_bytes_read += rows0 * n * bpe;
+    if (!lowp) {
+      // shift of pass 0: the column means of the first row panel
+      const int64_t rows0 = m < 4096 ? m : 4096;
+      int ns0 = 1;
+      int64_t rps0 = 0;
+      choose_rows(rows0, 1024, 64, &ns0, &rps0);
+      RPCA_TRY(launch_colsum(ST_F32, A, lda, rows0, n, nullptr, 0, rps0, ns0, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, ns0, n, 1.0 / (double)rows0, plan->mu, plan->shift, nullptr, st));
+      sx.a_bytes_read += rows0 * n * bpe;
+    }
   } else if (center) {
     RPCA_TRY(launch_colsum(storage, A, lda, m, n, cs, plane, plan->rps_cs, plan->ns_cs, plan->csp, st));
     if (lowp) {
@@ -1010,12 +1013,14 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       aa.ev_end = ev->b;
     }
     if (lowp) {
-      RPCA_TRY(launch_split_zt(aa.Z, L, m, l, plan->Zh, plan->Zl, plan->ldzs, plan->cpad_z, st));
+      // pass 0: an implicit ones column after the l columns of Z gives the column sums
+      RPCA_TRY(launch_split_zt(aa.Z, L, m, l, plan->Zh, plan->Zl, plan->ldzs, plan->cpad_z, st, p0));
       aa.Zh = plan->Zh;
       aa.Zl = plan->Zl;
       aa.ldzs = plan->ldzs;
       aa.cpad_z = plan->cpad_z;
       aa.plane = plane;
+      if (p0) aa.ncols = l + 1;
       RPCA_TRY(launch_adj_lowp(storage, aa, st));
     } else if (x6) {
       RPCA_TRY(launch_split3_zt(aa.Z, L, m, l, p0, (int)round_up(l + 1, 64), plan->Zp3, plan->ldzs3, plan->zplane3,
@@ -1027,19 +1032,24 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     } else {
       RPCA_TRY(launch_adj_f32(aa, st));
     }
-    if (p0) {
+    if (p0 && lowp) {
+      // mu = column sums / m of the stored matrix; the rank-one correction uses all of it
+      RPCA_TRY(launch_pass0_mean_lp(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, m, cs, plan->mu, st));
+      dres = plan->mu;
+    } else if (p0) {
       // d0 = colsum(A - 1 s0^T)/m; the later passes shift by fl32(s0 + d0)
       RPCA_TRY(launch_pass0_center(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, m, plan->shift, plan->d0,
                                    plan->mu, plan->dres, st));
       dres = plan->dres;
     }
+    const double* d0 = lowp ? plan->mu : plan->d0;  // pass 0's correction (s0 = 0 in low precision)
     float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
     int npart = 0;
     // X_1 = (A - 1 s0^T)^T Z - d0 (1^T Z)^T with Z the uncorrected block (exact: colsum(A - 1 s0^T) = m d0)
-    RPCA_TRY(launch_reduce_y(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, cs, p0 ? plan->d0 : dres,
+    RPCA_TRY(launch_reduce_y(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, cs, p0 ? d0 : dres,
                              center ? plan->zsum : nullptr, Xn, ldx, plan->sqp, &npart, st));
     if (p0) {  // H^(0) = (A - 1 s0^T) G - 1 (d0^T G)  (block scale 1)
-      RPCA_TRY(launch_dot_rows(plan->d0, Xj, ldx, n, l, plan->corr, st));
+      RPCA_TRY(launch_dot_rows(d0, Xj, ldx, n, l, plan->corr, st));
       RPCA_TRY(launch_sub_cols(plan->H, L, m, l, plan->corr, st));
     }
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));

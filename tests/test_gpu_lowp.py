@@ -165,8 +165,10 @@ def test_lowp_ragged_centered(storage):
     orc = O.rpca(Aq, k, l, i, G, center=True)
     g = _run(st, k, l, i, G, center=True)
     _compare(g, orc, k, n_vec=4)
+    # the column sums come from pass 0's adjoint (an implicit ones column: float32 chains per row
+    # split, float64 across splits), the accumulation of the float32-storage path, same bound
     mu = g[3].state("MU").cpu().numpy()
-    assert np.abs(mu - Aq.mean(axis=0)).max() <= 1e-12 * np.abs(Aq).max()
+    assert np.abs(mu - Aq.mean(axis=0)).max() <= 1e-9 * np.abs(Aq).max()
 
 
 @pytest.mark.parametrize("storage", STORAGES)

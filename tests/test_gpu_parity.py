@@ -268,3 +268,22 @@ def test_householder_step2_centered_and_rank_deficient():
     assert plan.stats()["qr_fallback"] == 3
     assert np.abs(S - sigma[:4]).max() / 5.0 < 1e-5
     assert abs(O.residual_exact(A, U, S, V) - 0.5) < 1e-5
+
+
+def test_block_rescale_keeps_large_matrices_finite():
+    """Section 3's overflow remark: with ||A|| = 1e10 and i = 3 the unscaled powers reach ~1e70,
+    far past float32; the positive block rescale keeps every iterate finite and the factorisation
+    scales exactly, while RPCA_FLAG_NO_RESCALE reports the overflow.  (A block X_j enters its
+    forward product before its scale, so the float32 path needs ||A||^3 well inside float32.)"""
+    from paper_1007_5510_amd import _lib
+    p = F.plain_small(seed=21, m=2000, n=1000)
+    A = F.to_f32(p["A"].astype(np.float64) * 1e10)
+    k, l, i = 8, 10, 3
+    G = F.gaussian_G(21, 1000, l)
+    orc = O.rpca(A, k, l, i, G)
+    g = run_gpu(A, k, l, i, G=G)
+    compare(g, orc, k)
+    assert np.all(np.isfinite(g[0])) and np.all(np.isfinite(g[2]))
+    with pytest.raises(_lib.RPCAError) as e:
+        run_gpu(A, k, l, i, G=G, flags=_lib.FLAG_NO_RESCALE)
+    assert e.value.code == 6  # RPCA_ERR_NONFINITE
