@@ -465,9 +465,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path "
-              f"(asked for --gpus {args.gpus}, WORLD_SIZE {world}); the row-panel sharding design is described "
-              f"in DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE {world}); across GPUs the rows of A would be sharded by row panels, with one all-reduce "
+              f"of each adjoint product and of each Gram matrix", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "stream":

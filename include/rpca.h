@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   RPCA_OK = 0,
   RPCA_ERR_INVALID_ARG = 1,   /* a precondition below is violated */
-  RPCA_ERR_UNSUPPORTED = 2,   /* valid request this build does not implement */
+  RPCA_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
   RPCA_ERR_OUT_OF_MEMORY = 3, /* workspace allocation failed */
   RPCA_ERR_HIP = 4,           /* a HIP runtime call failed; code in rpca_stats.hip_error */
   RPCA_ERR_CALLBACK = 5,      /* the panel callback returned non-zero */
@@ -110,12 +110,15 @@ enum {
   RPCA_FLAG_FP64_STEP1 = 1u << 5,
   /* Step 2 by Householder QR (a TSQR reduction tree over row blocks, Q formed
    * from the reflectors) instead of Cholesky QR; it is otherwise the last
-   * fallback.  Needs L = (i+1) l <= 256 (QR_BREAKDOWN beyond).              */
+   * fallback.  Needs L = (i+1) l <= 256 (QR_BREAKDOWN beyond).  The first
+   * Householder Step 2 of a plan allocates the tree's workspace (about
+   * 4 L^2 doubles per level-0 block, at most 2048 blocks), kept until
+   * rpca_destroy; OUT_OF_MEMORY if that fails.                             */
   RPCA_FLAG_FORCE_HOUSEHOLDER = 1u << 6
 };
 
 typedef struct {
-  int64_t m, n;        /* A is m x n; this build requires m >= n (Section 3 assumes n <= m) */
+  int64_t m, n;        /* A is m x n; the library requires m >= n (Section 3 assumes n <= m) */
   int32_t k;           /* rank of the approximation, 1 <= k < n */
   int32_t l;           /* block width, l >= k */
   int32_t i;           /* power steps, i >= 0, with (i+1) l <= n - k (Section 3) */
