@@ -96,7 +96,7 @@ enum {
    * matrix that is not 16-byte aligned with lda % 4 == 0 uses the float32
    * matrix-core kernels instead.                                              */
   RPCA_FLAG_SPLIT_BF16 = 1u << 4,
-  /* float32 A only, DEVICE source, no centring: carry Step 1 (the blocks
+  /* float32 A only, DEVICE source: carry Step 1 (the blocks
    * H^(0..i) of eqs. first_prod .. last_prod and the products A^T H^(j)) in
    * float64 on the FP64 matrix cores, each float32 entry of A exact in
    * float64, and keep H in float64 for Step 2 -- the arithmetic of the
@@ -104,9 +104,10 @@ enum {
    * double, Section 5).  Needed when the spectrum spans a wide range above
    * sigma_{k+1} and has a long, heavy tail, as in the paper's first example:
    * float32 products then lose the directions that the later blocks carry
-   * below ~1e-7 of the leading ones.  Step 3 stays on the float32 kernels.
-   * UNSUPPORTED with centring, other storage or sources, SPLIT_BF16 or
-   * KEEP_STATE.                                                            */
+   * below ~1e-7 of the leading ones.  Centring enters as exact float64
+   * rank-one corrections with the column means of a separate float64
+   * column-sum pass.  Step 3 stays on the float32 kernels.  UNSUPPORTED with
+   * other storage or sources, SPLIT_BF16 or KEEP_STATE.                     */
   RPCA_FLAG_FP64_STEP1 = 1u << 5,
   /* Step 2 by Householder QR (a TSQR reduction tree over row blocks, Q formed
    * from the reflectors) instead of Cholesky QR; it is otherwise the last

@@ -110,6 +110,7 @@ struct Fwd64Args {             // Z = alpha A Xt^T, float32 A, float64 X and Z
   int64_t ldx = 0;
   int ncols = 0;
   const double* alpha = nullptr;  // device scalar or null
+  const double* corr = nullptr;   // ncols or null: Z = alpha (A Xt^T - 1 corr^T)
   double* Z = nullptr;
   int64_t ldz = 0;
   bool vec = false;            // A 16-byte aligned and lda % 4 == 0
@@ -136,9 +137,17 @@ struct Adj64Args {             // P_s = (A_s^T Z_s)^T, float32 A, float64 Z and 
 
 hipError_t launch_fwd64(const Fwd64Args& a, hipStream_t st);
 hipError_t launch_adj64(const Adj64Args& a, hipStream_t st);
-// Xt[j][c] = sum_s P[s][j][c] in float64; per-block sums of squares into sq_part
+// Xt[j][c] = sum_s P[s][j][c] - d[c] zsum[j] (d, zsum null: no correction) in float64; per-block sums of
+// squares into sq_part
 hipError_t launch_reduce_x64(const double* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                             double* Xt, int64_t ldx, double* sq_part, int* n_sq_part, hipStream_t st);
+                             const double* d, const double* zsum, double* Xt, int64_t ldx, double* sq_part,
+                             int* n_sq_part, hipStream_t st);
+// corr[j] = sum_c d[c] Xt[j][c] (float64 X)
+hipError_t launch_dot_rows64(const double* d, const double* Xt, int64_t ldx, int64_t n, int ncols, double* corr,
+                             hipStream_t st);
+// part[s][c] = sum over rows of split s of X[r][c] (float64 X, rows x cols, ld)
+hipError_t launch_colsum_f64(const double* X, int64_t ld, int64_t rows, int cols, int64_t rows_per_split,
+                             int nsplit, double* part, hipStream_t st);
 hipError_t launch_check_finite_f64(const double* X, int64_t rows, int cols, int64_t ld, int* flag, hipStream_t st);
 void fwd64_split(int64_t m, int64_t n, int ncols, int64_t slots, int* ksplit, int64_t* kchunk);
 void adj64_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);

@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256, 2) void fwd64_kernel(const float* __restrict__
                                                        int64_t n, const double* __restrict__ Xt, int64_t ldx,
                                                        int ncols, int64_t kchunk,
                                                        const double* __restrict__ alpha_ptr,
-                                                       double* __restrict__ Z, int64_t ldz, int64_t split_stride,
-                                                       int direct) {
+                                                       const double* __restrict__ corr, double* __restrict__ Z,
+                                                       int64_t ldz, int64_t split_stride, int direct) {
   constexpr int RT = F64_RT, KST = F64_KST;
   constexpr int NC = 16 * CT;          // columns of X per block
   constexpr int XP = KST + 2;          // padded LDS row (doubles)
@@ -201,18 +201,20 @@ __global__ __launch_bounds__(256, 2) void fwd64_kernel(const float* __restrict__
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const int col = c0 + 16 * c + li;
+      const double cr = (direct && corr != nullptr && col < ncols) ? corr[col] : 0.0;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = r0 + 16 * r + 4 * v + g;
-        if (row < m && col < ncols) out[row * ldz + col] = al * acc[r][c][v];
+        if (row < m && col < ncols) out[row * ldz + col] = direct ? al * (acc[r][c][v] - cr) : acc[r][c][v];
       }
     }
 }
 
-// Z[r][c] = alpha * sum_s P[s][r][c], splits summed in order
+// Z[r][c] = alpha * (sum_s P[s][r][c] - corr[c]), splits summed in order
 __global__ __launch_bounds__(256) void fwd64_reduce_kernel(const double* __restrict__ P, int nsplit,
                                                            int64_t split_stride, int64_t ldp, int64_t m, int ncols,
                                                            const double* __restrict__ alpha_ptr,
+                                                           const double* __restrict__ corr,
                                                            double* __restrict__ Z, int64_t ldz) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= m * ncols) return;
@@ -220,6 +222,7 @@ __global__ __launch_bounds__(256) void fwd64_reduce_kernel(const double* __restr
   const int c = (int)(e % ncols);
   double v = 0.0;
   for (int s = 0; s < nsplit; ++s) v += P[(int64_t)s * split_stride + r * ldp + c];
+  if (corr != nullptr) v -= corr[c];
   Z[r * ldz + c] = (alpha_ptr != nullptr ? *alpha_ptr : 1.0) * v;
 }
 
@@ -358,11 +361,13 @@ __global__ __launch_bounds__(256, 2) void adj64_kernel(const float* __restrict__
     }
 }
 
-// Xt[j][c] = sum_s P[s][j][c] (float64, splits in order); per-block sums of squares into sq_part
+// Xt[j][c] = sum_s P[s][j][c] - d[c] zsum[j] (float64, splits in order); per-block sums of squares
+// into sq_part
 __global__ __launch_bounds__(256) void reduce_x64_kernel(const double* __restrict__ P, int nsplit,
                                                          int64_t split_stride, int64_t ldp, int64_t n,
-                                                         double* __restrict__ Xt, int64_t ldx,
-                                                         double* __restrict__ sq_part) {
+                                                         const double* __restrict__ d,
+                                                         const double* __restrict__ zsum, double* __restrict__ Xt,
+                                                         int64_t ldx, double* __restrict__ sq_part) {
   __shared__ double sh[4];
   const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int j = blockIdx.y;
@@ -371,6 +376,7 @@ __global__ __launch_bounds__(256) void reduce_x64_kernel(const double* __restric
     const double* p = P + (int64_t)j * ldp + c;
     double v = 0.0;
     for (int s = 0; s < nsplit; ++s) v += p[(int64_t)s * split_stride];
+    if (d != nullptr) v -= d[c] * zsum[j];
     Xt[(int64_t)j * ldx + c] = v;
     sq = v * v;
   }
@@ -378,6 +384,38 @@ __global__ __launch_bounds__(256) void reduce_x64_kernel(const double* __restric
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sq;
   __syncthreads();
   if (threadIdx.x == 0) sq_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// corr[j] = sum_c d[c] Xt[j][c], one block per j, fixed order within a block
+__global__ __launch_bounds__(256) void dot_rows64_kernel(const double* __restrict__ d, const double* __restrict__ Xt,
+                                                         int64_t ldx, int64_t n, double* __restrict__ corr) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int64_t c = threadIdx.x; c < n; c += 256) s += d[c] * Xt[(int64_t)j * ldx + c];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) corr[j] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// part[s][c] = sum of X[r][c] over the rows of split s (one block per split and 64 columns)
+__global__ __launch_bounds__(256) void colsum_f64_kernel(const double* __restrict__ X, int64_t ld, int64_t rows,
+                                                         int cols, int64_t rows_per_split,
+                                                         double* __restrict__ part) {
+  __shared__ double sh[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int w = threadIdx.x >> 6;
+  const int s = blockIdx.y;
+  const int64_t r0 = (int64_t)s * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < rows ? r0 + rows_per_split : rows;
+  double v = 0.0;
+  if (c < cols)
+    for (int64_t r = r0 + w; r < r1; r += 4) v += X[r * ld + c];
+  sh[w][threadIdx.x & 63] = v;
+  __syncthreads();
+  if (w == 0 && c < cols)
+    part[(int64_t)s * cols + c] = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
 }
 
 // flag |= 1 when any entry of X (rows x cols, ld) is not finite
@@ -449,10 +487,10 @@ static void launch_fwd64_ct(const Fwd64Args& a, dim3 grid, double* out, int64_t 
                             hipStream_t st) {
   if (a.vec)
     hipLaunchKernelGGL((fwd64_kernel<CT, true>), grid, dim3(256), 0, st, a.A, a.lda, a.m, a.n, a.Xt, a.ldx, a.ncols,
-                       kchunk, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
+                       kchunk, a.alpha, a.corr, out, ldo, a.split_stride, direct ? 1 : 0);
   else
     hipLaunchKernelGGL((fwd64_kernel<CT, false>), grid, dim3(256), 0, st, a.A, a.lda, a.m, a.n, a.Xt, a.ldx,
-                       a.ncols, kchunk, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
+                       a.ncols, kchunk, a.alpha, a.corr, out, ldo, a.split_stride, direct ? 1 : 0);
 }
 
 hipError_t launch_fwd64(const Fwd64Args& a, hipStream_t st) {
@@ -481,7 +519,7 @@ hipError_t launch_fwd64(const Fwd64Args& a, hipStream_t st) {
   if (e != hipSuccess || direct) return e;
   const int64_t tot = a.m * a.ncols;
   hipLaunchKernelGGL(fwd64_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, a.P, ns,
-                     a.split_stride, a.ldp, a.m, a.ncols, a.alpha, a.Z, a.ldz);
+                     a.split_stride, a.ldp, a.m, a.ncols, a.alpha, a.corr, a.Z, a.ldz);
   return hipGetLastError();
 }
 
@@ -519,10 +557,29 @@ hipError_t launch_adj64(const Adj64Args& a, hipStream_t st) {
 }
 
 hipError_t launch_reduce_x64(const double* P, int nsplit, int64_t split_stride, int64_t ldp, int ncols, int64_t n,
-                             double* Xt, int64_t ldx, double* sq_part, int* n_sq_part, hipStream_t st) {
+                             const double* d, const double* zsum, double* Xt, int64_t ldx, double* sq_part,
+                             int* n_sq_part, hipStream_t st) {
+  if ((d == nullptr) != (zsum == nullptr)) return hipErrorInvalidValue;
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
   *n_sq_part = (int)(grid.x * grid.y);
-  hipLaunchKernelGGL(reduce_x64_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, n, Xt, ldx, sq_part);
+  hipLaunchKernelGGL(reduce_x64_kernel, grid, dim3(256), 0, st, P, nsplit, split_stride, ldp, n, d, zsum, Xt, ldx,
+                     sq_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_rows64(const double* d, const double* Xt, int64_t ldx, int64_t n, int ncols, double* corr,
+                             hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dot_rows64_kernel, dim3((unsigned)ncols), dim3(256), 0, st, d, Xt, ldx, n, corr);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum_f64(const double* X, int64_t ld, int64_t rows, int cols, int64_t rows_per_split,
+                             int nsplit, double* part, hipStream_t st) {
+  if (rows <= 0 || cols <= 0 || nsplit <= 0) return hipSuccess;
+  if ((int64_t)nsplit * rows_per_split < rows) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)nsplit);
+  hipLaunchKernelGGL(colsum_f64_kernel, grid, dim3(256), 0, st, X, ld, rows, cols, rows_per_split, part);
   return hipGetLastError();
 }
 

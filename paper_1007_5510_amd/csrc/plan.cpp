@@ -144,6 +144,7 @@ struct rpca_plan_s {
   double* H64 = nullptr;   // m x L
   double* P64 = nullptr;   // adjoint partials [ns_y64][l][ldp64]
   double* Pf64 = nullptr;  // forward partials [fwd_ks64][m][l]
+  double* corr64 = nullptr;  // l: mu^T X_j (centring)
   int ns_y64 = 1, fwd_ks64 = 1;
   int64_t rps_y64 = 0, fwd_kchunk64 = 0;
 
@@ -348,9 +349,9 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     plan->ns_t6 = (int)((m + plan->rps_t6 - 1) / plan->rps_t6);
   }
   if (desc->flags & RPCA_FLAG_FP64_STEP1) {
-    // float64 Step 1 reads float32 A from device memory, without centring, and
-    // keeps no state for the reverse sweep
-    if (desc->storage != RPCA_A_F32 || desc->source != RPCA_SRC_DEVICE || desc->center != 0 ||
+    // float64 Step 1 reads float32 A from device memory and keeps no state for
+    // the reverse sweep
+    if (desc->storage != RPCA_A_F32 || desc->source != RPCA_SRC_DEVICE ||
         (desc->flags & (RPCA_FLAG_SPLIT_BF16 | RPCA_FLAG_KEEP_STATE)) != 0)
       return fail(RPCA_ERR_UNSUPPORTED);
     plan->f64s1 = true;
@@ -449,6 +450,7 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     ALLOC(H64, m * L);
     ALLOC(P64, (int64_t)plan->ns_y64 * l * plan->ldp64);
     ALLOC(Pf64, plan->fwd_ks64 > 1 ? (int64_t)plan->fwd_ks64 * m * l : 1);
+    ALLOC(corr64, l);
     if (hipMemset(plan->X64, 0, sizeof(double) * (size_t)((int64_t)(i + 1) * l * plan->ldx64)) != hipSuccess)
       return fail(RPCA_ERR_HIP);
   }
@@ -768,7 +770,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   // Low-precision storage has no in-register shift: d is the whole mean.
   // In-core storage folds the column sums into pass 0's adjoint (no separate
   // pass over A).
-  const bool fuse0 = center && !streamed && i >= 1;
+  const bool fuse0 = center && !streamed && i >= 1 && !plan->f64s1;
   if (center && streamed) {
     // a streamed pass of column sums (float64, accumulated over the panels)
     RPCA_TRY(launch_fill_f64(plan->acc, n, 0.0, st));
@@ -815,8 +817,10 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_gen_G(plan->d.seed, n, l, X0, ldx, st));
   RPCA_TRY(launch_fill_f64(plan->alpha, i + 1, 1.0, st));
 
-  // float64 Step 1: H^(j) = alpha_j A X_j and X_{j+1} = A^T H^(j) on the FP64
-  // matrix cores, X_0 = G widened exactly; alpha_{j+1} = 1/||X_{j+1}||_F
+  // float64 Step 1: H^(j) = alpha_j A~ X_j and X_{j+1} = A~^T H^(j) on the FP64
+  // matrix cores, X_0 = G widened exactly; alpha_{j+1} = 1/||X_{j+1}||_F.  With
+  // centring A~ = A - 1 mu^T enters as the exact rank-one corrections
+  // A~ X = A X - 1 (mu^T X) and A~^T H = A^T H - mu (1^T H) in float64.
   const bool f64s1 = plan->f64s1;
   if (f64s1) {
     const int64_t ldx64 = plan->ldx64;
@@ -831,6 +835,10 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       fa.ldx = ldx64;
       fa.ncols = l;
       fa.alpha = plan->alpha + j;
+      if (center) {
+        RPCA_TRY(launch_dot_rows64(plan->mu, fa.Xt, ldx64, n, l, plan->corr64, st));
+        fa.corr = plan->corr64;
+      }
       fa.Z = plan->H64 + (int64_t)j * l;
       fa.ldz = L;
       fa.vec = vec;
@@ -866,8 +874,13 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
         aa.ev_end = ev->b;
       }
       RPCA_TRY(launch_adj64(aa, st));
+      if (center) {  // 1^T H^(j)
+        RPCA_TRY(launch_colsum_f64(fa.Z, L, m, l, plan->rps_cn, plan->ns_cn, plan->csp, st));
+        RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, l, 1.0, plan->zsum, nullptr, nullptr, st));
+      }
       int npart = 0;
       RPCA_TRY(launch_reduce_x64(plan->P64, plan->ns_y64, aa.split_stride, plan->ldp64, l, n,
+                                 center ? plan->mu : nullptr, center ? plan->zsum : nullptr,
                                  plan->X64 + (int64_t)(j + 1) * l * ldx64, ldx64, plan->sqp, &npart, st));
       RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
     }
@@ -1072,7 +1085,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
                           : center ? static_cast<const void*>(plan->Q) : static_cast<const void*>(plan->H);
   for (int attempt = 0; attempt < 4; ++attempt) {
     RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 3 * sizeof(int), st));
-    if (center) {
+    if (center && !f64s1) {
       RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
       RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, L, 1.0, plan->zsum, nullptr, nullptr, st));
       RPCA_TRY(launch_center_cols(plan->H, L, m, L, plan->zsum, 1.0 / (double)m, plan->Q, L, st));

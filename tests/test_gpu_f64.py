@@ -85,6 +85,29 @@ def test_f64_shapes_and_edges(m, n, k, l, i, lda):
     assert abs(r_g - r_o) / r_o < 1e-5
 
 
+def test_f64_centered_parity():
+    """Low-rank + noise + U(0,1) column offsets, centred: H blocks of A~ = A - 1 mu^T to 1e-12, the
+    factorisation at the float32 tolerances, mu exact in float64."""
+    _need_gpu()
+    from paper_1007_5510_amd import rpca, _lib
+    m, n, r = 6000, 800, 12
+    sig = 1.0 / np.arange(1, r + 1)
+    p = F.lowrank_noise(31, m, n, r, sig, 1e-3, True)
+    k, l, i = 10, 14, 2
+    G = F.gaussian_G(31, n, l)
+    orc = O.rpca(p["A"], k, l, i, G, center=True)
+    Ad = torch.from_numpy(np.ascontiguousarray(p["A"], dtype=np.float32)).cuda()
+    plan = rpca.Plan(m, n, k, l, i, center=True, flags=_flag())
+    U, S, V = plan.factor(Ad, G=torch.from_numpy(G).cuda())
+    torch.cuda.synchronize()
+    g = (U.cpu().double().numpy(), S.cpu().double().numpy(), V.cpu().double().numpy(), plan)
+    check_blocks(plan, orc, l, i)
+    compare(g, orc, k, n_vec=4)
+    mu = plan.state("MU").cpu().numpy()
+    assert np.abs(mu - orc.mu).max() < 1e-12 * np.abs(p["A"]).max()
+    assert np.abs(np.ones(m) @ g[0]).max() < 1e-4
+
+
 def test_f64_reaches_eps0_on_reduced_first_example():
     """The paper's first example (A = E S F, DCT-II E and F) at 8000 x 8000, k = 16, l = 18,
     i = 3: float64 Step 1 gives ||A - U S V^T|| / sigma_{k+1} <= 1.1 and S_1..S_k to 1e-4;
@@ -131,8 +154,8 @@ def test_f64_reaches_eps0_on_reduced_first_example():
 def test_f64_unsupported_combinations():
     _need_gpu()
     from paper_1007_5510_amd import rpca, _lib
-    for kw in ({"center": True}, {"storage": "bf16"}, {"flags": _lib.FLAG_SPLIT_BF16},
-               {"flags": _lib.FLAG_KEEP_STATE}):
+    for kw in ({"storage": "bf16"}, {"flags": _lib.FLAG_SPLIT_BF16}, {"flags": _lib.FLAG_KEEP_STATE},
+               {"source": "host_pinned"}):
         flags = _flag() | kw.pop("flags", 0)
         with pytest.raises(RuntimeError):
             rpca.Plan(1000, 400, 4, 6, 1, flags=flags, **kw)
