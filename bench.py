@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 
 
 def log(*a):
@@ -459,7 +460,7 @@ def main():
     ap.add_argument("--compute", default="f32", choices=["f32", "split-bf16", "f64-step1"],
                     help="float32 products on float32 matrix cores, or with each operand split into three bfloat16 "
                          "parts on the bfloat16 matrix cores (float32 storage only), or Step 1 in float64 on the "
-                         "FP64 matrix cores (paper-example workloads only: they are not centred)")
+                         "FP64 matrix cores (float32 storage only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -495,12 +496,12 @@ def main():
         log(f"[bench] stored A as {storage}: {Ain.data.numel() * Ain.data.element_size() / 1e9:.2f} GB")
     bpe = {"f32": 4, "bf16": 2, "fp8_e4m3": 1, "bf16_hilo": 4}[storage]
     split = args.compute == "split-bf16"
-    if args.compute == "f64-step1":
-        raise SystemExit("--compute f64-step1 needs an uncentred workload (paper-ex1 / paper-ex2)")
-    if split and storage != "f32":
-        raise SystemExit("--compute split-bf16 applies to float32 storage only")
+    f64s1 = args.compute == "f64-step1"
+    if (split or f64s1) and storage != "f32":
+        raise SystemExit(f"--compute {args.compute} applies to float32 storage only")
     plan = rpca.Plan(m, n, k, l, i, storage=storage, center=True, seed=args.seed,
-                     flags=_lib.FLAG_PROFILE | (_lib.FLAG_SPLIT_BF16 if split else 0),
+                     flags=_lib.FLAG_PROFILE | (_lib.FLAG_SPLIT_BF16 if split else 0)
+                     | (_lib.FLAG_FP64_STEP1 if f64s1 else 0),
                      device=0)
     U = torch.empty((m, k), dtype=torch.float32, device=dev)
     S = torch.empty((k,), dtype=torch.float32, device=dev)
@@ -539,7 +540,14 @@ def main():
     fwd_tf = fwd_flops / (i + 1) / (fwd_avg * 1e-3) / 1e12
     adj_tf = adj_flops / (i + 1) / (adj_avg * 1e-3) / 1e12
     log(f"[bench] fwd kernel avg {fwd_avg:.3f} ms {fwd_tf:.1f} TF/s; adj kernel avg {adj_avg:.3f} ms {adj_tf:.1f} TF/s")
-    if split:
+    if f64s1:
+        # Step 1 on the FP64 matrix cores: the forward launches (all float64) against the FP64 peak
+        fwd_tf64 = 2.0 * m * n * l / (fwd_avg * 1e-3) / 1e12
+        log(f"[bench] fwd64_kernel avg {fwd_avg:.3f} ms = {fwd_tf64:.1f} TFLOP/s")
+        roof = {"bound": "mfma", "achieved": round(fwd_tf64, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(fwd_tf64 / PEAK_FP64_TFLOPS, 4), "traffic": None, "algorithmic_bytes": m * n * 4,
+                "kernel": "fwd64_kernel", "avg_launch_ms": round(fwd_avg, 4)}
+    elif split:
         # split products are meant to be bound by the read of A: algorithmic bytes = one read of A
         if adj_ms >= fwd_ms:
             dom = {"kernel": "adj_x6_kernel", "avg_ms": adj_avg, "tf": adj_tf}
@@ -598,7 +606,8 @@ def main():
         "metric": "rank-k PCA time & effective A-read GB/s (vs peak) at residual/sigma_{k+1} <= 1.1",
         "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": ("f32" if not split else "f32 as 3 x bf16 parts (6 bf16 products, f32 accumulate)")
+        "dtype": ("f64 Step 1 (f32 A exact in f64, FP64 matrix cores), f32 Step 3" if f64s1 else
+                  "f32 as 3 x bf16 parts (6 bf16 products, f32 accumulate)" if split else "f32")
         if storage == "f32" else "bf16-mfma/f32-acc", "data": "synthetic",
         "config": {"workload": f"in-core {storage} {m}x{n} low-rank+noise, centred, k={k} l={l} i={i}",
                    "m": m, "n": n, "k": k, "l": l, "i": i, "storage": storage, "center": True},
