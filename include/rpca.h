@@ -222,7 +222,10 @@ rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const floa
  *   gS  (k), gU (m x k, ldgu), gV (n x k, ldgv): device cotangents of S, U, V
  *       (any may be NULL = zero).
  *   dA  (m x n, ldda): device floats receiving dL/dA.
- * Errors: NO_STATE, INVALID_ARG, UNSUPPORTED (storage other than F32), HIP. */
+ * The first call allocates the reverse-sweep workspace, kept until
+ * rpca_destroy.  Blocks the calling thread until dA is written.
+ * Errors: NO_STATE, INVALID_ARG, UNSUPPORTED (storage other than F32,
+ * streamed sources), OUT_OF_MEMORY, HIP.                                   */
 rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, int64_t ldgu,
                           const float* gV, int64_t ldgv, float* dA, int64_t ldda);
 
@@ -231,7 +234,13 @@ rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, in
  * entries (Philox stream 9 under `seed`) and j power steps (the paper uses
  * j = 6 and q = k).  U (m x k), S (k), V (n x k) are device floats as
  * rpca_factor returns them; A as in rpca_factor (DEVICE source only).
- * *estimate receives the estimate (host double).                          */
+ * *estimate receives the estimate (host double).  Allocates its O((m+n) q)
+ * workspace on each call and frees it before returning; blocks the calling
+ * thread until done.
+ * Errors: INVALID_ARG (NULL pointers, j < 1, q < 1 or q > 1024, short leading
+ * dimensions), UNSUPPORTED (storage other than F32, streamed sources),
+ * NO_STATE (centring plan without a preceding rpca_factor), OUT_OF_MEMORY,
+ * HIP.                                                                     */
 rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const float* col_scale,
                           const float* U, int64_t ldu, const float* S, const float* V, int64_t ldv,
                           int32_t j, int32_t q, uint64_t seed, double* estimate);
