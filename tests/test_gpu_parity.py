@@ -287,3 +287,22 @@ def test_block_rescale_keeps_large_matrices_finite():
     with pytest.raises(_lib.RPCAError) as e:
         run_gpu(A, k, l, i, G=G, flags=_lib.FLAG_NO_RESCALE)
     assert e.value.code == 6  # RPCA_ERR_NONFINITE
+
+
+def test_householder_step2_at_its_width_limit():
+    """L = 256 (the Householder path's limit): parity with the oracle; one column more is refused
+    with RPCA_ERR_QR_BREAKDOWN instead of running."""
+    from paper_1007_5510_amd import _lib
+    m, n, k, l, i = 12000, 1500, 40, 64, 3
+    sigma = 0.97 ** np.arange(n, dtype=np.float64)
+    p = F.svd_problem(7070, m, n, sigma)
+    G = F.gaussian_G(7070, n, l)
+    orc = O.rpca(p["A"], k, l, i, G)
+    g = run_gpu(p["A"], k, l, i, G=G, flags=_lib.FLAG_FORCE_HOUSEHOLDER)
+    assert g[3].stats()["qr_fallback"] == 3
+    compare(g, orc, k, v_tol=2e-3)
+    Q = g[3].state("Q").cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye((i + 1) * l)).max() < 1e-13
+    with pytest.raises(_lib.RPCAError) as e:
+        run_gpu(p["A"], k, 65, i, G=F.gaussian_G(7070, n, 65), flags=_lib.FLAG_FORCE_HOUSEHOLDER)
+    assert e.value.code == 7  # RPCA_ERR_QR_BREAKDOWN: L = 260 > 256
