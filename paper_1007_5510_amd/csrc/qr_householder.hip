@@ -91,12 +91,14 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
       const int ib = j + (span * w) / 4, ie = j + (span * (w + 1)) / 4;
       for (int c = j + 1 + lane; c < L; c += 64) {
         double p = 0.0;
+#pragma unroll 8
         for (int i = ib; i < ie; ++i) p += v[i] * B[(int64_t)i * L + c];
         part[w * L + c] = p;
       }
       __syncthreads();
       for (int c = j + 1 + lane; c < L; c += 64) {
         const double wc = t * (part[c] + part[L + c] + part[2 * L + c] + part[3 * L + c]);
+#pragma unroll 8
         for (int i = ib; i < ie; ++i) B[(int64_t)i * L + c] -= v[i] * wc;
       }
     }
@@ -142,12 +144,14 @@ __global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict_
     const int ib = j + (span * w) / 4, ie = j + (span * (w + 1)) / 4;
     for (int c = lane; c < L; c += 64) {
       double p = 0.0;
+#pragma unroll 8
       for (int i = ib; i < ie; ++i) p += v[i] * Y[(int64_t)i * L + c];
       part[w * L + c] = p;
     }
     __syncthreads();
     for (int c = lane; c < L; c += 64) {
       const double wc = t * (part[c] + part[L + c] + part[2 * L + c] + part[3 * L + c]);
+#pragma unroll 8
       for (int i = ib; i < ie; ++i) Y[(int64_t)i * L + c] -= v[i] * wc;
     }
     __syncthreads();
