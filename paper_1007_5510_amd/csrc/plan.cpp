@@ -602,7 +602,7 @@ rpca_status householder_qr(rpca_plan_s* plan, bool x_f64, const void* H, double*
     int nb0 = (int)(m / bu0);
     if (nb0 < 1) nb0 = 1;
     const int64_t last0 = m - (int64_t)(nb0 - 1) * bu0;
-    if ((last0 > bu0 ? last0 : bu0) + 4 * L + 8 > 8192) return RPCA_ERR_QR_BREAKDOWN;  // LDS of one block
+    if ((last0 > bu0 ? last0 : bu0) + 16 * (L + 1) > 8192) return RPCA_ERR_QR_BREAKDOWN;  // LDS of one block
     t.rows.push_back(m);
     t.bu.push_back(bu0);
     t.nb.push_back(nb0);

@@ -9,7 +9,7 @@
 // is not applied: it permutes R's columns and leaves span(Q), on which Steps
 // 3-6 depend, unchanged.
 //
-// One workgroup (four waves) per block.  A reflector step on a block of nr
+// One workgroup (sixteen waves) per block.  A reflector step on a block of nr
 // rows: the sum of squares of the column below the diagonal (block
 // reduction), v and tau as in LAPACK's dlarfg (beta = -sign(alpha) ||x||,
 // tau = (beta - alpha) / beta, v = x / (alpha - beta), v_j = 1), v cached in
@@ -21,6 +21,9 @@
 #include "kernels.h"
 
 namespace rpca {
+
+constexpr int HH_WAVES = 16;  // waves per workgroup: the rows of a block are split over them
+constexpr int HH_THREADS = 64 * HH_WAVES;
 
 namespace {
 
@@ -37,21 +40,32 @@ RPCA_DEV double hh_block_sum(double v, double* red) {
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
-  return red[0] + red[1] + red[2] + red[3];
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < HH_WAVES; ++q) t += red[q];
+  return t;
+}
+
+// sum over the waves' partial dot products of column c
+RPCA_DEV double hh_part_sum(const double* part, int L, int c) {
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < HH_WAVES; ++q) t += part[q * L + c];
+  return t;
 }
 
 }  // namespace
 
 // Factor block k in place (reflectors below the diagonal, R on and above it),
 // tau[k L + j], and write R (upper, zeros below) to Rout + k L L.  Requires
-// nr >= L for every block.  LDS: maxrows + 4 L + 8 doubles.
-__global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, int64_t rows_total, int64_t bu,
+// nr >= L for every block.  LDS: maxrows + HH_WAVES (L + 1) doubles.
+__global__ __launch_bounds__(HH_THREADS) void hh_factor_kernel(double* __restrict__ X, int64_t rows_total, int64_t bu,
                                                         int nb, int L, int maxrows, double* __restrict__ tau,
                                                         double* __restrict__ Rout) {
   extern __shared__ double hsh[];
   double* v = hsh;
   double* part = hsh + maxrows;
-  double* red = part + 4 * L;
+  double* red = part + HH_WAVES * L;
   const int k = blockIdx.x;
   int64_t r0, nr64;
   hh_block_rows(rows_total, bu, nb, k, &r0, &nr64);
@@ -60,7 +74,7 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int j = 0; j < L; ++j) {
     double s = 0.0;
-    for (int i = j + 1 + tid; i < nr; i += 256) {
+    for (int i = j + 1 + tid; i < nr; i += HH_THREADS) {
       const double x = B[(int64_t)i * L + j];
       s += x * x;
     }
@@ -74,7 +88,7 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
       t = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    for (int i = j + 1 + tid; i < nr; i += 256) {
+    for (int i = j + 1 + tid; i < nr; i += HH_THREADS) {
       const double vi = B[(int64_t)i * L + j] * scale;
       B[(int64_t)i * L + j] = vi;
       v[i] = vi;
@@ -86,9 +100,9 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
     }
     __syncthreads();
     if (t != 0.0) {
-      // rows [j, nr) split into four contiguous ranges, one per wave
+      // rows [j, nr) split into HH_WAVES contiguous ranges, one per wave
       const int span = nr - j;
-      const int ib = j + (span * w) / 4, ie = j + (span * (w + 1)) / 4;
+      const int ib = j + (span * w) / HH_WAVES, ie = j + (span * (w + 1)) / HH_WAVES;
       for (int c = j + 1 + lane; c < L; c += 64) {
         double p = 0.0;
 #pragma unroll 8
@@ -97,7 +111,7 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
       }
       __syncthreads();
       for (int c = j + 1 + lane; c < L; c += 64) {
-        const double wc = t * (part[c] + part[L + c] + part[2 * L + c] + part[3 * L + c]);
+        const double wc = t * hh_part_sum(part, L, c);
 #pragma unroll 8
         for (int i = ib; i < ie; ++i) B[(int64_t)i * L + c] -= v[i] * wc;
       }
@@ -105,7 +119,7 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
     __syncthreads();
   }
   double* __restrict__ R = Rout + (int64_t)k * L * L;
-  for (int e = tid; e < L * L; e += 256) {
+  for (int e = tid; e < L * L; e += HH_THREADS) {
     const int i = e / L, c = e % L;
     R[e] = c >= i ? B[(int64_t)i * L + c] : 0.0;
   }
@@ -113,8 +127,8 @@ __global__ __launch_bounds__(256) void hh_factor_kernel(double* __restrict__ X, 
 
 // Block k of a level: Y (its nr rows of Yout) = Q_k [C_k; 0], with C_k rows
 // [k L, (k+1) L) of Cin (the identity when Cin is null) and Q_k the product
-// of the block's reflectors, applied last-to-first.  LDS: maxrows + 4 L + 8.
-__global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict__ X, int64_t rows_total, int64_t bu,
+// of the block's reflectors, applied last-to-first.  LDS: maxrows + HH_WAVES (L + 1).
+__global__ __launch_bounds__(HH_THREADS) void hh_apply_kernel(const double* __restrict__ X, int64_t rows_total, int64_t bu,
                                                        int nb, int L, int maxrows, const double* __restrict__ tau,
                                                        const double* __restrict__ Cin, double* __restrict__ Yout) {
   extern __shared__ double hsh[];
@@ -127,7 +141,7 @@ __global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict_
   const double* __restrict__ B = X + r0 * L;
   double* __restrict__ Y = Yout + r0 * L;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int64_t e = tid; e < (int64_t)nr * L; e += 256) {
+  for (int64_t e = tid; e < (int64_t)nr * L; e += HH_THREADS) {
     const int i = (int)(e / L), c = (int)(e % L);
     double y = 0.0;
     if (i < L) y = Cin != nullptr ? Cin[((int64_t)k * L + i) * L + c] : (i == c ? 1.0 : 0.0);
@@ -137,11 +151,11 @@ __global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict_
   for (int j = L - 1; j >= 0; --j) {
     const double t = tau[(int64_t)k * L + j];
     if (t == 0.0) continue;  // uniform across the workgroup
-    for (int i = j + 1 + tid; i < nr; i += 256) v[i] = B[(int64_t)i * L + j];
+    for (int i = j + 1 + tid; i < nr; i += HH_THREADS) v[i] = B[(int64_t)i * L + j];
     if (tid == 0) v[j] = 1.0;
     __syncthreads();
     const int span = nr - j;
-    const int ib = j + (span * w) / 4, ie = j + (span * (w + 1)) / 4;
+    const int ib = j + (span * w) / HH_WAVES, ie = j + (span * (w + 1)) / HH_WAVES;
     for (int c = lane; c < L; c += 64) {
       double p = 0.0;
 #pragma unroll 8
@@ -150,7 +164,7 @@ __global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict_
     }
     __syncthreads();
     for (int c = lane; c < L; c += 64) {
-      const double wc = t * (part[c] + part[L + c] + part[2 * L + c] + part[3 * L + c]);
+      const double wc = t * hh_part_sum(part, L, c);
 #pragma unroll 8
       for (int i = ib; i < ie; ++i) Y[(int64_t)i * L + c] -= v[i] * wc;
     }
@@ -158,7 +172,7 @@ __global__ __launch_bounds__(256) void hh_apply_kernel(const double* __restrict_
   }
 }
 
-static size_t hh_lds(int L, int maxrows) { return sizeof(double) * (size_t)(maxrows + 4 * L + 8); }
+static size_t hh_lds(int L, int maxrows) { return sizeof(double) * (size_t)(maxrows + HH_WAVES * (L + 1)); }
 
 hipError_t launch_hh_factor(double* X, int64_t rows_total, int64_t bu, int nb, int L, double* tau, double* Rout,
                             hipStream_t st) {
@@ -167,7 +181,7 @@ hipError_t launch_hh_factor(double* X, int64_t rows_total, int64_t bu, int nb, i
   const int64_t maxrows = rows_total - (int64_t)(nb - 1) * bu > bu ? rows_total - (int64_t)(nb - 1) * bu : bu;
   const size_t lds = hh_lds(L, (int)maxrows);
   if (maxrows > (1 << 20) || lds > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hh_factor_kernel, dim3((unsigned)nb), dim3(256), lds, st, X, rows_total, bu, nb, L,
+  hipLaunchKernelGGL(hh_factor_kernel, dim3((unsigned)nb), dim3(HH_THREADS), lds, st, X, rows_total, bu, nb, L,
                      (int)maxrows, tau, Rout);
   return hipGetLastError();
 }
@@ -179,7 +193,7 @@ hipError_t launch_hh_apply(const double* X, int64_t rows_total, int64_t bu, int 
   const int64_t maxrows = rows_total - (int64_t)(nb - 1) * bu > bu ? rows_total - (int64_t)(nb - 1) * bu : bu;
   const size_t lds = hh_lds(L, (int)maxrows);
   if (maxrows > (1 << 20) || lds > 65536) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)nb), dim3(256), lds, st, X, rows_total, bu, nb, L,
+  hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)nb), dim3(HH_THREADS), lds, st, X, rows_total, bu, nb, L,
                      (int)maxrows, tau, Cin, Yout);
   return hipGetLastError();
 }
