@@ -56,6 +56,44 @@ def measured_traffic(kernel):
     return None
 
 
+def measured_peaks(device):
+    """Achievable rates on this GPU for the roofline context (measurement only, outside the timed
+    region): library GEMMs (torch/hipBLASLt) at 8192^3 in float32, bfloat16 and float64, and a 2 GiB
+    device-to-device copy (read + write bytes)."""
+    import torch
+    out = {}
+    nn = 8192
+    for name, dt in (("fp32_gemm_tflops", torch.float32), ("bf16_gemm_tflops", torch.bfloat16),
+                     ("fp64_gemm_tflops", torch.float64)):
+        a = torch.randn((nn, nn), device=device, dtype=torch.float32).to(dt)
+        b = torch.randn((nn, nn), device=device, dtype=torch.float32).to(dt)
+        c = a @ b
+        torch.cuda.synchronize()
+        reps = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round(2.0 * nn ** 3 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e12, 1)
+        del a, b, c
+    src = torch.empty(1 << 28, dtype=torch.float64, device=device).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_gbs"] = round(2.0 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def make_incore(m, n, r, seed, device):
     import numpy as np
     import torch
@@ -445,6 +483,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2020)
     ap.add_argument("--cpu-rows", type=int, default=80000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peak-probe", action="store_true",
+                    help="skip the measured GEMM / copy rates reported beside the roofline")
     ap.add_argument("--no-gate", action="store_true")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8_e4m3", "bf16_hilo"],
                     help="stored format of A (low-precision copies are made from the float32 matrix with "
@@ -513,10 +553,12 @@ def main():
     fwd_ms = adj_ms = 0.0
     nf = na = 0
     stage = {"ms_power": 0.0, "ms_qr": 0.0, "ms_tpass": 0.0, "ms_small_svd": 0.0, "ms_assemble": 0.0}
+    step_ms = []
     t0 = time.perf_counter()
     for s in range(args.steps):
         plan.factor(Ain, out=(U, S, V))
         st = plan.stats()
+        step_ms.append(st["ms_total"])
         fwd_ms += st["ms_fwd_kernel"]
         adj_ms += st["ms_adj_kernel"]
         nf += st["fwd_launches"]
@@ -532,6 +574,22 @@ def main():
         " ".join(f"{key}={v / args.steps:.2f}" for key, v in stage.items()))
     a_bytes = (i + 2) * m * n * bpe
     value = a_bytes / (ms * 1e-3) / 1e9
+    # whole-step roofline: every product's algorithmic flops on the matrix cores of the
+    # compute precision, every kernel read of A at the HBM peak; fractions reported apart
+    L = (i + 1) * l
+    step_flops = 2.0 * m * n * (l * (i + 1) + l * i + L)
+    mfma_peak = {"f32": PEAK_FP32_TFLOPS, "f64-step1": PEAK_FP64_TFLOPS}.get(args.compute, PEAK_FP32_TFLOPS)
+    if storage != "f32" or split:
+        mfma_peak = 2500.0  # bfloat16 matrix cores
+    t_mfma = step_flops / (mfma_peak * 1e12) * 1e3
+    reads = st_last["fwd_launches"] + st_last["adj_launches"] if st_last["fwd_launches"] else 2 * i + 2
+    t_hbm = reads * m * n * bpe / (PEAK_HBM_GBS * 1e9) * 1e3
+    step_roof = {"t_roof_ms": round(max(t_mfma, t_hbm), 3), "frac": round(max(t_mfma, t_hbm) / ms, 4),
+                 "mfma_ms": round(t_mfma, 3), "mfma_frac": round(t_mfma / ms, 4),
+                 "hbm_ms": round(t_hbm, 3), "hbm_frac": round(t_hbm / ms, 4),
+                 "mfma_peak_tflops": mfma_peak, "kernel_reads_of_A": reads,
+                 "note": "small float64 steps not included in t_roof"}
+    paper_gbs = 2 * (i + 1) * m * n * bpe / (ms * 1e-3) / 1e9
     # dominant kernel: per-launch algorithmic flops (2 m n c for c right-hand columns)
     fwd_flops = 2.0 * m * n * l * (i + 1)
     adj_flops = 2.0 * m * n * (l * i + (i + 1) * l)
@@ -597,6 +655,11 @@ def main():
         gate = {"residual_est": est, "sigma_k1_ref": sref, "ratio": est / sref}
         log(f"[bench] gate residual {est:.5f} sigma_k+1 {sref:.5f} ratio {est / sref:.4f} "
             f"({time.perf_counter() - t:.1f}s)")
+    peaks = None
+    if not args.no_peak_probe:
+        t = time.perf_counter()
+        peaks = measured_peaks(dev)
+        log(f"[bench] measured peaks {peaks} ({time.perf_counter() - t:.1f}s)")
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -612,6 +675,10 @@ def main():
         "config": {"workload": f"in-core {storage} {m}x{n} low-rank+noise, centred, k={k} l={l} i={i}",
                    "m": m, "n": n, "k": k, "l": l, "i": i, "storage": storage, "center": True},
         "frac_of_hbm_peak": round(value / PEAK_HBM_GBS, 4),
+        "ms_per_step_median": round(float(sorted(step_ms)[len(step_ms) // 2]), 4),
+        "paper_schedule_gbs": round(paper_gbs, 3),
+        "step_roofline": step_roof,
+        "measured_peaks": peaks,
         "a_passes_actual": plan.stats()["passes"],
         "a_reads_actual": round((nf + na) / max(args.steps, 1), 2),
         "roofline": roof,
