@@ -92,7 +92,9 @@ __global__ __launch_bounds__(256, MINB) void fwd32_kernel(
   constexpr int XV = KST / 16;  // float4 of X per thread per stage
   constexpr int SV = KST / 4;   // float4 of the shift per stage
   __shared__ float Xs[2][64][XP];
-  __shared__ float Ss[2][KST];
+  // shift of the stage: entries [0, KST) are read; every thread stores one entry of
+  // its own (threads past KST store duplicates) so the store needs no branch
+  __shared__ __attribute__((aligned(16))) float Ss[2][256];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, kh = lane >> 5;
@@ -135,7 +137,8 @@ __global__ __launch_bounds__(256, MINB) void fwd32_kernel(
     floatx4 a[KST / 8];
   };
   struct XStage {
-    floatx4 x[XV], s;
+    floatx4 x[XV];
+    float s;
   };
   auto load_a = [&](AStage& b, int64_t kb) {
 #pragma unroll
@@ -144,12 +147,12 @@ __global__ __launch_bounds__(256, MINB) void fwd32_kernel(
   auto load_x = [&](XStage& b, int64_t kb) {
 #pragma unroll
     for (int v = 0; v < XV; ++v) b.x[v] = ld4<true>(xsrc + kb + (KST / 4) * xq + 4 * v);
-    b.s = ld4<true>(shift + kb + 4 * (tid & (SV - 1)));
+    b.s = shift[kb + (tid & (KST - 1))];
   };
   auto store_x = [&](const XStage& b, int buf) {
 #pragma unroll
     for (int v = 0; v < XV; ++v) *reinterpret_cast<floatx4*>(&Xs[buf][xc][(KST / 4) * xq + 4 * v]) = b.x[v];
-    if (tid < SV) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = b.s;
+    Ss[buf][tid] = b.s;
   };
   auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
@@ -167,7 +170,9 @@ __global__ __launch_bounds__(256, MINB) void fwd32_kernel(
     }
   };
 
-  // whole stages: straight-line body, the prefetch after the last one re-reads it
+  // whole stages: straight-line body, the prefetch after the last one re-reads it.
+  // The prologue's loads are waited for before the loop, so the loop header
+  // carries no wait on loads issued inside the loop.
   const int64_t nfull = (kend - kbeg) / KST;
   int it = 0;
   if (nfull > 0) {
@@ -176,6 +181,7 @@ __global__ __launch_bounds__(256, MINB) void fwd32_kernel(
     load_x(xr, kbeg);
     load_a(ac, kbeg);
     store_x(xr, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int64_t st = 0; st < nfull; ++st) {
       const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * KST;
@@ -335,14 +341,17 @@ __global__ __launch_bounds__(256, MINB) void adj_f32_kernel(
       b.a[q] = VEC ? ld4<true>(arow + clc) : ld4_masked(arow, cl, n);
     }
   };
+  // unconditional load (zcol is clamped, so the address is valid); the ones
+  // column is substituted when the stage is stored to LDS, after the compute,
+  // so that nothing waits on these loads before then
   auto load_z = [&](ZStage& b, int64_t rb) {
 #pragma unroll
-    for (int q = 0; q < ZQ; ++q) b.z[q] = zone[q] ? 1.f : Z[(rb + zrow[q]) * ldz + zcol[q]];
+    for (int q = 0; q < ZQ; ++q) b.z[q] = Z[(rb + zrow[q]) * ldz + zcol[q]];
   };
   auto store_z = [&](const ZStage& b, int buf) {
     float* base = &Zs[buf][0][0][0];
 #pragma unroll
-    for (int q = 0; q < ZQ; ++q) base[zrow[q] * 64 + zslot[q]] = b.z[q];
+    for (int q = 0; q < ZQ; ++q) base[zrow[q] * 64 + zslot[q]] = zone[q] ? 1.f : b.z[q];
   };
   auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
@@ -357,28 +366,51 @@ __global__ __launch_bounds__(256, MINB) void adj_f32_kernel(
     }
   };
 
+  // Two register stages used alternately (no copy between them): stage st
+  // computes from one while the loads of stage st + 1 land in the other, so a
+  // load has a whole stage to arrive before its first use.  The prologue's
+  // loads are waited for before the loop, so the loop header carries no wait
+  // on loads issued inside the loop.
   const int64_t nfull = (rend - rbeg) / RS;
   int it = 0;
+  auto step_done = [&]() {
+    if (++it == 256 / RS) {  // fold every 64 MFMA K-steps (256 rows)
+      it = 0;
+      fold();
+    }
+  };
   if (nfull > 0) {
-    AStage ac, an;
+    AStage a0, a1;
     ZStage zr;
     load_z(zr, rbeg);
-    load_a(ac, rbeg);
+    load_a(a0, rbeg);
     store_z(zr, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t rn = rbeg + (st + 1 < nfull ? st + 1 : st) * RS;
-      load_z(zr, rn);
-      load_a(an, rn);
+    int64_t st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+      const int64_t r1 = rbeg + (st + 1) * RS;
+      load_z(zr, r1);
+      load_a(a1, r1);
       __builtin_amdgcn_sched_barrier(0);
-      compute(ac, (int)(st & 1));
-      store_z(zr, (int)((st + 1) & 1));
+      compute(a0, 0);
+      store_z(zr, 1);
       __syncthreads();
-      ac = an;
-      if (++it == 256 / RS) {  // fold every 64 MFMA K-steps (256 rows)
-        it = 0;
-        fold();
-      }
+      step_done();
+      // past the last whole stage the prefetch re-reads stage st + 1
+      const int64_t r2 = rbeg + (st + 2 < nfull ? st + 2 : st + 1) * RS;
+      load_z(zr, r2);
+      load_a(a0, r2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_z(zr, 0);
+      __syncthreads();
+      step_done();
+    }
+    if (st < nfull) {  // odd stage count: the last stage is in a0, Z in buffer 0
+      compute(a0, 0);
+      __syncthreads();
+      step_done();
     }
   }
   // tail rows (fewer than a stage): masked by row, zeros beyond rend
