@@ -579,15 +579,24 @@ def main():
     L = (i + 1) * l
     step_flops = 2.0 * m * n * (l * (i + 1) + l * i + L)
     mfma_peak = {"f32": PEAK_FP32_TFLOPS, "f64-step1": PEAK_FP64_TFLOPS}.get(args.compute, PEAK_FP32_TFLOPS)
+    # bfloat16 paths do several bfloat16 products per product: split float32 operands
+    # take six (three parts each, terms i + j <= 2), stored bf16 / fp8 two (X as hi + lo),
+    # a stored hi + lo pair three (hi hi, hi lo, lo hi)
+    bf16_products = 1
+    if split:
+        bf16_products = 6
+    elif storage != "f32":
+        bf16_products = 3 if storage == "bf16_hilo" else 2
     if storage != "f32" or split:
         mfma_peak = 2500.0  # bfloat16 matrix cores
-    t_mfma = step_flops / (mfma_peak * 1e12) * 1e3
+    t_mfma = bf16_products * step_flops / (mfma_peak * 1e12) * 1e3
     reads = st_last["fwd_launches"] + st_last["adj_launches"] if st_last["fwd_launches"] else 2 * i + 2
     t_hbm = reads * m * n * bpe / (PEAK_HBM_GBS * 1e9) * 1e3
     step_roof = {"t_roof_ms": round(max(t_mfma, t_hbm), 3), "frac": round(max(t_mfma, t_hbm) / ms, 4),
                  "mfma_ms": round(t_mfma, 3), "mfma_frac": round(t_mfma / ms, 4),
                  "hbm_ms": round(t_hbm, 3), "hbm_frac": round(t_hbm / ms, 4),
-                 "mfma_peak_tflops": mfma_peak, "kernel_reads_of_A": reads,
+                 "mfma_peak_tflops": mfma_peak, "matrix_products_per_product": bf16_products,
+                 "kernel_reads_of_A": reads,
                  "note": "small float64 steps not included in t_roof"}
     paper_gbs = 2 * (i + 1) * m * n * bpe / (ms * 1e-3) / 1e9
     # dominant kernel: per-launch algorithmic flops (2 m n c for c right-hand columns)

@@ -143,7 +143,9 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
   constexpr int NS = KST / 16;  // MFMA K-steps per stage
   constexpr int XQ = KST / 32;  // 16-byte X chunks per thread per plane
   __shared__ uint16_t Xs[2][3][64][XP];
-  __shared__ float Ss[2][KST];
+  // shift of the stage: entries [0, KST) are read; every thread stores one entry of
+  // its own (threads past KST store duplicates) so the store needs no branch
+  __shared__ __attribute__((aligned(16))) float Ss[2][256];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int li = lane & 31, g = lane >> 5;
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
   };
   struct XStage {
     x6_u32x4 x[3][XQ];
-    floatx4 s;
+    float s;
   };
   auto load_a = [&](AStage& b, int64_t kb) {
 #pragma unroll
@@ -194,14 +196,14 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
     for (int q = 0; q < 3; ++q)
 #pragma unroll
       for (int h = 0; h < XQ; ++h) b.x[q][h] = *reinterpret_cast<const x6_u32x4*>(xsrc + q * xplane + kb + 8 * h);
-    b.s = *reinterpret_cast<const floatx4*>(shift + kb + 4 * (tid & (KST / 4 - 1)));
+    b.s = shift[kb + (tid & (KST - 1))];
   };
   auto store_x = [&](const XStage& b, int buf) {
 #pragma unroll
     for (int q = 0; q < 3; ++q)
 #pragma unroll
       for (int h = 0; h < XQ; ++h) *reinterpret_cast<x6_u32x4*>(&Xs[buf][q][xc][xk + 8 * h]) = b.x[q][h];
-    if (tid < KST / 4) *reinterpret_cast<floatx4*>(&Ss[buf][4 * tid]) = b.s;
+    Ss[buf][tid] = b.s;
   };
   auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
@@ -223,28 +225,50 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
     }
   };
 
+  // whole stages on two register stages used alternately (no copy between
+  // them, so a load has a whole stage to arrive); the prologue's loads are
+  // waited for before the loop, so its header carries no wait on loads issued
+  // inside it
   const int64_t nfull = (kend - kbeg) / KST;
   int it = 0;
+  auto step_done = [&]() {
+    if (++it == 1024 / KST) {  // fold every 1024 K
+      it = 0;
+      fold();
+    }
+  };
   if (nfull > 0) {
-    AStage ac, an;
+    AStage a0, a1;
     XStage xr;
     load_x(xr, kbeg);
-    load_a(ac, kbeg);
+    load_a(a0, kbeg);
     store_x(xr, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * KST;
-      load_x(xr, kn);
-      load_a(an, kn);
+    int64_t st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+      const int64_t k1 = kbeg + (st + 1) * KST;
+      load_x(xr, k1);
+      load_a(a1, k1);
       __builtin_amdgcn_sched_barrier(0);
-      compute(ac, (int)(st & 1));
-      store_x(xr, (int)((st + 1) & 1));
+      compute(a0, 0);
+      store_x(xr, 1);
       __syncthreads();
-      ac = an;
-      if (++it == 1024 / KST) {  // fold every 1024 K
-        it = 0;
-        fold();
-      }
+      step_done();
+      // past the last whole stage the prefetch re-reads stage st + 1
+      const int64_t k2 = kbeg + (st + 2 < nfull ? st + 2 : st + 1) * KST;
+      load_x(xr, k2);
+      load_a(a0, k2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_x(xr, 0);
+      __syncthreads();
+      step_done();
+    }
+    if (st < nfull) {  // odd stage count: the last stage is in a0, X in buffer 0
+      compute(a0, 0);
+      __syncthreads();
+      step_done();
     }
   }
   // tail stage (fewer than KST columns left): A and the shift read as zero beyond kend
@@ -397,23 +421,37 @@ __global__ __launch_bounds__(256, 2) void adj_x6_kernel(
     }
   };
 
+  // two register stages used alternately, prologue drained (as in the forward kernel)
   const int64_t nfull = (rend - rbeg) / X6_RS;
   if (nfull > 0) {
-    AStage ac, an;
+    AStage a0, a1;
     ZStage zs;
     load_z(zs, rbeg);
-    load_a(ac, rbeg);
+    load_a(a0, rbeg);
     store_z(zs, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t rn = rbeg + (st + 1 < nfull ? st + 1 : st) * X6_RS;
-      load_z(zs, rn);
-      load_a(an, rn);
+    int64_t st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+      const int64_t r1 = rbeg + (st + 1) * X6_RS;
+      load_z(zs, r1);
+      load_a(a1, r1);
       __builtin_amdgcn_sched_barrier(0);
-      compute(ac, (int)(st & 1));
-      store_z(zs, (int)((st + 1) & 1));
+      compute(a0, 0);
+      store_z(zs, 1);
       __syncthreads();
-      ac = an;
+      // past the last whole stage the prefetch re-reads stage st + 1
+      const int64_t r2 = rbeg + (st + 2 < nfull ? st + 2 : st + 1) * X6_RS;
+      load_z(zs, r2);
+      load_a(a0, r2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_z(zs, 0);
+      __syncthreads();
+    }
+    if (st < nfull) {  // odd stage count: the last stage is in a0, Z in buffer 0
+      compute(a0, 0);
+      __syncthreads();
     }
   }
   // tail rows (fewer than a stage): rows at or past rend read as the shift (zero after shifting)
