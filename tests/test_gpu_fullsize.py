@@ -106,3 +106,85 @@ def test_incore_full_size_sampled_and_invariants():
     assert np.abs(V.T @ V - np.eye(K)).max() < 1e-5
     assert np.all(np.diff(S) <= 1e-6 * S[0])
 
+
+
+def test_on_the_fly_full_size_sampled_and_invariants():
+    """The streamed workload at its full size, 4e6 x 25000 (400 GB in float32, more than HBM holds),
+    rank 100 with sigma_j = exp(-j/20) plus 1e-4 noise, k = 100, l = 120, i = 2, every 16384-row
+    panel generated on the device in every pass (the benchmark's on-the-fly configuration).  The
+    reference regenerates the panels once more and keeps 64 sampled rows and 64 sampled columns of A
+    on the host: rows give H^(0) = A G one row at a time, columns give (A^T U_k)[c] = A[:, c]^T U_k,
+    which equals (V_k S_k)[c] (the identity above), both in float64."""
+    _need_gpu()
+    from synth import gpu as SG
+    from paper_1007_5510_amd import rpca, _lib
+    m, n, r, k, l, i, pr, seed = 4_000_000, 25000, 100, 100, 120, 2, 16384, 4000
+    dev = torch.device("cuda", 0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    Ur = torch.linalg.qr(torch.randn((m, r), dtype=torch.float64, device=dev, generator=g))[0].float()
+    Vr = torch.linalg.qr(torch.randn((n, r), dtype=torch.float64, device=dev, generator=g))[0]
+    sigma = torch.exp(-torch.arange(1, r + 1, dtype=torch.float64, device=dev) / 20.0)
+    B = (Vr * sigma).T.contiguous().float()
+    del Vr
+    tmp = torch.empty((pr, n), dtype=torch.float32, device=dev)
+    noise = torch.empty((pr, n), dtype=torch.float32, device=dev)
+
+    def fill(row0, nrows, stream):
+        with torch.cuda.stream(stream):
+            gp = torch.Generator(device=dev)
+            gp.manual_seed(seed * 1000003 + row0)
+            torch.matmul(Ur[row0:row0 + nrows], B, out=tmp[:nrows])
+            noise[:nrows].normal_(generator=gp)
+            tmp[:nrows].add_(noise[:nrows], alpha=1e-4)
+
+    def gen(row0, nrows, dst, ld, stream):
+        fill(row0, nrows, torch.cuda.ExternalStream(stream, device=dev))
+        SG.copy_rows_at(dst, ld, tmp, 0, nrows, stream)
+
+    Gh = F.gaussian_G(seed, n, l).astype(np.float32)
+    plan = rpca.Plan(m, n, k, l, i, source="device_callback", panel_rows=pr, flags=_lib.FLAG_PROFILE)
+    U, S, V = plan.factor(None, G=torch.from_numpy(Gh).cuda(), panel_fn=gen)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    print(f"  factor {st['ms_total']:.0f} ms, passes {st['passes']}, Step 2 level {st['qr_fallback']}")
+    assert st["passes"] == i + 2
+    Ud = U.double()
+    S = S.cpu().double().numpy()
+    V = V.cpu().double().numpy()
+    H0 = plan.state("H")[:, :l].cpu().double().numpy()
+    scale0 = float(plan.state("HSCALE").cpu().numpy()[0])
+
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([np.array([0, pr - 1, pr, m - 1]), rng.integers(0, m, 60)]))
+    cols = np.unique(np.concatenate([np.array([0, n - 1]), rng.integers(0, n, 62)]))
+    cols_d = torch.from_numpy(cols).cuda()
+    Arows = {}
+    AtU_c = np.zeros((len(cols), k))
+    cur = torch.cuda.current_stream()
+    for r0 in range(0, m, pr):
+        nr = min(pr, m - r0)
+        fill(r0, nr, cur)
+        panel = tmp[:nr]
+        # sampled columns (an exact gather on the device), then A[:, c]^T U in float64 on the host
+        Ac = panel.index_select(1, cols_d).double().cpu().numpy()
+        AtU_c += Ac.T @ Ud[r0:r0 + nr].cpu().numpy()
+        for rr in rows[(rows >= r0) & (rows < r0 + nr)]:
+            Arows[int(rr)] = panel[rr - r0].double().cpu().numpy()
+    torch.cuda.synchronize()
+
+    errs = []
+    for rr in rows:
+        ref = Arows[int(rr)] @ Gh.astype(np.float64)
+        errs.append(np.linalg.norm(H0[rr] / scale0 - ref) / np.linalg.norm(ref))
+    print(f"  sampled H^(0) rows: max rel err {max(errs):.2e} over {len(rows)} rows")
+    assert max(errs) <= 2e-6
+
+    resid = np.linalg.norm(AtU_c - V[cols] * S)
+    print(f"  sampled rows of A^T U - V S: {resid:.3e} (||S||_F {np.linalg.norm(S):.3f}, {len(cols)} columns)")
+    assert resid <= 1e-5 * np.linalg.norm(S)
+
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-5
+    Uh = Ud.cpu().numpy()
+    assert np.abs(Uh.T @ Uh - np.eye(k)).max() < 1e-5
+    assert np.all(np.diff(S) <= 1e-6 * S[0])
