@@ -58,8 +58,8 @@ def measured_traffic(kernel):
 
 def measured_peaks(device):
     """Achievable rates on this GPU for the roofline context (measurement only, outside the timed
-    region): library GEMMs (torch/hipBLASLt) at 8192^3 in float32, bfloat16 and float64, and a 2 GiB
-    device-to-device copy (read + write bytes)."""
+    region): library GEMMs (torch/hipBLASLt) at 8192^3 in float32, bfloat16 and float64, a 2 GiB
+    device-to-device copy (read + write bytes) and a read-only sum over the same 2 GiB."""
     import torch
     out = {}
     nn = 8192
@@ -89,7 +89,16 @@ def measured_peaks(device):
     e1.record()
     torch.cuda.synchronize()
     out["hbm_copy_gbs"] = round(2.0 * src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
-    del src, dst
+    # read-only streaming: a sum over the same 2 GiB (one read, a few KB written)
+    acc = src.sum()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        acc = src.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_read_gbs"] = round(src.numel() * 8 * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst, acc
     torch.cuda.empty_cache()
     return out
 
@@ -473,7 +482,7 @@ def run_stream(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--m", type=int, default=200000)
     ap.add_argument("--n", type=int, default=20000)
