@@ -176,6 +176,8 @@ typedef struct {
   int32_t eig_vectors;   /* eigenvectors computed in Step 4 (k, or L when state is kept) */
   int32_t hip_error;     /* raw hipError_t of the last RPCA_ERR_HIP */
   int32_t passes;        /* full passes over A performed */
+  double ms_tpass_kernel;  /* the Step 3 (T pass) launches among ms_adj_kernel (event timed) */
+  int64_t tpass_launches;  /* number of those launches */
 } rpca_stats;
 
 /* Creates a plan for the problem in *desc, bound to hip_stream (a hipStream_t,

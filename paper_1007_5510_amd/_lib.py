@@ -48,6 +48,7 @@ class Stats(ctypes.Structure):
         ("fwd_launches", ctypes.c_int64), ("adj_launches", ctypes.c_int64), ("a_bytes_read", ctypes.c_int64),
         ("h2d_bytes", ctypes.c_int64), ("qr_fallback", ctypes.c_int32), ("eig_vectors", ctypes.c_int32),
         ("hip_error", ctypes.c_int32), ("passes", ctypes.c_int32),
+        ("ms_tpass_kernel", ctypes.c_double), ("tpass_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -264,6 +264,7 @@ RPCA_DEV int64_t xcd_remap(int64_t b, int64_t total) {
 }
 
 constexpr int ADJ_RS = 16;  // rows of A per LDS stage of the launched configuration
+constexpr int64_t ADJ_MAX_CHAIN = 8192;  // longest float32 accumulation chain (rows of one split)
 
 // RS: rows of A per LDS stage (16 or 32); MINB: workgroups per CU the
 // register budget is sized for; FOLD2: second float32 accumulation level
@@ -463,6 +464,197 @@ __global__ __launch_bounds__(256, MINB) void adj_f32_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// adjoint for a wide Z (the T pass): each wave owns 32 columns of A (a float2
+// per lane feeds two M tiles) x 16 NT columns of Z (NT = 8 or 12 tiles), so
+// one read of A serves every Z column of the block instead of one read per 64;
+// 4 waves per block cover 128 columns of A.  The Z rows of a stage are staged
+// in LDS as [row][p][t] (column 16 t + p), NT / 4 16-byte reads per lane per
+// K step.  Each output is accumulated over the same rows in the same MFMA K
+// grouping as adj_f32_kernel, so the two kernels give identical sums.  Lane
+// (p, kk) ends with the A columns c0 + 8 kk .. + 7 of its Z column, written as
+// two 16-byte vectors.
+// VEC: A 8-byte aligned, lda and n even.  Z is read in 16-byte pieces: Z
+// 16-byte aligned, ldz and ncols multiples of 4.
+// ---------------------------------------------------------------------------
+typedef float adjw_f2 __attribute__((ext_vector_type(2)));
+constexpr int ADJW_ACOLS = 128;  // A columns per block
+
+// Z tiles per block of the wide-Z adjoint for ncols columns (host side: launcher and split rule)
+static inline int adjw_tiles(int ncols) { return ncols <= 128 ? 8 : 12; }
+
+template <int NT, bool VEC>
+__global__ __launch_bounds__(256, 2) void adj_wide_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
+    const float* __restrict__ Z, int64_t ldz, int ncols, int64_t rows_per_split, int nsplit, int jtiles,
+    int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride) {
+  constexpr int RS = ADJ_RS;
+  constexpr int ZCOLS = 16 * NT;  // Z columns per block
+  constexpr int ZH = NT / 4;      // 4-column Z pieces per thread per stage (16 threads per row)
+  __shared__ __attribute__((aligned(16))) float Zs[2][RS][16][NT];
+  const int64_t total = (int64_t)jtiles * ctiles * nsplit;
+  const int64_t logical = xcd_remap(blockIdx.x, total);
+  const int jt = (int)(logical % jtiles);
+  const int64_t rest = logical / jtiles;
+  const int ct = (int)(rest % ctiles);
+  const int sp = (int)(rest / ctiles);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int p = lane & 15;
+  const int kk = lane >> 4;
+  const int64_t c0 = (int64_t)ct * ADJW_ACOLS + wave * 32;
+  const int64_t cl = c0 + 2 * p;
+  const int64_t clc = cl < n ? cl : 0;  // clamped column for the unmasked path
+  const int j0 = jt * ZCOLS;
+  const int64_t rbeg = (int64_t)sp * rows_per_split;
+  const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
+  auto ld2 = [&](const float* __restrict__ row) -> adjw_f2 {
+    if (VEC) return *reinterpret_cast<const adjw_f2*>(row + clc);
+    adjw_f2 v = {0.f, 0.f};
+    if (cl < n) v.x = row[cl];
+    if (cl + 1 < n) v.y = row[cl + 1];
+    return v;
+  };
+  const adjw_f2 sh = ld2(shift);
+  // cooperative Z loader: thread -> row zr of the stage, ZH 4-column pieces at columns
+  // 4 (ZH (tid % 16) + h); a piece past the last real column re-reads the last piece (its
+  // products land in columns that are never stored).  Element cc of the stage row goes to
+  // LDS slot [zr][cc % 16][cc / 16].
+  const int zr = tid >> 4;
+  int zcol[ZH], zslot[ZH];
+#pragma unroll
+  for (int h = 0; h < ZH; ++h) {
+    const int cc = 4 * (ZH * (tid & 15) + h);
+    zcol[h] = j0 + cc + 4 <= ncols ? j0 + cc : ncols - 4;
+    zslot[h] = zr * (16 * NT) + (cc & 15) * NT + (cc >> 4);
+  }
+
+  floatx4 acc[2][NT];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[v][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  struct AStage {
+    adjw_f2 a[RS / 4];
+  };
+  struct ZStage {
+    floatx4 z[ZH];
+  };
+  auto load_a = [&](AStage& b, int64_t rb) {
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q) b.a[q] = ld2(A + (rb + 4 * q + kk) * lda);
+  };
+  auto load_z = [&](ZStage& b, int64_t rb) {
+    const float* zrow = Z + (rb + zr) * ldz;
+#pragma unroll
+    for (int h = 0; h < ZH; ++h) b.z[h] = *reinterpret_cast<const floatx4*>(zrow + zcol[h]);
+  };
+  // columns cc .. cc + 3 of a piece share the tile cc / 16 and take slots p = cc % 16 .. + 3
+  auto store_z = [&](const ZStage& b, int buf) {
+    float* base = &Zs[buf][0][0][0];
+#pragma unroll
+    for (int h = 0; h < ZH; ++h)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) base[zslot[h] + e * NT] = b.z[h][e];
+  };
+  auto compute = [&](const AStage& b, int buf) {
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q) {
+      const floatx4* zp = reinterpret_cast<const floatx4*>(&Zs[buf][4 * q + kk][p][0]);
+      floatx4 z[ZH];
+#pragma unroll
+      for (int h = 0; h < ZH; ++h) z[h] = zp[h];
+      const adjw_f2 a = b.a[q] - sh;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[v][t] = mfma4(a[v], z[t >> 2][t & 3], acc[v][t]);
+      }
+    }
+  };
+
+  // two register stages used alternately, prologue drained (as in adj_f32_kernel)
+  const int64_t nfull = (rend - rbeg) / RS;
+  if (nfull > 0) {
+    AStage a0, a1;
+    ZStage zr;
+    load_z(zr, rbeg);
+    load_a(a0, rbeg);
+    store_z(zr, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int64_t st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+      const int64_t r1 = rbeg + (st + 1) * RS;
+      load_z(zr, r1);
+      load_a(a1, r1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a0, 0);
+      store_z(zr, 1);
+      __syncthreads();
+      // past the last whole stage the prefetch re-reads stage st + 1
+      const int64_t r2 = rbeg + (st + 2 < nfull ? st + 2 : st + 1) * RS;
+      load_z(zr, r2);
+      load_a(a0, r2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_z(zr, 0);
+      __syncthreads();
+    }
+    if (st < nfull) {  // odd stage count: the last stage is in a0, Z in buffer 0
+      compute(a0, 0);
+      __syncthreads();
+    }
+  }
+  // tail rows (fewer than a stage): Z zero past rend, A read as the shift there
+  const int64_t rt = rbeg + nfull * RS;
+  if (rt < rend) {
+    const int buf = (int)(nfull & 1);
+    ZStage zt;
+    if (rt + zr < rend) {
+      load_z(zt, rt);
+    } else {
+#pragma unroll
+      for (int h = 0; h < ZH; ++h) zt.z[h] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    store_z(zt, buf);
+    AStage at;
+#pragma unroll
+    for (int q = 0; q < RS / 4; ++q) {
+      const int64_t r = rt + 4 * q + kk;
+      at.a[q] = r < rend ? ld2(A + r * lda) : sh;
+    }
+    __syncthreads();
+    compute(at, buf);
+  }
+
+  // D of tile (v, t): lane (p, kk) register w holds A column c0 + 2 (4 kk + w) + v, Z column
+  // j0 + 16 t + p; the eight values of a lane are A columns c0 + 8 kk .. + 7 in order
+  float* __restrict__ Ps = P + (int64_t)sp * split_stride;
+  const int64_t c = c0 + 8 * kk;
+  const bool vst = (ldp & 3) == 0 && c + 7 < n;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = j0 + 16 * t + p;
+    if (j >= ncols) continue;
+    float* __restrict__ prow = Ps + (int64_t)j * ldp;
+    const floatx4 o0 = {acc[0][t][0], acc[1][t][0], acc[0][t][1], acc[1][t][1]};
+    const floatx4 o1 = {acc[0][t][2], acc[1][t][2], acc[0][t][3], acc[1][t][3]};
+    if (vst) {
+      *reinterpret_cast<floatx4*>(prow + c) = o0;
+      *reinterpret_cast<floatx4*>(prow + c + 4) = o1;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (c + e < n) prow[c + e] = o0[e];
+        if (c + 4 + e < n) prow[c + 4 + e] = o1[e];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 template <int NT2>
@@ -538,13 +730,21 @@ int adj_nt_for(int ncols) {
 }
 
 // Row split of the adjoint product: among split counts giving at least two
-// rounds of `slots` concurrent blocks, the one whose last round is fullest
-// (ties to fewer splits, i.e. less partial-sum traffic); rows per split are a
-// multiple of the LDS stage.
+// rounds of `slots` concurrent blocks and float32 chains of at most
+// ADJ_MAX_CHAIN rows (up to twice the smallest such count), the one whose last
+// round is fullest (ties to fewer splits, i.e. less partial-sum traffic); rows
+// per split are a multiple of the LDS stage.
 void adj_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split) {
-  const int64_t per = (int64_t)((ncols + 63) / 64) * ((n + 255) / 256);
+  // blocks per row split: 64 Z columns x 256 A columns, or for a wide Z (the kernel
+  // launch_adj_f32 picks for more than 64 columns) 16 adjw_tiles Z columns x 128 A columns
+  const int64_t wcols = 16 * adjw_tiles(ncols);
+  const int64_t per = ncols > 64 ? (int64_t)((ncols + wcols - 1) / wcols) * ((n + ADJW_ACOLS - 1) / ADJW_ACOLS)
+                                 : (int64_t)((ncols + 63) / 64) * ((n + 255) / 256);
   int64_t lo = (2 * slots + per - 1) / per;
-  int64_t hi = lo * 4 + 8;
+  // every float32 chain (one split) within ADJ_MAX_CHAIN rows
+  const int64_t lo_chain = (m + ADJ_MAX_CHAIN - 1) / ADJ_MAX_CHAIN;
+  if (lo < lo_chain) lo = lo_chain;
+  int64_t hi = lo * 2 > lo + 8 ? lo * 2 : lo + 8;
   const int64_t maxs = m / 64 > 0 ? m / 64 : 1;
   if (lo > maxs) lo = maxs;
   if (hi > maxs) hi = maxs;
@@ -572,6 +772,25 @@ hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
   if (a.A == nullptr || a.shift == nullptr || a.Z == nullptr || a.P == nullptr) return hipErrorInvalidValue;
   if (a.lda < a.n || a.ldp < a.n || a.rows_per_split % 4 != 0) return hipErrorInvalidValue;
   if ((int64_t)a.nsplit * a.rows_per_split < a.m) return hipErrorInvalidValue;
+  // a wide Z (the T pass) read in one pass over A when its layout allows 16-byte pieces
+  const bool wide = a.ncols > 64 && !a.ones && a.vec && a.n % 2 == 0 && a.ncols % 4 == 0 && a.ldz % 4 == 0 &&
+                    (reinterpret_cast<uintptr_t>(a.Z) & 15) == 0;
+  if (wide) {
+    const int nt = adjw_tiles(a.ncols);
+    const int jt = (a.ncols + 16 * nt - 1) / (16 * nt);
+    const int ct = (int)((a.n + ADJW_ACOLS - 1) / ADJW_ACOLS);
+    const dim3 grid((unsigned)((int64_t)jt * ct * a.nsplit));
+    if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
+    if (nt == 8)
+      hipLaunchKernelGGL((adj_wide_kernel<8, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+                         a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jt, ct, a.P, a.ldp, a.split_stride);
+    else
+      hipLaunchKernelGGL((adj_wide_kernel<12, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+                         a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jt, ct, a.P, a.ldp, a.split_stride);
+    hipError_t e = hipGetLastError();
+    if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
+    return e;
+  }
   const int jtiles = (a.ncols + (a.ones ? 1 : 0) + 63) / 64;
   const int ctiles = (int)((a.n + 255) / 256);
   const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;

@@ -185,6 +185,7 @@ struct rpca_plan_s {
   rpca_stats stats{};
   std::vector<EventPair> ev_fwd, ev_adj;
   int nev_fwd = 0, nev_adj = 0;
+  int tp_ev0 = 0, tp_ev1 = 0;  // adjoint events [tp_ev0, tp_ev1) belong to the T pass
 
   ~rpca_plan_s() {
     DevGuard g(device);
@@ -740,6 +741,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   sx = rpca_stats{};
   plan->have_state = false;
   plan->nev_fwd = plan->nev_adj = 0;
+  plan->tp_ev0 = plan->tp_ev1 = 0;
   plan->A_last = streamed ? nullptr : A;
   plan->lda_last = lda;
   const bool center = plan->d.center != 0;
@@ -1143,6 +1145,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const auto t_qr = std::chrono::steady_clock::now();
 
   // Step 3: T = A~^T Q  (n x L, FP64 after the ordered split reduction)
+  plan->tp_ev0 = plan->nev_adj;
   if (center) {
     RPCA_TRY(launch_colsum(ST_F32, plan->Q32, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
     RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, L, 1.0, plan->zsum, nullptr, nullptr, st));
@@ -1216,6 +1219,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     sx.passes += 1;
     sx.a_bytes_read += m * n * bpe;
   }
+  plan->tp_ev1 = plan->nev_adj;
   RPCA_TRY(hipStreamSynchronize(st));
   const auto t_tpass = std::chrono::steady_clock::now();
 
@@ -1257,9 +1261,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       float t = 0.f;
       RPCA_TRY(hipEventElapsedTime(&t, plan->ev_adj[q].a, plan->ev_adj[q].b));
       sx.ms_adj_kernel += t;
+      if (q >= plan->tp_ev0 && q < plan->tp_ev1) sx.ms_tpass_kernel += t;
     }
     sx.fwd_launches = plan->nev_fwd;
     sx.adj_launches = plan->nev_adj;
+    sx.tpass_launches = plan->tp_ev1 - plan->tp_ev0;
   }
   plan->have_state = true;
   plan->Qfinal_is_Q1 = (Qfinal == plan->Q1);

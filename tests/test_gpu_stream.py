@@ -133,7 +133,11 @@ def test_device_callback_matches_host_pinned():
 
 def test_device_regenerated_rows_match_in_core():
     """Rows regenerated by the seeded device generator in every pass (the on-the-fly mode) against the
-    same matrix generated once and factored in core."""
+    same matrix generated once and factored in core.  The two runs split the row sums differently
+    (6000-row panels against the in-core row split), so they agree to float32 accuracy, not bit for
+    bit: singular values within 1e-6 relative, vectors within the float32 vector tolerance 1e-4 in
+    2-norm (the 20th vector, gap sigma_20 - sigma_21 = 0.013 against sigma_1 = 0.9, is 5e-5 from the
+    float64 oracle on either path)."""
     _need_gpu()
     from synth import gpu as SG
     from paper_1007_5510_amd import rpca, _lib
@@ -161,7 +165,7 @@ def test_device_regenerated_rows_match_in_core():
     S0, S1 = S0.cpu().double().numpy(), S1.cpu().double().numpy()
     assert np.abs(S0 - S1).max() / S0[0] < 1e-6
     V0, V1 = V0.cpu().double().numpy(), V1.cpu().double().numpy()
-    assert np.linalg.norm(V0 - V1, axis=0).max() < 1e-5
+    assert np.linalg.norm(V0 - V1, axis=0).max() < 1e-4
 
 
 def test_device_callback_error_is_reported():
