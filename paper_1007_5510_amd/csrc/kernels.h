@@ -69,7 +69,6 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
 hipError_t launch_fwd_f32(const FwdArgs& a, hipStream_t st);
 // K split for the forward product over `slots` concurrent blocks
 void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);
-int adj_nt_for(int ncols);  // 16-column tiles per wave used by the adjoint kernels
 // row split of the adjoint product over `slots` concurrent blocks
 void adj_split(int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit, int64_t* rows_per_split);
 hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st);

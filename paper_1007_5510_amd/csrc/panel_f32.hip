@@ -724,11 +724,6 @@ void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk
   *kchunk = chunk;
 }
 
-int adj_nt_for(int ncols) {
-  (void)ncols;
-  return 4;  // 64 Z columns per block (j tile)
-}
-
 // Row split of the adjoint product: among split counts giving at least two
 // rounds of `slots` concurrent blocks and float32 chains of at most
 // ADJ_MAX_CHAIN rows (up to twice the smallest such count), the one whose last
