@@ -306,3 +306,18 @@ def test_householder_step2_at_its_width_limit():
     with pytest.raises(_lib.RPCAError) as e:
         run_gpu(p["A"], k, 65, i, G=F.gaussian_G(7070, n, 65), flags=_lib.FLAG_FORCE_HOUSEHOLDER)
     assert e.value.code == 7  # RPCA_ERR_QR_BREAKDOWN: L = 260 > 256
+
+
+def test_wide_t_pass_matches_fallback_bitwise():
+    """The T pass with L = 120 runs on the wide-Z adjoint when A's rows allow vector loads and on the
+    64-column adjoint otherwise; both sum every output over the same rows in the same order, so the
+    same matrix with an aligned and with an odd leading dimension factors to identical bits."""
+    m, n, k, l, i = 6000, 1000, 20, 40, 2
+    sigma = 0.9 ** np.arange(n, dtype=np.float64)
+    p = F.svd_problem(6100, m, n, sigma)
+    G = F.gaussian_G(6100, n, l)
+    a = run_gpu(p["A"], k, l, i, G=G, lda=1004)  # 16-byte rows: vector loads, wide T pass
+    b = run_gpu(p["A"], k, l, i, G=G, lda=1001)  # odd stride: scalar loads, 64-column T pass
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a[3].state("T").cpu().numpy(), b[3].state("T").cpu().numpy())
