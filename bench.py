@@ -626,17 +626,40 @@ def main():
                 "frac": round(fwd_tf64 / PEAK_FP64_TFLOPS, 4), "traffic": None, "algorithmic_bytes": m * n * 4,
                 "kernel": "fwd64_kernel", "avg_launch_ms": round(fwd_avg, 4)}
     elif split:
-        # split products are meant to be bound by the read of A: algorithmic bytes = one read of A
-        if adj_ms >= fwd_ms:
-            dom = {"kernel": "adj_x6_kernel", "avg_ms": adj_avg, "tf": adj_tf}
+        # per kernel: the forward launches (l columns), the power-step adjoints (l columns) and the
+        # T pass (L columns; one read of A in adj_x6w_kernel when L is in (64, 192]); each bound by
+        # the larger of one read of A at the HBM peak and six bfloat16 products at the bfloat16 peak
+        tp_kernel = "adj_x6w_kernel" if 64 < L <= 192 else "adj_x6_kernel"
+        per = {"fwd_x6_kernel": [nf, fwd_ms, l]}
+        if tp_kernel == "adj_x6w_kernel":
+            per["adj_x6_kernel"] = [na - ntp, adj_ms - tp_ms, l]
+            per["adj_x6w_kernel"] = [ntp, tp_ms, L]
         else:
-            dom = {"kernel": "fwd_x6_kernel", "avg_ms": fwd_avg, "tf": fwd_tf}
-        gbs = m * n * 4 / (dom["avg_ms"] * 1e-3) / 1e9
-        log(f"[bench] {dom['kernel']} avg {dom['avg_ms']:.3f} ms = {gbs:.0f} GB/s of A")
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                "algorithmic_bytes": m * n * 4, "kernel": dom["kernel"], "avg_launch_ms": round(dom["avg_ms"], 4),
-                "algorithmic_tflops_f32": round(dom["tf"], 3)}
+            per["adj_x6_kernel"] = [na, adj_ms, (l * i + L) / (i + 1)]
+        kern = {}
+        for name, (cnt, tot, cols) in per.items():
+            if cnt <= 0:
+                continue
+            avg = tot / cnt
+            gbs = m * n * 4 / (avg * 1e-3) / 1e9
+            bf_tf = 6 * 2.0 * m * n * cols / (avg * 1e-3) / 1e12
+            t_h = m * n * 4 / (PEAK_HBM_GBS * 1e9) * 1e3
+            t_m = 6 * 2.0 * m * n * cols / (2500.0 * 1e12) * 1e3
+            kern[name] = {"launches_per_step": round(cnt / args.steps, 2), "ms_per_step": round(tot / args.steps, 3),
+                          "avg_launch_ms": round(avg, 4), "gbs_of_A": round(gbs, 1),
+                          "bf16_tflops": round(bf_tf, 1), "bound": "hbm" if t_h >= t_m else "mfma",
+                          "frac": round(max(t_h, t_m) / avg, 4)}
+            log(f"[bench] {name}: {cnt / args.steps:.0f} launches, avg {avg:.3f} ms, {gbs:.0f} GB/s of A, "
+                f"{bf_tf:.0f} bf16 TF/s")
+        dom_name = max(kern, key=lambda nm: kern[nm]["ms_per_step"])
+        dom = kern[dom_name]
+        if dom["bound"] == "hbm":
+            roof = {"bound": "hbm", "achieved": dom["gbs_of_A"], "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+        else:
+            roof = {"bound": "mfma", "achieved": dom["bf16_tflops"], "peak": 2500.0, "unit": "TFLOP/s"}
+        roof.update({"frac": dom["frac"], "traffic": None, "algorithmic_bytes": m * n * 4, "kernel": dom_name,
+                     "avg_launch_ms": dom["avg_launch_ms"], "dominance": "largest summed launch time per step",
+                     "kernels": kern})
     elif storage == "f32":
         # per kernel: the forward launches (l columns), the power-step adjoints (l columns, pass 0's
         # implicit ones column not counted) and the T pass (L columns; the wide-Z kernel when its

@@ -67,6 +67,23 @@ RPCA_DEV floatx16 x6_six(const x6_u32x4 (&a)[3], const x6_u32x4 (&b)[3], floatx1
   return x6_mfma(a[0], b[0], acc);
 }
 
+// the same sums for two tiles (za with acc0, zb with acc1) with the two chains interleaved
+RPCA_DEV void x6_six2(const x6_u32x4 (&za)[3], const x6_u32x4 (&zb)[3], const x6_u32x4 (&b)[3], floatx16& acc0,
+                      floatx16& acc1) {
+  acc0 = x6_mfma(za[2], b[0], acc0);
+  acc1 = x6_mfma(zb[2], b[0], acc1);
+  acc0 = x6_mfma(za[1], b[1], acc0);
+  acc1 = x6_mfma(zb[1], b[1], acc1);
+  acc0 = x6_mfma(za[0], b[2], acc0);
+  acc1 = x6_mfma(zb[0], b[2], acc1);
+  acc0 = x6_mfma(za[1], b[0], acc0);
+  acc1 = x6_mfma(zb[1], b[0], acc1);
+  acc0 = x6_mfma(za[0], b[1], acc0);
+  acc1 = x6_mfma(zb[0], b[1], acc1);
+  acc0 = x6_mfma(za[0], b[0], acc0);
+  acc1 = x6_mfma(zb[0], b[0], acc1);
+}
+
 // ---------------------------------------------------------------------------
 // operand planes
 // ---------------------------------------------------------------------------
@@ -487,6 +504,170 @@ __global__ __launch_bounds__(256, 2) void adj_x6_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// wide adjoint for the T pass: one read of A for up to 32 NT columns of Z.
+// Each wave owns 32 columns of A (lane i: column c0 + i, one float per row) x
+// 32 NT columns of Z (NT tiles of 32); 8 waves per block cover 256 columns of A
+// and share the Z planes of a stage in LDS.  Two tiles are computed at a time so
+// that two accumulation chains are in flight.  Every output element sees the same
+// rows, K-steps, splits and six-term order as in adj_x6_kernel, so the partial
+// sums are the same.  Six bfloat16 products over up to 192 columns make the pass
+// bound by the matrix cores rather than by the read of A.  Requires
+// rows_per_split % 32 == 0 (a stage of Z rows stays inside the zero-padded planes)
+// and 32 NT <= the planes' columns.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(512, 1) void adj_x6w_kernel(
+    const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
+    const uint16_t* __restrict__ Zp, int64_t ldzs, int64_t zplane, int nout, int64_t rows_per_split, int nsplit,
+    int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride) {
+  constexpr int ZC = 32 * NT;            // Z columns of the block
+  constexpr int NCH = 3 * ZC * 4;        // 16-byte chunks per stage: 3 planes x ZC columns x 4 row groups
+  constexpr int ZQ = (NCH + 511) / 512;  // chunks per thread
+  static_assert(ZQ * 512 - NCH <= 3 * ZC, "spare chunks need a padding slot each");
+  __shared__ __attribute__((aligned(16))) uint16_t Zs[2][3][ZC][X6_ZP];
+  const int64_t total = (int64_t)ctiles * nsplit;
+  const int64_t logical = x6_xcd_remap(blockIdx.x, total);
+  const int ct = (int)(logical % ctiles);
+  const int sp = (int)(logical / ctiles);
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, g = lane >> 5;
+  const int64_t c = (int64_t)ct * 256 + wave * 32 + li;
+  const int64_t cc = c < n ? c : n - 1;  // clamped column
+  const int64_t rbeg = (int64_t)sp * rows_per_split;
+  const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
+  const float sh = shift[cc];
+  const float* __restrict__ acol = A + cc;
+  // cooperative Z loader: chunk e = tid + 512 q -> plane e / (4 ZC), column (e / 4) % ZC,
+  // rows 8 (e % 4) .. + 8 of the stage.  Chunks past NCH load chunk e - NCH again and
+  // store it into the unused padding of a row (columns 32 .. 39), so no store needs a branch.
+  int64_t zoff[ZQ];
+  int ldsoff[ZQ];
+#pragma unroll
+  for (int q = 0; q < ZQ; ++q) {
+    const int e = tid + 512 * q;
+    const int es = e < NCH ? e : e - NCH;
+    const int pl = es / (4 * ZC), col = (es / 4) % ZC, rg = es % 4;
+    zoff[q] = (int64_t)pl * zplane + (int64_t)col * ldzs + 8 * rg;
+    ldsoff[q] = e < NCH ? (pl * ZC + col) * X6_ZP + 8 * rg : es * X6_ZP + 32;
+  }
+
+  floatx16 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[t][e] = 0.f;
+  struct AStage {
+    float a[16];  // row 16 s + 8 g + u at a[8 s + u]
+  };
+  struct ZStage {
+    x6_u32x4 z[ZQ];
+  };
+  auto load_a = [&](AStage& b, int64_t rb) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b.a[8 * s + u] = acol[(rb + 16 * s + 8 * g + u) * lda];
+  };
+  auto load_z = [&](ZStage& b, int64_t rb) {
+#pragma unroll
+    for (int q = 0; q < ZQ; ++q) b.z[q] = *reinterpret_cast<const x6_u32x4*>(Zp + zoff[q] + rb);
+  };
+  auto store_z = [&](const ZStage& b, int buf) {
+    uint16_t* base = &Zs[buf][0][0][0];
+#pragma unroll
+    for (int q = 0; q < ZQ; ++q) *reinterpret_cast<x6_u32x4*>(base + ldsoff[q]) = b.z[q];
+  };
+  auto compute = [&](const AStage& b, int buf) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      // B operand (A, shifted and split): rows 16 s + 8 g .. + 8 of column c
+      X6Parts pu[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) pu[u] = x6_split(b.a[8 * s + 2 * u] - sh, b.a[8 * s + 2 * u + 1] - sh);
+      const x6_u32x4 bp[3] = {x6_u32x4{pu[0].h, pu[1].h, pu[2].h, pu[3].h},
+                              x6_u32x4{pu[0].m, pu[1].m, pu[2].m, pu[3].m},
+                              x6_u32x4{pu[0].l, pu[1].l, pu[2].l, pu[3].l}};
+      // two tiles at a time: two independent accumulation chains
+#pragma unroll
+      for (int t = 0; t < NT; t += 2) {
+        x6_u32x4 za[3], zb[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          za[q] = *reinterpret_cast<const x6_u32x4*>(&Zs[buf][q][32 * t + li][16 * s + 8 * g]);
+          zb[q] = *reinterpret_cast<const x6_u32x4*>(&Zs[buf][q][32 * t + 32 + li][16 * s + 8 * g]);
+        }
+        x6_six2(za, zb, bp, acc[t], acc[t + 1]);
+      }
+    }
+  };
+
+  // two register stages used alternately, prologue drained (as in adj_x6_kernel)
+  const int64_t nfull = (rend - rbeg) / X6_RS;
+  if (nfull > 0) {
+    AStage a0, a1;
+    ZStage zr;
+    load_z(zr, rbeg);
+    load_a(a0, rbeg);
+    store_z(zr, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int64_t st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+      const int64_t r1 = rbeg + (st + 1) * X6_RS;
+      load_z(zr, r1);
+      load_a(a1, r1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a0, 0);
+      store_z(zr, 1);
+      __syncthreads();
+      // past the last whole stage the prefetch re-reads stage st + 1
+      const int64_t r2 = rbeg + (st + 2 < nfull ? st + 2 : st + 1) * X6_RS;
+      load_z(zr, r2);
+      load_a(a0, r2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_z(zr, 0);
+      __syncthreads();
+    }
+    if (st < nfull) {  // odd stage count: the last stage is in a0, Z in buffer 0
+      compute(a0, 0);
+      __syncthreads();
+    }
+  }
+  // tail rows (fewer than a stage): rows at or past rend read as the shift (zero after shifting)
+  const int64_t rt = rbeg + nfull * X6_RS;
+  if (rt < rend) {
+    const int buf = (int)(nfull & 1);
+    ZStage zt;
+    load_z(zt, rt);
+    store_z(zt, buf);
+    AStage at;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t r = rt + 16 * s + 8 * g + u;
+        at.a[8 * s + u] = r < rend ? acol[r * lda] : sh;
+      }
+    __syncthreads();
+    compute(at, buf);
+  }
+
+  // D[Z column][A column]: register e of tile t holds Z column 32 t + 8 (e / 4) + 4 g + e % 4
+  float* __restrict__ Ps = P + (int64_t)sp * split_stride + c;
+  if (c >= n) return;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int j = 32 * t + 8 * (e >> 2) + 4 * g + (e & 3);
+      if (j < nout) Ps[(int64_t)j * ldp] = acc[t][e];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_split3_x(const float* Xt, int64_t ldx, int64_t n, int ncols, int cpad, uint16_t* Xp, int64_t ldxs,
@@ -540,6 +721,25 @@ hipError_t launch_adj_x6(const AdjArgs& a, hipStream_t st) {
   if (a.ldzs3 % 64 != 0 || a.zplane3 % 8 != 0 || a.ldzs3 < a.m) return hipErrorInvalidValue;
   if ((int64_t)a.nsplit * a.rows_per_split < a.m || a.rows_per_split % 8 != 0) return hipErrorInvalidValue;
   const int nout = a.ncols + (a.ones ? 1 : 0);
+  // the T pass (more than 64 columns, up to 192): one read of A in the wide kernel
+  const int64_t zcols = a.zplane3 / a.ldzs3;
+  const int wnt = nout <= 128 ? 4 : 6;
+  if (nout > 64 && nout <= 192 && 32 * wnt <= zcols && a.rows_per_split % X6_RS == 0) {
+    const int wct = (int)((a.n + 255) / 256);
+    const int64_t wtotal = (int64_t)wct * a.nsplit;
+    if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
+    if (wnt == 4)
+      hipLaunchKernelGGL(adj_x6w_kernel<4>, dim3((unsigned)wtotal), dim3(512), 0, st, (const float*)a.A, a.lda, a.m,
+                         a.n, a.shift, a.Z3, a.ldzs3, a.zplane3, nout, a.rows_per_split, a.nsplit, wct, a.P, a.ldp,
+                         a.split_stride);
+    else
+      hipLaunchKernelGGL(adj_x6w_kernel<6>, dim3((unsigned)wtotal), dim3(512), 0, st, (const float*)a.A, a.lda, a.m,
+                         a.n, a.shift, a.Z3, a.ldzs3, a.zplane3, nout, a.rows_per_split, a.nsplit, wct, a.P, a.ldp,
+                         a.split_stride);
+    hipError_t e = hipGetLastError();
+    if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
+    return e;
+  }
   const int jtiles = (nout + 63) / 64;
   const int ctiles = (int)((a.n + 255) / 256);
   const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;

@@ -50,6 +50,7 @@ def test_split_intermediates_match_oracle():
     (900, 300, 6, 8, 0, None, 1e-4),      # i = 0
     (4000, 1500, 30, 40, 2, None, 2e-3),  # several Z tiles in the T pass (L = 120)
     (5000, 1200, 40, 70, 2, None, 2e-3),  # two forward column tiles (l = 70)
+    (6100, 1002, 40, 60, 2, None, 2e-3),  # T pass over 180 columns in one read of A, ragged column tile
 ])
 def test_split_shapes_and_edges(m, n, k, l, i, lda, v_tol):
     sigma = 0.93 ** np.arange(n, dtype=np.float64)
