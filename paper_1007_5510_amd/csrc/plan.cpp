@@ -121,7 +121,7 @@ struct rpca_plan_s {
   double* zsum = nullptr;   // L
   double* sqp = nullptr;    // sum of squares partials
   float* corr = nullptr;    // L
-  int* flags = nullptr;     // [0] nonfinite, [1] chol breakdown round 1, [2] round 2, [3] round 3
+  int* flags = nullptr;     // [0] nonfinite, [1..3] Cholesky breakdown in the first, second, third Cholesky QR
   uint16_t* Xh = nullptr;   // low-precision storage only
   uint16_t* Xl = nullptr;
   uint16_t* Zh = nullptr;
