@@ -51,6 +51,8 @@ def test_split_intermediates_match_oracle():
     (4000, 1500, 30, 40, 2, None, 2e-3),  # several Z tiles in the T pass (L = 120)
     (5000, 1200, 40, 70, 2, None, 2e-3),  # two forward column tiles (l = 70)
     (6100, 1002, 40, 60, 2, None, 2e-3),  # T pass over 180 columns in one read of A, ragged column tile
+    (3000, 900, 20, 64, 1, None, 2e-3),   # T pass of exactly 128 columns; pass 0 adjoint of 65 (ones column)
+    (2500, 640, 30, 48, 3, 644, 2e-3),    # T pass of exactly 192 columns, padded lda
 ])
 def test_split_shapes_and_edges(m, n, k, l, i, lda, v_tol):
     sigma = 0.93 ** np.arange(n, dtype=np.float64)
