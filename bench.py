@@ -35,16 +35,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None.
+def measured_traffic(kernel, source="panel_f32.hip", summary_name="incore_f32_hbm_counters.md"):
+    """HBM bytes per launch of `kernel` from a committed counter summary, or None.
 
     The summary lists calibrated FETCH_SIZE / WRITE_SIZE averages together with
-    the sha256 prefix of the panel-kernel source they were taken on; a source
-    change since then makes the numbers stale and they are not reported.
+    the sha256 prefix of the kernel source they were taken on; a source change
+    since then makes the numbers stale and they are not reported.
     """
     import hashlib
-    src = os.path.join(ROOT, "paper_1007_5510_amd", "csrc", "panel_f32.hip")
-    summary = os.path.join(ROOT, "profiles", "incore_f32_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_1007_5510_amd", "csrc", source)
+    summary = os.path.join(ROOT, "profiles", summary_name)
     try:
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
         for line in open(summary):
@@ -657,7 +657,10 @@ def main():
             roof = {"bound": "hbm", "achieved": dom["gbs_of_A"], "peak": PEAK_HBM_GBS, "unit": "GB/s"}
         else:
             roof = {"bound": "mfma", "achieved": dom["bf16_tflops"], "peak": 2500.0, "unit": "TFLOP/s"}
-        roof.update({"frac": dom["frac"], "traffic": None, "algorithmic_bytes": m * n * 4, "kernel": dom_name,
+        tr = measured_traffic(dom_name, "panel_x6.hip", "incore_split_hbm_counters.md")
+        roof.update({"frac": dom["frac"], "traffic": round(tr["fetch"] + tr["write"]) if tr else None,
+                     "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_bytes": m * n * 4, "kernel": dom_name,
                      "avg_launch_ms": dom["avg_launch_ms"], "dominance": "largest summed launch time per step",
                      "kernels": kern})
     elif storage == "f32":

@@ -54,3 +54,19 @@ def test_traffic_reported_only_for_the_profiled_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("adj_f32_kernel") is None  # counters of another source
     src.write_text("// kernel source, changed\n")
     assert bench.measured_traffic("fwd32_kernel") is None
+
+
+def test_traffic_of_another_source_uses_its_own_summary(tmp_path, monkeypatch):
+    import bench
+    src_dir = tmp_path / "paper_1007_5510_amd" / "csrc"
+    src_dir.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    (src_dir / "panel_f32.hip").write_text("// float32 kernels\n")
+    x6 = src_dir / "panel_x6.hip"
+    x6.write_text("// split kernels\n")
+    sha = hashlib.sha256(x6.read_bytes()).hexdigest()[:16]
+    (tmp_path / "profiles" / "incore_split_hbm_counters.md").write_text(f"traffic fwd_x6_kernel {sha} 300 40\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("fwd_x6_kernel", "panel_x6.hip", "incore_split_hbm_counters.md") == \
+        {"fetch": 300.0, "write": 40.0}
+    assert bench.measured_traffic("fwd_x6_kernel") is None  # not in the float32 summary
