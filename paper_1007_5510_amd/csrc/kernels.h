@@ -80,6 +80,8 @@ hipError_t launch_split3_x(const float* Xt, int64_t ldx, int64_t n, int ncols, i
 hipError_t launch_split3_zt(const float* Z, int64_t ldz, int64_t m, int ncols, bool ones, int cpad, uint16_t* Zp,
                             int64_t ldzs, int64_t plane, hipStream_t st);
 hipError_t launch_fwd_x6(const FwdArgs& a, hipStream_t st);
+// 65 to 192 output columns (with rows_per_split % 32 == 0 and planes at least that wide) go to the
+// one-read wide kernel, others to 64-column tiles
 hipError_t launch_adj_x6(const AdjArgs& a, hipStream_t st);
 hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st);
 hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st);
