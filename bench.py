@@ -218,7 +218,7 @@ PAPER_TABLES = {
 
 
 def run_paper_example(args):
-    """The paper's first or second example (Section 5.1): A = E S F with unitary DCT-II matrices E, F and
+    """The paper's first or second example (Section 6.1): A = E S F with unitary DCT-II matrices E, F and
     the example's diagonal S, at the sizes of Tables 1a / 2a, A resident in HBM as float32 (the paper
     stores A in single precision); l = k + 2, i = 3, no centring.  A is built on the device outside the
     timed region.  For each table row: t_PCA (one factorisation, averaged over --steps), the Appendix

@@ -101,7 +101,7 @@ enum {
    * float64 on the FP64 matrix cores, each float32 entry of A exact in
    * float64, and keep H in float64 for Step 2 -- the arithmetic of the
    * paper's experiments (A stored in single precision, computations in
-   * double, Section 5).  Needed when the spectrum spans a wide range above
+   * double, Section 6).  Needed when the spectrum spans a wide range above
    * sigma_{k+1} and has a long, heavy tail, as in the paper's first example:
    * float32 products then lose the directions that the later blocks carry
    * below ~1e-7 of the leading ones.  Centring enters as exact float64
@@ -151,7 +151,7 @@ typedef struct rpca_plan_s* rpca_plan_t;
  * synchronisation, no work on other streams that dst depends on).  It is
  * called once per panel per pass, panels in row order, and the same rows must
  * come back identical in every pass (Section 4.1: rows evaluated on demand,
- * every contribution of a row made at once; Section 5.3: regenerated rows
+ * every contribution of a row made at once; Section 6.1, third example: regenerated rows
  * restart their generator from the same seed).                              */
 typedef int (*rpca_device_panel_cb)(void* user, int64_t row0, int64_t nrows, float* dst, int64_t ld,
                                     void* hip_stream);

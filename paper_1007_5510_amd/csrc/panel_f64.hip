@@ -1,7 +1,7 @@
 // Passes over the float32 data matrix of Step 1 (eqs. first_prod .. last_prod)
 // carried in float64 on the gfx950 FP64 matrix cores (v_mfma_f64_16x16x4_f64),
 // the arithmetic the paper's experiments use (matrix stored in single
-// precision, every computation in double precision, Section 5):
+// precision, every computation in double precision, Section 6):
 //
 //   fwd:  Z = alpha * A X            m x c, X held transposed (Xt, c x n)
 //   adj:  P_s = (A_s^T Z_s)^T        c x n per row split s

@@ -4,7 +4,7 @@ Every matrix is addressable by row panel: a panel [row0, row0+rows) can be
 rebuilt without the rest, which is what the out-of-core and callback sources
 need.  Factor matrices are float64; the stored data matrix A is float32 with
 round-to-nearest-even from the float64 value, the storage precision the paper
-uses for the matrix on disk (Section 5, opening paragraphs).
+uses for the matrix on disk (Section 6, opening paragraphs).
 
 Workloads
 ---------
@@ -17,7 +17,7 @@ Workloads
   (200000 x 20000, r=50, sigma_j=1/j, noise 1e-3, offsets) and the streaming
   (r=100, sigma_j=exp(-j/20), noise 1e-4, no offsets) structure.
 * ``example_dct``: A = E S F with unitary DCT-II matrices E, F and the paper's
-  diagonal S of its first and second examples (Section 5.1).
+  diagonal S of its first and second examples (Section 6.1).
 """
 from __future__ import annotations
 

@@ -94,7 +94,7 @@ def normals(out, seed, stream_id, start):
 
 def example_dct_rows(which: int, m: int, n: int, out, chunk_bytes: int = 1 << 32):
     """Fill ``out`` (an m x n float32 tensor, any device) with A = E S F of the paper's first or second
-    example (Section 5.1): E, F unitary DCT-II of orders m and n (first n columns of E), S the
+    example (Section 6.1): E, F unitary DCT-II of orders m and n (first n columns of E), S the
     example's diagonal.  Matches ``synth.fixtures.example_dct(which, m, n)["A"]``.
 
     A row of A is the inverse DCT (DCT-III) of sigma o E[r, :n], done in float64 as one complex FFT of

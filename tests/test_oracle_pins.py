@@ -203,7 +203,7 @@ def test_centering_equals_explicit_centering():
 
 
 def test_pass_count_matches_cost_model():
-    """Section 4.3's data-transfer total 2(i+1) m n entries (Step 1 plus Step 3)."""
+    """Section 5.2's data-transfer total 2(i+1) m n entries (Step 1 plus Step 3)."""
     p = F.plain_small(seed=2, m=300, n=100)
     for i in (0, 1, 3):
         G = F.gaussian_G(2, 100, 5)
@@ -449,3 +449,198 @@ def test_backward_oracle_converges_to_full_svd_gradient():
     loss.backward()
     ref = At.grad.numpy()
     assert np.linalg.norm(dA - ref) <= 2e-5 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- pins of the remaining helpers
+def _first_max_sign(col):
+    """Sign of the first entry of largest magnitude, by a plain scan (ties keep the earlier index)."""
+    best, sgn = -1.0, 1.0
+    for x in col:
+        if abs(x) > best:
+            best, sgn = abs(x), (1.0 if x >= 0 else -1.0)
+    return sgn if best > 0 else 1.0
+
+
+def _sign_rule_ok(fn):
+    V = np.array([[0.1, -0.5, 0.3, 0.0, 0.0],
+                  [-0.7, 0.5, -0.3, 0.2, 0.0],
+                  [0.2, 0.1, 0.1, -0.2, 0.0]])
+    # column 0: largest |.| is -0.7 -> flip; column 1: tie -0.5 / 0.5, first is negative -> flip;
+    # column 2: tie 0.3 / -0.3, first positive -> keep; column 3: tie 0.2 / -0.2 -> keep; zero column -> keep
+    want = np.array([-1.0, -1.0, 1.0, 1.0, 1.0])
+    return np.array_equal(np.asarray(fn(V), dtype=np.float64), want)
+
+
+def test_sign_convention_hand_built():
+    """Reading of the unspecified sign: largest-magnitude entry of v_j positive, ties to the lowest index."""
+    assert _sign_rule_ok(O.sign_convention)
+    # planted mistakes: ties to the last index, signed maximum instead of magnitude, no flip at all
+    last_tie = lambda V: np.array([np.sign(V[V.shape[0] - 1 - np.argmax(np.abs(V[::-1, j])), j]) or 1.0
+                                   for j in range(V.shape[1])])
+    signed_max = lambda V: np.sign(V[np.argmax(V, axis=0), np.arange(V.shape[1])]) + (V.max(axis=0) == 0)
+    no_flip = lambda V: np.ones(V.shape[1])
+    for bad in (last_tie, signed_max, no_flip):
+        assert not _sign_rule_ok(bad)
+
+
+def test_sign_convention_applied_to_outputs():
+    """Every returned v_j has its first largest-magnitude entry positive, and u_j follows (A^T u_j = s_j v_j)."""
+    p = F.plain_small(seed=21, m=300, n=120)
+    G = F.gaussian_G(21, 120, 8)
+    r = O.rpca(p["A"], 6, 8, 1, G)
+    for j in range(6):
+        assert _first_max_sign(r.V[:, j]) == 1.0
+    At_U = p["A"].astype(np.float64).T @ r.U
+    assert np.max(np.abs(At_U - r.V * r.S)) < 1e-12
+
+
+def test_error_bound_values():
+    """Eq. sort_of_svd at hand-computed points.
+
+    C1 (k = 10, n = 1000, i = 1, C = 100): (10^6)^(1/3) = 100 and min(1, 100/1000) = 0.1, so the
+    factor is sqrt(100.1) = 10.004998750624610...; i = 0, k = 2, n = 50: sqrt(10^4 + 1);
+    C = 10, k = 5, n = 200, i = 2: (10^4)^(1/5) = 10^0.8 plus min(1, 0.05).
+    """
+    cases = [((10, 1000, 1, 1.0, 100.0), 10.004998750624610),
+             ((10, 1000, 1, 0.25, 100.0), 0.25 * 10.004998750624610),
+             ((2, 50, 0, 1.0, 100.0), 100.00499987500625),
+             ((5, 200, 2, 1.0, 10.0), math.sqrt(6.309573444801933 + 0.05))]
+
+    def ok(fn):
+        return all(abs(fn(k, n, i, s, C) - want) <= 1e-13 * want for (k, n, i, s, C), want in cases)
+
+    assert ok(O.error_bound)
+    planted = [
+        lambda k, n, i, s, C=100.0: math.sqrt((C * k * n) ** (1.0 / (2 * i)) + min(1.0, C / n)) * s if i else s,
+        lambda k, n, i, s, C=100.0: math.sqrt((C * k * n) ** (1.0 / (2 * i + 1))) * s,
+        lambda k, n, i, s, C=100.0: math.sqrt((C * k * n) ** (1.0 / (2 * i + 1)) + min(1.0, n / C)) * s,
+        lambda k, n, i, s, C=100.0: ((C * k * n) ** (1.0 / (2 * i + 1)) + min(1.0, C / n)) * s,
+    ]
+    for bad in planted:
+        assert not ok(bad)
+
+
+def _gram_ok(fn):
+    rng = np.random.default_rng(17)
+    A = rng.standard_normal((90, 30)).astype(np.float32) + np.linspace(0, 2, 30, dtype=np.float32)
+    for center in (False, True):
+        # a general (not orthonormal) U, S, V: the Gram form is exact for any factors
+        U = rng.standard_normal((90, 4))
+        S = np.abs(rng.standard_normal(4)) + 0.5
+        V = rng.standard_normal((30, 4))
+        ref = O.residual_exact(A, U, S, V, center=center)
+        got = fn(A, U, S, V, center=center, panel_rows=32)
+        if abs(got - ref) > 1e-10 * ref:
+            return False
+    return True
+
+
+def test_residual_gram_matches_dense_svd():
+    """The Gram route to ||A~ - U S V^T||_2 against the dense SVD of the difference (any U, S, V)."""
+    assert _gram_ok(O.residual_gram)
+    # and on the algorithm's own output, centred, where U is orthonormal
+    p = F.lowrank_noise(6, 400, 60, 5, 1.0 / np.arange(1, 6), 1e-3, True)
+    G = F.gaussian_G(6, 60, 7)
+    r = O.rpca(p["A"], 5, 7, 2, G, center=True)
+    ex = O.residual_exact(p["A"], r.U, r.S, r.V, center=True)
+    assert abs(O.residual_gram(p["A"], r.U, r.S, r.V, center=True, panel_rows=128) - ex) <= 1e-9 * ex
+
+    # planted mistakes: U^T U taken as the identity, a cross term with the wrong sign
+    def assume_orthonormal(A, U, S, V, center=False, panel_rows=O.PANEL_ROWS):
+        # the last term with U^T U replaced by the identity
+        A64 = np.asarray(A, np.float64)
+        if center:
+            A64 = A64 - A64.mean(axis=0)[None, :]
+        U, VS = np.asarray(U, np.float64), np.asarray(V, np.float64) * np.asarray(S, np.float64)
+        AU = A64.T @ U
+        M = A64.T @ A64 - AU @ VS.T - VS @ AU.T + VS @ VS.T
+        return float(math.sqrt(max(np.linalg.eigvalsh(0.5 * (M + M.T))[-1], 0.0)))
+
+    def wrong_sign(A, U, S, V, center=False, panel_rows=O.PANEL_ROWS):
+        return O.residual_gram(A, -np.asarray(U, np.float64), S, V, center, panel_rows)
+
+    for bad in (assume_orthonormal, wrong_sign):
+        assert not _gram_ok(bad)
+
+
+def test_estimator_failure_bound_values():
+    """Appendix eq. high_prob at hand-computed points: (2n / ((2j - 1) 16^j))^(k/2).
+
+    n = 1000, j = 6: 16^6 = 16777216, times 11 = 184549376, so the base is 2000/184549376;
+    k = 2 gives the base itself, k = 4 its square, k = 1 its square root; j = 1, n = 8, k = 2: 16/16 = 1.
+    """
+    from fractions import Fraction
+    base = Fraction(2000, 184549376)
+    cases = [((1000, 6, 2), float(base)), ((1000, 6, 4), float(base * base)),
+             ((1000, 6, 1), math.sqrt(float(base))), ((8, 1, 2), 1.0)]
+
+    def ok(fn):
+        return all(abs(fn(n, j, k) - want) <= 1e-13 * want for (n, j, k), want in cases)
+
+    assert ok(O.estimator_failure_bound)
+    planted = [
+        lambda n, j, k: (2.0 * n / ((2 * j + 1) * 16.0 ** j)) ** (k / 2.0),
+        lambda n, j, k: (2.0 * n / ((2 * j - 1) * 16.0 ** (j - 1))) ** (k / 2.0),
+        lambda n, j, k: (2.0 * n / ((2 * j - 1) * 16.0 ** j)) ** k,
+        lambda n, j, k: (n / ((2 * j - 1) * 16.0 ** j)) ** (k / 2.0),
+    ]
+    for bad in planted:
+        assert not ok(bad)
+
+
+def _fp8_scale_ok(fn):
+    from fractions import Fraction
+    # columns with amax 448 (scale 1), 896 (scale 2), 7/8 (= 448 / 512, scale 2^-9), 1 (1/448 rounded
+    # to float32), 3e-3 (rounded), and an all-zero column (scale 1 by the reading)
+    A = np.zeros((4, 6), dtype=np.float32)
+    A[:, 0] = [1.0, -448.0, 3.0, 0.5]
+    A[:, 1] = [896.0, -1.0, 0.0, 2.0]
+    A[:, 2] = [0.5, -0.875, 0.25, 0.0]
+    A[:, 3] = [-1.0, 0.5, 0.25, 0.75]
+    A[:, 4] = [0.003, -0.001, 0.002, -0.0025]
+    q, s = fn(A)
+    s = np.asarray(s)
+    if s.dtype != np.float32 or s.shape != (6,):
+        return False
+    if not (s[0] == 1.0 and s[1] == 2.0 and s[2] == 2.0 ** -9 and s[5] == 1.0):
+        return False
+    # columns 3 and 4: the float32 nearest to amax/448 (checked in exact rational arithmetic)
+    for j, amax in ((3, Fraction(1)), (4, Fraction(np.float32(0.003).item()))):
+        sj = Fraction(float(s[j]))
+        ulp = Fraction(float(np.spacing(s[j])))
+        if abs(sj - amax / 448) > ulp / 2:
+            return False
+    # the largest-magnitude entry of every nonzero column is coded as +-448 (0x7E / 0xFE)
+    q = np.asarray(q)
+    for j in range(5):
+        r = int(np.argmax(np.abs(A[:, j])))
+        if int(q[r, j]) & 0x7F != 0x7E:
+            return False
+    return True
+
+
+def test_fp8_scale_rule():
+    """Per-column e4m3 scale = float32(amax / 448), an all-zero column scaled by 1."""
+    from oracle import quantize_ref as Qr
+    assert _fp8_scale_ok(Qr.fp8_quantize)
+
+    def scale_240(A):
+        A = np.asarray(A, dtype=np.float32)
+        amax = np.abs(A).max(axis=0)
+        s = np.where(amax > 0, amax / np.float32(240.0), np.float32(1.0)).astype(np.float32)
+        return Qr.e4m3_bits(A / s), s
+
+    def zero_col_zero_scale(A):
+        q, s = Qr.fp8_quantize(A)
+        s = s.copy()
+        s[np.abs(np.asarray(A)).max(axis=0) == 0] = 0.0
+        return q, s
+
+    def scale_f64(A):
+        A = np.asarray(A, dtype=np.float32)
+        amax = np.abs(A).max(axis=0).astype(np.float64)
+        s = np.where(amax > 0, amax / 448.0, 1.0)
+        return Qr.e4m3_bits((A / s).astype(np.float32)), s
+
+    for bad in (scale_240, zero_col_zero_scale, scale_f64):
+        assert not _fp8_scale_ok(bad)
