@@ -119,7 +119,10 @@ enum {
 };
 
 typedef struct {
-  int64_t m, n;        /* A is m x n; the library requires m >= n (Section 3 assumes n <= m) */
+  int64_t m, n;        /* A is m x n.  Section 3 takes n <= m and applies the method to A^T
+                          otherwise: for m < n the plan factors B = A~^T (n x m, float32 A in
+                          device memory, no KEEP_STATE / SPLIT_BF16 / FP64_STEP1) and returns
+                          U, V of A (U = V_B, V = U_B); the sign rule then applies to u_j */
   int32_t k;           /* rank of the approximation, 1 <= k < n */
   int32_t l;           /* block width, l >= k */
   int32_t i;           /* power steps, i >= 0, with (i+1) l <= n - k (Section 3) */
@@ -155,37 +158,47 @@ typedef struct rpca_plan_s* rpca_plan_t;
  * restart their generator from the same seed).                              */
 typedef int (*rpca_device_panel_cb)(void* user, int64_t row0, int64_t nrows, float* dst, int64_t ld,
                                     void* hip_stream);
-/* Timing and counters of the last rpca_factor call (PROFILE adds the ms_* stages). */
+/* Timing and counters of the last rpca_factor call.  Without PROFILE only
+ * ms_total and the counters are filled; with PROFILE the ms_* stages are the
+ * times between HIP events recorded on the plan's stream at the stage
+ * boundaries, and the kernel times are event pairs around the panel kernels. */
 typedef struct {
   double ms_total;       /* entry to results ready, host clock */
-  double ms_colmean;     /* column-mean pass (centering) */
-  double ms_power;       /* Step 1: all power passes */
-  double ms_qr;          /* Step 2 */
-  double ms_tpass;       /* Step 3 */
-  double ms_small_svd;   /* Step 4 */
-  double ms_assemble;    /* Steps 5-6 */
+  double ms_colmean;     /* column-mean pass or pass-0 shift (centering), HIP events */
+  double ms_power;       /* Step 1: all power passes, HIP events */
+  double ms_qr;          /* Step 2, HIP events */
+  double ms_tpass;       /* Step 3, HIP events */
+  double ms_small_svd;   /* Step 4, HIP events */
+  double ms_assemble;    /* Steps 5-6, HIP events */
   double ms_fwd_kernel;  /* summed duration of the A X panel kernels (event timed) */
   double ms_adj_kernel;  /* summed duration of the A^T Z panel kernels (event timed) */
   int64_t fwd_launches;  /* number of A X kernel launches timed above */
   int64_t adj_launches;  /* number of A^T Z kernel launches timed above */
-  int64_t a_bytes_read;  /* bytes of A read by the panel kernels (algorithmic) */
+  int64_t a_bytes_read;  /* bytes of A the panel kernels read: a_reads full reads of
+                            the stored matrix, plus the rows of the pass-0 shift */
   int64_t h2d_bytes;     /* bytes of A moved host -> device (streamed sources) */
   int32_t qr_fallback;   /* Step 2: 0 Cholesky QR twice; 1 shifted Cholesky QR three times;
                             2 shifted rounds repeated until plain Cholesky QR applies;
                             3 Householder TSQR */
   int32_t eig_vectors;   /* eigenvectors computed in Step 4 (k, or L when state is kept) */
   int32_t hip_error;     /* raw hipError_t of the last RPCA_ERR_HIP */
-  int32_t passes;        /* full passes over A performed */
+  int32_t passes;        /* passes of the schedule: i power steps, one A X pass, one
+                            A^T Q pass (i + 2), plus a column-mean pass when one is made */
   double ms_tpass_kernel;  /* the Step 3 (T pass) launches among ms_adj_kernel (event timed) */
   int64_t tpass_launches;  /* number of those launches */
+  int32_t a_reads;       /* full reads of A the kernels made: a power step run as a
+                            forward launch and an adjoint launch reads A twice, a
+                            streamed panel or a fused power step once */
+  int32_t reserved;
 } rpca_stats;
 
 /* Creates a plan for the problem in *desc, bound to hip_stream (a hipStream_t,
  * NULL = the null stream) on desc->device, and allocates its workspace
  * (O((i+1) l (m+n)) entries, Section 4: only Steps 1 and 3 touch A).
- * Errors: INVALID_ARG when desc is NULL, out is NULL, m < n, or the Section 3
- * parameter rules fail (1 <= k < n, l >= k, (i+1) l <= n - k, i >= 0);
- * UNSUPPORTED for (i+1) l > 1024 or an unknown storage/source;
+ * Errors: INVALID_ARG when desc is NULL, out is NULL, or the Section 3
+ * parameter rules fail for s = min(m, n) (1 <= k < s, l >= k, (i+1) l <= s - k,
+ * i >= 0); UNSUPPORTED for (i+1) l > 1024, an unknown storage/source, or
+ * m < n with a storage, source or flag the transposed problem does not take;
  * OUT_OF_MEMORY / HIP when allocation fails.  On error *out is NULL.      */
 rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out);
 
@@ -198,16 +211,21 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
  *              (HOST_PINNED); NULL otherwise.
  *   cb, user   CALLBACK source only (DEVICE_CALLBACK plans use the generator
  *              registered by rpca_set_device_panel_cb; INVALID_ARG without one).
- *   G          n x l device floats (row-major, leading dimension l), the
- *              Gaussian test matrix of Step 1; NULL = generate from desc->seed
+ *   G          min(m, n) x l device floats (row-major, leading dimension l),
+ *              the Gaussian test matrix of Step 1 (m < n: of the problem of
+ *              A^T, whose columns are the m rows of A); NULL = generate from desc->seed
  *              with Philox4x32-10 (counter = element index r*l+c >> 1, stream 1,
  *              key = seed) and Box-Muller, rounded to float.
  *   U, ldu     device, m x k floats, ldu >= k.
  *   S          device, k floats.
  *   V, ldv     device, n x k floats, ldv >= k.
  * Column j of U and V is signed so that the largest-magnitude entry of v_j is
- * positive.  A is read (i+2) times (one fused pass A^T(A X) per power step,
- * one A X pass, one A^T Q pass), plus one column-mean pass when centering.
+ * positive.  The schedule has i + 2 passes (one A^T(A X) per power step, one
+ * A X pass, one A^T Q pass); in device memory a power step is a forward and an
+ * adjoint launch, so A is read 2i + 2 times (rpca_stats.a_reads), once per
+ * pass when it is streamed by panels.  Centring adds a column-mean pass for
+ * streamed sources, for i = 0 and for FP64 Step 1; otherwise it is folded
+ * into pass 0.
  * Low-precision storage: with centring the column means come from the
  * stored values (times col_scale for FP8) and enter only through the exact
  * rank-one correction.

@@ -49,6 +49,7 @@ class Stats(ctypes.Structure):
         ("h2d_bytes", ctypes.c_int64), ("qr_fallback", ctypes.c_int32), ("eig_vectors", ctypes.c_int32),
         ("hip_error", ctypes.c_int32), ("passes", ctypes.c_int32),
         ("ms_tpass_kernel", ctypes.c_double), ("tpass_launches", ctypes.c_int64),
+        ("a_reads", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

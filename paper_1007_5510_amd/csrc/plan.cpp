@@ -148,6 +148,27 @@ struct rpca_plan_s {
   int ns_y64 = 1, fwd_ks64 = 1;
   int64_t rps_y64 = 0, fwd_kchunk64 = 0;
 
+  // m < n (Section 3: the algorithm runs on the transpose).  The plan's m, n, k, l, i are those
+  // of B = A~^T (n x m); Steps 1 and 3 run the A-kernels with the roles of the products swapped:
+  // B X = A~^T X is an adjoint launch over A, B^T Y = A~ Y a forward launch.  Buffers over A's
+  // shape (am x an, am < an):
+  struct Trans {
+    bool on = false;
+    int64_t am = 0, an = 0;
+    int64_t ldxa = 0;            // an rounded up to 4
+    float* shift = nullptr;      // ldxa, zero tail
+    double* mu = nullptr;        // an
+    double* dres = nullptr;      // an
+    float* Z = nullptr;          // am x L: the blocks X_B^(j) (row-major), then T_B in float32
+    float* HBt = nullptr;        // L x ldxa: a block of H_B (or Q_B) transposed, zero past an
+    double* H64 = nullptr;       // an x L: H_B in float64 (Step 2 input)
+    float* P = nullptr;          // adjoint partials [ns_y][l][ldxa]
+    float* Pf = nullptr;         // forward partials [fwd_ks][am][ldpf]
+    double* sqp = nullptr;       // sums of squares of a transposed block
+    int ns_y = 1, fwd_ks = 1, ns_cs = 1, ns_cz = 1;
+    int64_t rps_y = 0, fwd_kchunk = 0, ldpf = 0, rps_cs = 0, rps_cz = 0;
+  } tr;
+
   bool have_state = false;
   bool Qfinal_is_Q1 = false;
   const void* A_last = nullptr;  // matrix of the last factorisation (for the backward passes)
@@ -184,6 +205,7 @@ struct rpca_plan_s {
   } bw;
   rpca_stats stats{};
   std::vector<EventPair> ev_fwd, ev_adj;
+  hipEvent_t stage_ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // PROFILE stage marks
   int nev_fwd = 0, nev_adj = 0;
   int tp_ev0 = 0, tp_ev1 = 0;  // adjoint events [tp_ev0, tp_ev1) belong to the T pass
 
@@ -206,6 +228,8 @@ struct rpca_plan_s {
       if (e.a) (void)hipEventDestroy(e.a);
       if (e.b) (void)hipEventDestroy(e.b);
     }
+    for (hipEvent_t e : stage_ev)
+      if (e) (void)hipEventDestroy(e);
   }
 
   template <typename T>
@@ -236,10 +260,11 @@ namespace {
 // Section 3 parameter rules (reading: enforce l >= k and (i+1) l <= n - k).
 rpca_status validate_desc(const rpca_desc* d) {
   if (d == nullptr) return RPCA_ERR_INVALID_ARG;
-  if (d->m <= 0 || d->n <= 0 || d->m < d->n) return RPCA_ERR_INVALID_ARG;
-  if (d->k < 1 || (int64_t)d->k >= d->n) return RPCA_ERR_INVALID_ARG;
+  if (d->m <= 0 || d->n <= 0) return RPCA_ERR_INVALID_ARG;
+  const int64_t small = d->m < d->n ? d->m : d->n;  // m < n: the rules apply to A^T (n x m)
+  if (d->k < 1 || (int64_t)d->k >= small) return RPCA_ERR_INVALID_ARG;
   if (d->l < d->k || d->i < 0) return RPCA_ERR_INVALID_ARG;
-  if ((int64_t)(d->i + 1) * d->l > d->n - d->k) return RPCA_ERR_INVALID_ARG;
+  if ((int64_t)(d->i + 1) * d->l > small - d->k) return RPCA_ERR_INVALID_ARG;
   if (d->storage < RPCA_A_F32 || d->storage > RPCA_A_BF16_HILO) return RPCA_ERR_UNSUPPORTED;
   if (d->source < RPCA_SRC_DEVICE || d->source > RPCA_SRC_DEVICE_CALLBACK) return RPCA_ERR_UNSUPPORTED;
   if ((int64_t)(d->i + 1) * d->l > 1024) return RPCA_ERR_UNSUPPORTED;
@@ -302,7 +327,12 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   plan->max_lds = prop.sharedMemPerBlock;
   set_max_lds(plan->max_lds);
 
-  const int64_t m = desc->m, n = desc->n;
+  // m < n: plan the problem of B = A~^T (n x m); float32 A in device memory, no reverse sweep
+  const bool trans = desc->m < desc->n;
+  if (trans && (desc->storage != RPCA_A_F32 || desc->source != RPCA_SRC_DEVICE ||
+                (desc->flags & (RPCA_FLAG_SPLIT_BF16 | RPCA_FLAG_FP64_STEP1 | RPCA_FLAG_KEEP_STATE)) != 0))
+    return fail(RPCA_ERR_UNSUPPORTED);
+  const int64_t m = trans ? desc->n : desc->m, n = trans ? desc->m : desc->n;
   const int k = desc->k, l = desc->l, i = desc->i, L = (i + 1) * l;
   plan->m = m;
   plan->n = n;
@@ -459,6 +489,31 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     ALLOC(Xp3, 3 * plan->xplane3);
     ALLOC(Zp3, 3 * plan->zplane3);
   }
+  if (trans) {
+    auto& t = plan->tr;
+    t.on = true;
+    t.am = n;  // A is am x an with am = the plan's n, an = the plan's m
+    t.an = m;
+    t.ldxa = round_up(t.an, 4);
+    adj_split(t.am, t.an, l, slots, &t.ns_y, &t.rps_y);
+    fwd_split(t.am, t.an, slots, &t.fwd_ks, &t.fwd_kchunk);
+    t.ldpf = round_up(L, 64);
+    choose_rows(t.am, 4096, 256, &t.ns_cs, &t.rps_cs);
+    choose_rows(t.am, 512, 1024, &t.ns_cz, &t.rps_cz);
+    ALLOC(tr.shift, t.ldxa);
+    ALLOC(tr.mu, t.an);
+    ALLOC(tr.dres, t.an);
+    ALLOC(tr.Z, t.am * L);
+    ALLOC(tr.HBt, (int64_t)L * t.ldxa);
+    ALLOC(tr.H64, t.an * L);
+    ALLOC(tr.P, (int64_t)t.ns_y * l * t.ldxa);
+    ALLOC(tr.Pf, t.fwd_ks > 1 ? (int64_t)t.fwd_ks * t.am * t.ldpf : 1);
+    ALLOC(tr.sqp, ((t.an + 255) / 256) * (int64_t)l + 16);
+    ALLOC(csp, (int64_t)std::max(t.ns_cs, t.ns_cz) * (t.ldxa + L));
+    if (hipMemset(plan->tr.shift, 0, sizeof(float) * (size_t)t.ldxa) != hipSuccess ||
+        hipMemset(plan->tr.HBt, 0, sizeof(float) * (size_t)(L * t.ldxa)) != hipSuccess)
+      return fail(RPCA_ERR_HIP);
+  }
   if (lowp) {
     ALLOC(Xh, (int64_t)plan->cpad_x * plan->ldxs);
     ALLOC(Xl, (int64_t)plan->cpad_x * plan->ldxs);
@@ -477,6 +532,9 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   for (auto* vec : {&plan->ev_fwd, &plan->ev_adj})
     for (auto& ev : *vec)
       if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return fail(RPCA_ERR_HIP);
+  if (desc->flags & RPCA_FLAG_PROFILE)
+    for (hipEvent_t& e : plan->stage_ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(RPCA_ERR_HIP);
   *out = plan;
   return RPCA_OK;
 }
@@ -503,6 +561,13 @@ namespace {
 EventPair* next_fwd_events(rpca_plan_s* plan) {
   if (!(plan->d.flags & RPCA_FLAG_PROFILE) || plan->nev_fwd >= (int)plan->ev_fwd.size()) return nullptr;
   return &plan->ev_fwd[plan->nev_fwd++];
+}
+
+// Stage mark q of the PROFILE timing (0 entry, 1 centring, 2 Step 1, 3 Step 2,
+// 4 Step 3, 5 Step 4, 6 Steps 5-6), recorded on the plan's stream.
+hipError_t mark_stage(rpca_plan_s* plan, int q) {
+  if (!(plan->d.flags & RPCA_FLAG_PROFILE) || plan->stage_ev[q] == nullptr) return hipSuccess;
+  return hipEventRecord(plan->stage_ev[q], plan->stream);
 }
 
 EventPair* next_adj_events(rpca_plan_s* plan) {
@@ -729,7 +794,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     if (plan->dcb == nullptr) return RPCA_ERR_INVALID_ARG;
     cb = nullptr;
   } else {
-    if (A == nullptr || lda < n) return RPCA_ERR_INVALID_ARG;
+    if (A == nullptr || lda < (plan->tr.on ? plan->tr.an : n)) return RPCA_ERR_INVALID_ARG;
     cb = nullptr;
   }
   const bool streamed = plan->streamed;
@@ -763,6 +828,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   const int64_t bpe = storage == RPCA_A_FP8_E4M3 ? 1 : (storage == RPCA_A_BF16 ? 2 : 4);
 
   RPCA_TRY(hipMemsetAsync(plan->flags, 0, 8 * sizeof(int), st));
+  RPCA_TRY(mark_stage(plan, 0));
 
   // centring: mu = column means (FP64), shift = fl32(mu), d = mu - shift.
   // The panel kernels always read a shift vector: without centring it is the
@@ -772,8 +838,17 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   // Low-precision storage has no in-register shift: d is the whole mean.
   // In-core storage folds the column sums into pass 0's adjoint (no separate
   // pass over A).
-  const bool fuse0 = center && !streamed && i >= 1 && !plan->f64s1;
-  if (center && streamed) {
+  const bool trans = plan->tr.on;
+  auto& tr = plan->tr;
+  const bool fuse0 = center && !streamed && i >= 1 && !plan->f64s1 && !trans;
+  if (center && trans) {
+    // column means of A (am x an): shift = fl32(mu), dres = mu - fl32(mu)
+    RPCA_TRY(launch_colsum(ST_F32, A, lda, tr.am, tr.an, nullptr, 0, tr.rps_cs, tr.ns_cs, plan->csp, st));
+    RPCA_TRY(launch_colsum_reduce(plan->csp, tr.ns_cs, tr.an, 1.0 / (double)tr.am, tr.mu, tr.shift, tr.dres, st));
+    sx.passes += 1;
+    sx.a_reads += 1;
+    sx.a_bytes_read += m * n * bpe;
+  } else if (center && streamed) {
     // a streamed pass of column sums (float64, accumulated over the panels)
     RPCA_TRY(launch_fill_f64(plan->acc, n, 0.0, st));
     rpca_status r = stream_panels(plan, Ahost, lda, cb, user, [&](const float* P, int64_t ldb, int64_t, int64_t rows) {
@@ -785,6 +860,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_colsum_reduce(plan->acc, 1, n, 1.0 / (double)m, plan->mu, plan->shift, plan->dres, st));
     dres = plan->dres;
     sx.passes += 1;
+    sx.a_reads += 1;
     sx.a_bytes_read += m * n * bpe;
   } else if (fuse0) {
     if (!lowp) {
@@ -808,8 +884,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       dres = plan->dres;
     }
     sx.passes += 1;
+    sx.a_reads += 1;
     sx.a_bytes_read += m * n * bpe;
   }
+
+  RPCA_TRY(mark_stage(plan, 1));
 
   // Step 1: X_0 = G
   float* X0 = plan->X;
@@ -855,6 +934,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       }
       RPCA_TRY(launch_fwd64(fa, st));
       sx.passes += 1;
+      sx.a_reads += 1;
       sx.a_bytes_read += m * n * bpe;
       if (j == i) break;
       Adj64Args aa;
@@ -876,6 +956,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
         aa.ev_end = ev->b;
       }
       RPCA_TRY(launch_adj64(aa, st));
+      sx.a_reads += 1;
+      sx.a_bytes_read += m * n * bpe;
       if (center) {  // 1^T H^(j)
         RPCA_TRY(launch_colsum_f64(fa.Z, L, m, l, plan->rps_cn, plan->ns_cn, plan->csp, st));
         RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, l, 1.0, plan->zsum, nullptr, nullptr, st));
@@ -888,6 +970,85 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     }
     RPCA_TRY(launch_check_finite_f64(plan->H64, m, L, L, plan->flags, st));
   }
+
+  // m < n: Step 1 on B = A~^T (the plan's m x n is an x am).  H_B^(j) = A~^T X_B^(j) is an adjoint
+  // launch over A with Z = X_B^(j) (am x l, row-major); X_B^(j+1) = alpha_{j+1} A~ H_B^(j) a forward
+  // launch with H_B^(j) transposed, alpha_{j+1} = 1/||H_B^(j)||_F.  Centring: A~^T Z =
+  // (A - 1 s^T)^T Z - d (1^T Z) and A~ Y = (A - 1 s^T) Y - 1 (d^T Y), s = fl32(mu), d = mu - s.
+  for (int j = 0; trans && j <= i; ++j) {
+    float* Zj = tr.Z + (int64_t)j * l;
+    if (j == 0) {
+      if (G != nullptr)
+        RPCA_TRY(hipMemcpy2DAsync(tr.Z, sizeof(float) * (size_t)L, G, sizeof(float) * (size_t)l,
+                                  sizeof(float) * (size_t)l, (size_t)tr.am, hipMemcpyDeviceToDevice, st));
+      else
+        RPCA_TRY(launch_transpose_G(X0, ldx, l, (int)tr.am, tr.Z, L, st));
+    }
+    if (center) {
+      RPCA_TRY(launch_colsum(ST_F32, Zj, L, tr.am, l, nullptr, 0, tr.rps_cz, tr.ns_cz, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, tr.ns_cz, l, 1.0, plan->zsum, nullptr, nullptr, st));
+    }
+    AdjArgs aa;
+    aa.A = A;
+    aa.lda = lda;
+    aa.m = tr.am;
+    aa.n = tr.an;
+    aa.shift = tr.shift;
+    aa.Z = Zj;
+    aa.ldz = L;
+    aa.ncols = l;
+    aa.rows_per_split = tr.rps_y;
+    aa.nsplit = tr.ns_y;
+    aa.P = tr.P;
+    aa.ldp = tr.ldxa;
+    aa.split_stride = (int64_t)l * tr.ldxa;
+    aa.vec = vec;
+    if (EventPair* ev = next_adj_events(plan)) {
+      aa.ev_begin = ev->a;
+      aa.ev_end = ev->b;
+    }
+    RPCA_TRY(launch_adj_f32(aa, st));
+    sx.passes += 1;
+    sx.a_reads += 1;
+    sx.a_bytes_read += m * n * bpe;
+    const double* dz = center ? tr.dres : nullptr;
+    const double* zs = center ? plan->zsum : nullptr;
+    RPCA_TRY(launch_reduce_t(tr.P, tr.ns_y, aa.split_stride, tr.ldxa, l, tr.an, nullptr, dz, zs, tr.H64 + (int64_t)j * l,
+                             L, st));
+    if (j == i) break;
+    int npart = 0;
+    RPCA_TRY(launch_reduce_y(tr.P, tr.ns_y, aa.split_stride, tr.ldxa, l, tr.an, nullptr, dz, zs, tr.HBt, tr.ldxa,
+                             tr.sqp, &npart, st));
+    RPCA_TRY(launch_finish_scale(tr.sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
+    if (center) RPCA_TRY(launch_dot_rows(tr.dres, tr.HBt, tr.ldxa, tr.an, l, plan->corr, st));
+    FwdArgs fa;
+    fa.A = A;
+    fa.lda = lda;
+    fa.m = tr.am;
+    fa.n = tr.an;
+    fa.shift = tr.shift;
+    fa.Xt = tr.HBt;
+    fa.ldx = tr.ldxa;
+    fa.ncols = l;
+    fa.corr = center ? plan->corr : nullptr;
+    fa.alpha = plan->alpha + j + 1;
+    fa.Z = tr.Z + (int64_t)(j + 1) * l;
+    fa.ldz = L;
+    fa.vec = vec;
+    fa.ksplit = tr.fwd_ks;
+    fa.kchunk = tr.fwd_kchunk;
+    fa.P = tr.Pf;
+    fa.ldp = tr.ldpf;
+    fa.split_stride = tr.am * tr.ldpf;
+    if (EventPair* ev = next_fwd_events(plan)) {
+      fa.ev_begin = ev->a;
+      fa.ev_end = ev->b;
+    }
+    RPCA_TRY(launch_fwd_f32(fa, st));
+    sx.a_reads += 1;
+    sx.a_bytes_read += m * n * bpe;
+  }
+  if (trans) RPCA_TRY(launch_check_finite_f64(tr.H64, m, L, L, plan->flags, st));
 
   // streamed: one host-link transfer per pass; each panel runs the forward
   // product and the adjoint of its own rows while it is resident in HBM
@@ -941,6 +1102,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     });
     if (r != RPCA_OK) return r;
     sx.passes += 1;
+    sx.a_reads += 1;
     sx.a_bytes_read += m * n * bpe;
     if (j == i) break;
     if (center) {
@@ -955,7 +1117,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
 
-  for (int j = 0; !streamed && !f64s1 && j <= i; ++j) {
+  for (int j = 0; !streamed && !f64s1 && !trans && j <= i; ++j) {
     float* Xj = plan->X + (int64_t)j * l * ldx;
     // with fused centring, pass 0 writes the uncorrected product (A - 1 s0^T) G and corrects it below
     const bool p0 = fuse0 && j == 0;
@@ -1000,6 +1162,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       RPCA_TRY(launch_fwd_f32(fa, st));
     }
     sx.passes += 1;
+    sx.a_reads += 1;
     sx.a_bytes_read += m * n * bpe;
     if (j == i) break;
     // fused half of the pass: X_{j+1} = A~^T H^(j)
@@ -1047,6 +1210,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     } else {
       RPCA_TRY(launch_adj_f32(aa, st));
     }
+    sx.a_reads += 1;
+    sx.a_bytes_read += m * n * bpe;
     if (p0 && lowp) {
       // mu = column sums / m of the stored matrix; the rank-one correction uses all of it
       RPCA_TRY(launch_pass0_mean_lp(plan->P, ns_y, aa.split_stride, plan->ldp, l, n, m, cs, plan->mu, st));
@@ -1069,8 +1234,8 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     }
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
-  if (!f64s1) RPCA_TRY(launch_check_finite_f32(plan->H, m, L, L, plan->flags, st));
-  const auto t_power = std::chrono::steady_clock::now();
+  if (!f64s1 && !trans) RPCA_TRY(launch_check_finite_f32(plan->H, m, L, L, plan->flags, st));
+  RPCA_TRY(mark_stage(plan, 2));
 
   // Step 2: Cholesky QR twice; shifted Cholesky QR three times as the first
   // fallback, repeated shifted rounds as the second, Householder TSQR as the
@@ -1082,12 +1247,14 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   // rounding of H leaves a component along 1 that the conditioning of H would
   // amplify inside span(Q), so it is removed in float64 before the QR (a no-op
   // in exact arithmetic).
-  const bool x_f64 = center || f64s1;
-  const void* Hqr = f64s1 ? static_cast<const void*>(plan->H64)
-                          : center ? static_cast<const void*>(plan->Q) : static_cast<const void*>(plan->H);
+  const bool x_f64 = center || f64s1 || trans;
+  const void* Hqr = f64s1    ? static_cast<const void*>(plan->H64)
+                    : trans  ? static_cast<const void*>(tr.H64)
+                    : center ? static_cast<const void*>(plan->Q)
+                             : static_cast<const void*>(plan->H);
   for (int attempt = 0; attempt < 4; ++attempt) {
     RPCA_TRY(hipMemsetAsync(plan->flags + 1, 0, 3 * sizeof(int), st));
-    if (center && !f64s1) {
+    if (center && !f64s1 && !trans) {
       RPCA_TRY(launch_colsum(ST_F32, plan->H, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
       RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, L, 1.0, plan->zsum, nullptr, nullptr, st));
       RPCA_TRY(launch_center_cols(plan->H, L, m, L, plan->zsum, 1.0 / (double)m, plan->Q, L, st));
@@ -1142,15 +1309,50 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     ++level;
   }
   sx.qr_fallback = level;
-  const auto t_qr = std::chrono::steady_clock::now();
+  RPCA_TRY(mark_stage(plan, 3));
 
   // Step 3: T = A~^T Q  (n x L, FP64 after the ordered split reduction)
   plan->tp_ev0 = plan->nev_adj;
-  if (center) {
+  if (center && !trans) {
     RPCA_TRY(launch_colsum(ST_F32, plan->Q32, L, m, L, nullptr, 0, plan->rps_cn, plan->ns_cn, plan->csp, st));
     RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, L, 1.0, plan->zsum, nullptr, nullptr, st));
   }
-  if (streamed) {
+  if (trans) {
+    // T_B = B^T Q_B = A~ Q_B (am x L): a forward launch with Q_B transposed, corrected by d^T Q_B;
+    // centred, T_B's columns lie in range(A~), orthogonal to 1, so the float32 rounding component
+    // along 1 is removed in float64 (a no-op in exact arithmetic)
+    RPCA_TRY(launch_transpose_G(plan->Q32, L, tr.an, L, tr.HBt, tr.ldxa, st));
+    if (center) RPCA_TRY(launch_dot_rows(tr.dres, tr.HBt, tr.ldxa, tr.an, L, plan->corr, st));
+    FwdArgs fa;
+    fa.A = A;
+    fa.lda = lda;
+    fa.m = tr.am;
+    fa.n = tr.an;
+    fa.shift = tr.shift;
+    fa.Xt = tr.HBt;
+    fa.ldx = tr.ldxa;
+    fa.ncols = L;
+    fa.corr = center ? plan->corr : nullptr;
+    fa.Z = tr.Z;
+    fa.ldz = L;
+    fa.vec = vec;
+    fa.ksplit = tr.fwd_ks;
+    fa.kchunk = tr.fwd_kchunk;
+    fa.P = tr.Pf;
+    fa.ldp = tr.ldpf;
+    fa.split_stride = tr.am * tr.ldpf;
+    RPCA_TRY(launch_fwd_f32(fa, st));
+    if (center) {
+      RPCA_TRY(launch_colsum(ST_F32, tr.Z, L, tr.am, L, nullptr, 0, tr.rps_cz, tr.ns_cz, plan->csp, st));
+      RPCA_TRY(launch_colsum_reduce(plan->csp, tr.ns_cz, L, 1.0, plan->zsum, nullptr, nullptr, st));
+      RPCA_TRY(launch_center_cols(tr.Z, L, tr.am, L, plan->zsum, 1.0 / (double)tr.am, plan->T, L, st));
+    } else {
+      RPCA_TRY(launch_widen(tr.Z, L, (int)tr.am, L, plan->T, L, st));
+    }
+    sx.passes += 1;
+    sx.a_reads += 1;
+    sx.a_bytes_read += m * n * bpe;
+  } else if (streamed) {
     RPCA_TRY(launch_fill_f64(plan->acc, (int64_t)L * plan->ldp, 0.0, st));
     rpca_status r = stream_panels(plan, Ahost, lda, cb, user,
                                   [&](const float* P, int64_t ldb, int64_t row0, int64_t rows) {
@@ -1176,6 +1378,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     if (r != RPCA_OK) return r;
     RPCA_TRY(launch_reduce_t64(plan->acc, plan->ldp, L, n, dres, center ? plan->zsum : nullptr, plan->T, L, st));
     sx.passes += 1;
+    sx.a_reads += 1;
     sx.a_bytes_read += m * n * bpe;
   } else {
     AdjArgs aa;
@@ -1217,11 +1420,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_reduce_t(plan->P, aa.nsplit, aa.split_stride, plan->ldp, L, n, cs, dres,
                              center ? plan->zsum : nullptr, plan->T, L, st));
     sx.passes += 1;
+    sx.a_reads += 1;
     sx.a_bytes_read += m * n * bpe;
   }
   plan->tp_ev1 = plan->nev_adj;
-  RPCA_TRY(hipStreamSynchronize(st));
-  const auto t_tpass = std::chrono::steady_clock::now();
+  RPCA_TRY(mark_stage(plan, 4));
 
   // Step 4: T^T T = W diag(S~^2) W^T (tridiagonal reduction, bisection, inverse iteration)
   RPCA_TRY(launch_gram(true, plan->T, L, n, L, plan->rps_gt, plan->ns_gt, plan->gp, st));
@@ -1230,28 +1433,29 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   RPCA_TRY(launch_syev_small(plan->Mg, L, kvec, plan->eigwork, plan->lam, plan->sigL, plan->Wsorted, L, plan->max_lds,
                              st));
   sx.eig_vectors = kvec;
-  RPCA_TRY(hipStreamSynchronize(st));
-  const auto t_svd = std::chrono::steady_clock::now();
+  RPCA_TRY(mark_stage(plan, 5));
 
   // Steps 5-6: V = T W_k / ||T W_k|| (signed), S = ||T W_k||, U = Q W_k (signed)
+  // (m < n: the plan's U is A's V and the plan's V is A's U)
+  float* Uo = trans ? V : U;
+  float* Vo = trans ? U : V;
+  const int64_t lduo = trans ? ldv : ldu, ldvo = trans ? ldu : ldv;
   RPCA_TRY(launch_gemm64(true, plan->T, L, plan->Wsorted, L, n, k, L, false, nullptr, plan->Vk, k, nullptr, 0, st));
   RPCA_TRY(launch_normalize_sign(plan->Vk, n, k, k, plan->sig, plan->sgn, st));
-  RPCA_TRY(launch_gemm64(true, Qfinal, L, plan->Wsorted, L, m, k, L, false, plan->sgn, nullptr, 0, U, ldu, st));
-  RPCA_TRY(launch_to_f32(plan->Vk, n, k, k, nullptr, V, ldv, st));
+  RPCA_TRY(launch_gemm64(true, Qfinal, L, plan->Wsorted, L, m, k, L, false, plan->sgn, nullptr, 0, Uo, lduo, st));
+  RPCA_TRY(launch_to_f32(plan->Vk, n, k, k, nullptr, Vo, ldvo, st));
   RPCA_TRY(launch_to_f32(plan->sig, 1, k, k, nullptr, S, k, st));
+  RPCA_TRY(mark_stage(plan, 6));
   RPCA_TRY(hipStreamSynchronize(st));
   const auto t_end = std::chrono::steady_clock::now();
-
-  auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
-    return std::chrono::duration<double, std::milli>(b - a).count();
-  };
-  sx.ms_total = ms(t0, t_end);
-  sx.ms_power = ms(t0, t_power);
-  sx.ms_qr = ms(t_power, t_qr);
-  sx.ms_tpass = ms(t_qr, t_tpass);
-  sx.ms_small_svd = ms(t_tpass, t_svd);
-  sx.ms_assemble = ms(t_svd, t_end);
+  sx.ms_total = std::chrono::duration<double, std::milli>(t_end - t0).count();
   if (plan->d.flags & RPCA_FLAG_PROFILE) {
+    double* stage_ms[6] = {&sx.ms_colmean, &sx.ms_power, &sx.ms_qr, &sx.ms_tpass, &sx.ms_small_svd, &sx.ms_assemble};
+    for (int q = 0; q < 6; ++q) {
+      float t = 0.f;
+      RPCA_TRY(hipEventElapsedTime(&t, plan->stage_ev[q], plan->stage_ev[q + 1]));
+      *stage_ms[q] = t;
+    }
     for (int q = 0; q < plan->nev_fwd; ++q) {
       float t = 0.f;
       RPCA_TRY(hipEventElapsedTime(&t, plan->ev_fwd[q].a, plan->ev_fwd[q].b));
@@ -1274,6 +1478,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
 
 extern "C" rpca_status rpca_get_state(rpca_plan_t plan, int32_t which, void* dst, int64_t ld) {
   if (plan == nullptr || dst == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (plan->tr.on) return RPCA_ERR_UNSUPPORTED;  // m < n: intermediates belong to A^T's problem
   if (!plan->have_state) return RPCA_ERR_NO_STATE;
   DevGuard g(plan->device);
   const int64_t m = plan->m, n = plan->n;
@@ -1533,7 +1738,7 @@ extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t ld
   (void)col_scale;
   if (plan == nullptr || A == nullptr || U == nullptr || S == nullptr || V == nullptr || estimate == nullptr)
     return RPCA_ERR_INVALID_ARG;
-  if (plan->storage != RPCA_A_F32 || plan->streamed) return RPCA_ERR_UNSUPPORTED;
+  if (plan->storage != RPCA_A_F32 || plan->streamed || plan->tr.on) return RPCA_ERR_UNSUPPORTED;
   const int64_t m = plan->m, n = plan->n, ldx = plan->ldx, ldp = plan->ldp;
   const int k = plan->k;
   if (j < 1 || q < 1 || q > 1024 || lda < n || ldu < k || ldv < k) return RPCA_ERR_INVALID_ARG;

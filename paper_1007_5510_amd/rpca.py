@@ -165,8 +165,9 @@ class Plan:
         if self.source == "device" and data.device != self.device:
             raise ValueError("A must live on the plan's device")
         if G is not None:
-            if G.dtype != torch.float32 or tuple(G.shape) != (n, self.l) or not G.is_contiguous():
-                raise ValueError(f"G must be a contiguous float32 {n} x {self.l} tensor")
+            gn = min(m, n)  # m < n: the test matrix of A^T's problem
+            if G.dtype != torch.float32 or tuple(G.shape) != (gn, self.l) or not G.is_contiguous():
+                raise ValueError(f"G must be a contiguous float32 {gn} x {self.l} tensor")
         if out is None:
             U = torch.empty((m, k), dtype=torch.float32, device=self.device)
             S = torch.empty((k,), dtype=torch.float32, device=self.device)
@@ -218,7 +219,7 @@ class Plan:
 
 
 def factor(A, k, l, i, *, center=False, G=None, seed=0, flags=0):
-    """One-shot rank-k randomized PCA of the device matrix A (m x n, m >= n)."""
+    """One-shot rank-k randomized PCA of the device matrix A (m x n; m < n runs on A^T)."""
     m, n = A.shape
     with Plan(m, n, k, l, i, center=center, seed=seed, flags=flags, device=A.device) as p:
         return p.factor(A, G=G)

@@ -55,7 +55,7 @@ def test_parameter_validation_without_device():
     assert plan(i=40) == 1                 # (i+1) l > n - k
     assert plan(k=400) == 1                # k >= n
     assert plan(k=0) == 1
-    assert plan(m=300) == 1                # m < n
+    assert plan(m=30) == 1                 # m < n: the rules on min(m, n) = 30 fail ((i+1) l > 30 - k)
     assert plan(storage=9) == 2            # unknown storage
     assert plan(l=1100, k=10, i=0, n=4000, m=8000) == 2  # (i+1) l > 1024 unsupported
     assert lib.rpca_plan(None, None, ctypes.byref(h)) == 1
