@@ -182,6 +182,43 @@ def quality_gate(A, U, S, V, k, seed):
     return est, float(sref[k])
 
 
+def exact_gate(A, U, S, V, k, chunk=8192):
+    """residual / sigma_{k+1} in float64 from n x n Gram matrices formed on the device with torch
+    float64 GEMMs (measurement only, outside the timed region):
+
+    sigma_{k+1}^2 = (k+1)-th eigenvalue of A~^T A~, A~ = A - 1 mu^T with mu the float64 column means;
+    ||A~ - U S V^T||_2^2 = largest eigenvalue of D^T D = A~^T A~ - C S V^T - V S C^T + V S (U^T U) S V^T
+    with C = A~^T U, an identity for any U, S, V (U need not be exactly orthonormal).
+    Both are exact up to float64 rounding, so by Eckart-Young the ratio is >= 1.
+    """
+    import torch
+    m, n = A.shape
+    mu = torch.zeros(n, dtype=torch.float64, device=A.device)
+    for r0 in range(0, m, chunk):
+        mu += A[r0:r0 + chunk].double().sum(0)
+    mu /= m
+    Gm = torch.zeros((n, n), dtype=torch.float64, device=A.device)
+    C = torch.zeros((n, k), dtype=torch.float64, device=A.device)
+    U64 = U.double()
+    for r0 in range(0, m, chunk):
+        P = A[r0:r0 + chunk].double() - mu
+        Gm += P.T @ P
+        C += P.T @ U64[r0:r0 + chunk]
+        del P
+    Gm = 0.5 * (Gm + Gm.T)
+    lam = torch.linalg.eigvalsh(Gm)
+    sigma_k1 = float(lam[n - 1 - k].clamp_min(0).sqrt())
+    VS = V.double() * S.double()[None, :]
+    Gm -= C @ VS.T
+    Gm -= VS @ C.T
+    Gm += VS @ (U64.T @ U64) @ VS.T
+    Gm = 0.5 * (Gm + Gm.T)
+    resid = float(torch.linalg.eigvalsh(Gm)[-1].clamp_min(0).sqrt())
+    del Gm, C, U64
+    torch.cuda.empty_cache()
+    return resid, sigma_k1
+
+
 def cpu_baseline(A, k, l, i, rows, seed):
     """The float64 oracle, untuned, on the first `rows` rows of the same workload."""
     import numpy as np
@@ -601,7 +638,7 @@ def main():
     if storage != "f32" or split:
         mfma_peak = 2500.0  # bfloat16 matrix cores
     t_mfma = bf16_products * step_flops / (mfma_peak * 1e12) * 1e3
-    reads = st_last["fwd_launches"] + st_last["adj_launches"] if st_last["fwd_launches"] else 2 * i + 2
+    reads = st_last["a_reads"]
     t_hbm = reads * m * n * bpe / (PEAK_HBM_GBS * 1e9) * 1e3
     step_roof = {"t_roof_ms": round(max(t_mfma, t_hbm), 3), "frac": round(max(t_mfma, t_hbm) / ms, 4),
                  "mfma_ms": round(t_mfma, 3), "mfma_frac": round(t_mfma / ms, 4),
@@ -716,10 +753,16 @@ def main():
     gate = None
     if not args.no_gate:
         t = time.perf_counter()
-        est, sref = quality_gate(A, U, S, V, k, args.seed)
-        gate = {"residual_est": est, "sigma_k1_ref": sref, "ratio": est / sref}
-        log(f"[bench] gate residual {est:.5f} sigma_k+1 {sref:.5f} ratio {est / sref:.4f} "
-            f"({time.perf_counter() - t:.1f}s)")
+        res, sk1 = exact_gate(A, U, S, V, k)
+        t_exact = time.perf_counter() - t
+        est, _sref = quality_gate(A, U, S, V, k, args.seed)
+        gate = {"residual": res, "sigma_k1": sk1, "ratio": res / sk1, "limit": 1.1,
+                "method": "float64 eigenvalues of n x n Gram matrices (exact up to float64 rounding)",
+                "residual_appendix_p6": est}
+        log(f"[bench] gate: exact residual {res:.6f} sigma_k+1 {sk1:.6f} ratio {res / sk1:.5f} ({t_exact:.1f}s); "
+            f"Appendix estimate p_6,k {est:.6f}")
+        if res / sk1 > 1.1:
+            log("[bench] residual / sigma_(k+1) above 1.1: the rate is not counted (value null)")
     peaks = None
     if not args.no_peak_probe:
         t = time.perf_counter()
@@ -732,7 +775,8 @@ def main():
         log(f"[bench] cpu baseline {cpu['value']} GB/s ({time.perf_counter() - t:.1f}s)")
     out = {
         "metric": "rank-k PCA time & effective A-read GB/s (vs peak) at residual/sigma_{k+1} <= 1.1",
-        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": round(value, 3) if (gate is None or gate["ratio"] <= 1.1) else None,
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": ("f64 Step 1 (f32 A exact in f64, FP64 matrix cores), f32 Step 3" if f64s1 else
                   "f32 as 3 x bf16 parts (6 bf16 products, f32 accumulate)" if split else "f32")
@@ -745,7 +789,7 @@ def main():
         "step_roofline": step_roof,
         "measured_peaks": peaks,
         "a_passes_actual": plan.stats()["passes"],
-        "a_reads_actual": round((nf + na) / max(args.steps, 1), 2),
+        "a_reads_actual": st_last["a_reads"],
         "roofline": roof,
         "gate": gate,
         "cpu_baseline": cpu,

@@ -107,7 +107,16 @@ hipError_t launch_xty(bool x64, const void* X, int64_t ldx, int na, bool y64, co
 }
 
 // ---------------------------------------------------------------- small-SVD adjoint pieces
-// WT = W^T; Wsc[r][a] = W[r][a] / s_a; for a < k: Ck[a][c] = sgn_a W[c][a] / s_a, Bp[a][c] = sgn_a W[c][a]
+// A trailing S~_a (a >= k) at or below sqrt(u) S~_1 is rounding noise of the eigenvalues of T^T T:
+// its direction of T has no defined singular vector.  In the adjoint such a direction only
+// enters through the F-matrix term and the projector term, which cancel as S~_a -> 0, so it is
+// treated as part of the complement (its column of W / S~ and its row of N are zero).
+RPCA_DEV bool svd_dropped(const double* __restrict__ sig, int a, int k) {
+  return a >= k && !(sig[a] > 1.4901161193847656e-08 * sig[0]);
+}
+
+// WT = W^T; Wsc[r][a] = W[r][a] / s_a (0 for a dropped direction); for a < k: Ck[a][c] = sgn_a W[c][a] / s_a,
+// Bp[a][c] = sgn_a W[c][a]
 __global__ void svdadj_prep_kernel(const double* __restrict__ W, const double* __restrict__ sig,
                                    const double* __restrict__ sgn, int L, int k, double* __restrict__ WT,
                                    double* __restrict__ Wsc, double* __restrict__ Ck, double* __restrict__ Bp) {
@@ -116,7 +125,7 @@ __global__ void svdadj_prep_kernel(const double* __restrict__ W, const double* _
   const int r = (int)(e / L), a = (int)(e % L);
   const double w = W[e];
   WT[(int64_t)a * L + r] = w;
-  Wsc[e] = w / sig[a];
+  Wsc[e] = svd_dropped(sig, a, k) ? 0.0 : w / sig[a];
   if (a < k) {
     Ck[(int64_t)a * L + r] = sgn[a] * w / sig[a];
     Bp[(int64_t)a * L + r] = sgn[a] * w;
@@ -124,26 +133,34 @@ __global__ void svdadj_prep_kernel(const double* __restrict__ W, const double* _
 }
 
 // N = M - (V~^T V_bar) S~^-1 with M the bracket of the SVD adjoint;
-// XV = W^T (T^T V_bar) (L x k, so (V~^T V_bar)[a][b] = XV[a][b] / s_a), YW = W^T W_bar (L x k)
+// XV = W^T (T^T V_bar) (L x k, so (V~^T V_bar)[a][b] = XV[a][b] / s_a), YW = W^T W_bar (L x k).
+// Entries with a, b >= k carry no cotangent (every factor is zero) and are skipped, so ties and
+// zeros among the trailing S~ never meet a 0/0; a dropped trailing direction gives a zero row.
 __global__ void svdadj_mid_kernel(const double* __restrict__ XV, const double* __restrict__ YW,
                                   const double* __restrict__ sig, const float* __restrict__ gS, int L, int k,
                                   double* __restrict__ N) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)L * L) return;
   const int a = (int)(e / L), b = (int)(e % L);
+  if ((a >= k && b >= k) || svd_dropped(sig, a, k)) {
+    N[e] = 0.0;
+    return;
+  }
   const double sa = sig[a], sb = sig[b];
-  const double xab = b < k ? XV[(int64_t)a * k + b] / sa : 0.0;
-  const double xba = a < k ? XV[(int64_t)b * k + a] / sb : 0.0;
+  const double XVab = b < k ? XV[(int64_t)a * k + b] : 0.0;  // s_a (V~^T V_bar)[a][b]
+  const double XVba = a < k ? XV[(int64_t)b * k + a] : 0.0;  // s_b (V~^T V_bar)[b][a]
   const double yab = b < k ? YW[(int64_t)a * k + b] : 0.0;
   const double yba = a < k ? YW[(int64_t)b * k + a] : 0.0;
   double m = 0.0;
   if (a != b) {
+    // F_ab ((V~^T V_bar)_ab - (V~^T V_bar)_ba) s_b + s_a F_ab ((W^T W_bar)_ab - (W^T W_bar)_ba),
+    // F_ab = 1 / (s_b^2 - s_a^2); no division by s_b (which may be a tiny trailing value)
     const double f = 1.0 / ((sb - sa) * (sb + sa));
-    m = f * (xab - xba) * sb + sa * f * (yab - yba);
+    m = f * (XVab * (sb / sa) - XVba) + sa * f * (yab - yba);
   } else if (gS != nullptr && a < k) {
     m = (double)gS[a];
   }
-  N[e] = m - xab / sb;
+  N[e] = b < k ? m - XVab / (sa * sb) : m;
 }
 
 hipError_t launch_svdadj_prep(const double* W, const double* sig, const double* sgn, int L, int k, double* WT,

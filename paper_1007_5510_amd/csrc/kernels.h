@@ -162,6 +162,9 @@ hipError_t launch_hh_factor(double* X, int64_t rows_total, int64_t bu, int nb, i
                             hipStream_t st);
 hipError_t launch_hh_apply(const double* X, int64_t rows_total, int64_t bu, int nb, int L, const double* tau,
                            const double* Cin, double* Yout, hipStream_t st);
+// per-workgroup LDS of the device for the two kernels above; whether blocks of maxrows rows fit
+void set_hh_lds_limit(size_t bytes);
+bool hh_fits(int L, int64_t maxrows);
 
 // ---------------------------------------------------------------- auxiliary
 // FP64 column sums of a row-major matrix in a given storage: part[s][c] over row splits.
@@ -281,5 +284,14 @@ hipError_t launch_gen_normal64(uint64_t seed, uint32_t stream, int64_t rows, int
                                hipStream_t st);
 hipError_t launch_neg_rowscale(double* C, const float* s, int k, int q, hipStream_t st);
 hipError_t launch_sqrt_max(const double* v, int q, double* out, hipStream_t st);
+
+// ---------------------------------------------------------------- quantiser entry points (plan.cpp)
+// split rule and scratch bytes; argument checks; the kernels on a caller-provided scratch
+size_t quantize_scratch(int64_t m, int64_t n, int* ns, int64_t* rps);
+int quantize_check(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, const void* out, int64_t ldo,
+                   const float* col_scale, const float* shift, int32_t shift_mode);
+hipError_t quantize_run(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out, int64_t ldo,
+                        float* col_scale, float* shift, int32_t shift_mode, void* scratch, int ns, int64_t rps,
+                        hipStream_t st);
 
 }  // namespace rpca

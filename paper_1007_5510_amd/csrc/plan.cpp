@@ -202,6 +202,9 @@ struct rpca_plan_s {
     double *M2 = nullptr, *Smat = nullptr, *Rf = nullptr, *Rt = nullptr, *RfInv = nullptr, *RinvT = nullptr;
     double *Ck = nullptr, *Bp = nullptr;             // k x L
     double* ppart = nullptr;                         // column-sum partials of P
+    int Rp = 0;                                      // R rounded up to 4 (zero padding)
+    float *P32 = nullptr, *Y32 = nullptr;            // m x Rp, n x Rp: float32 factors of dA
+    float* zshift = nullptr;                         // Rp zeros (no shift in the dA product)
   } bw;
   rpca_stats stats{};
   std::vector<EventPair> ev_fwd, ev_adj;
@@ -326,6 +329,7 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   if (hipGetDeviceProperties(&prop, plan->device) != hipSuccess) return fail(RPCA_ERR_HIP);
   plan->max_lds = prop.sharedMemPerBlock;
   set_max_lds(plan->max_lds);
+  set_hh_lds_limit(plan->max_lds);
 
   // m < n: plan the problem of B = A~^T (n x m); float32 A in device memory, no reverse sweep
   const bool trans = desc->m < desc->n;
@@ -654,21 +658,22 @@ rpca_status cholqr_repeated(rpca_plan_s* plan, bool x_f64, const void* H, double
 
 // Step 2 by Householder TSQR (qr_householder.hip): orthonormal to rounding for
 // any H.  Level 0 takes blocks of at least 2L rows (at most 2048 blocks); each
-// higher level stacks the triangles of the level below in pairs.  Supported
-// for L <= 256 (one workgroup per block keeps the block's reflector in LDS).
+// higher level stacks the triangles of the level below in pairs.  One
+// workgroup per block keeps the block's reflector and its partial sums in LDS:
+// (block rows + 16 (L + 1)) doubles, which the device's LDS (160 KB per
+// workgroup on gfx950) holds for every L <= 1024 the plan accepts.
 rpca_status householder_qr(rpca_plan_s* plan, bool x_f64, const void* H, double** Qout) {
   const int L = plan->L;
   const int64_t m = plan->m, LL = (int64_t)L * L;
   hipStream_t st = plan->stream;
   auto& t = plan->tsqr;
-  if (L > 256) return RPCA_ERR_QR_BREAKDOWN;
   if (!t.ready) {
     int64_t bu0 = (m + 2047) / 2048;
     if (bu0 < 2 * L) bu0 = 2 * L;
     int nb0 = (int)(m / bu0);
     if (nb0 < 1) nb0 = 1;
     const int64_t last0 = m - (int64_t)(nb0 - 1) * bu0;
-    if ((last0 > bu0 ? last0 : bu0) + 16 * (L + 1) > 8192) return RPCA_ERR_QR_BREAKDOWN;  // LDS of one block
+    if (!hh_fits(L, last0 > bu0 ? last0 : bu0) || !hh_fits(L, 2 * (int64_t)L)) return RPCA_ERR_QR_BREAKDOWN;
     t.rows.push_back(m);
     t.bu.push_back(bu0);
     t.nb.push_back(nb0);
@@ -1557,7 +1562,16 @@ rpca_status backward_alloc(rpca_plan_s* plan) {
   BALLOC(Ck, (int64_t)k * L);
   BALLOC(Bp, (int64_t)k * L);
   BALLOC(ppart, (int64_t)plan->ns_cs * b.R);
+  b.Rp = (b.R + 3) / 4 * 4;
+  BALLOC(P32, m * b.Rp);
+  BALLOC(Y32, plan->n * b.Rp);
+  BALLOC(zshift, b.Rp);
 #undef BALLOC
+  // the K padding of the float32 factors and the shift stay zero
+  if (hipMemset(b.P32, 0, sizeof(float) * (size_t)(m * b.Rp)) != hipSuccess ||
+      hipMemset(b.Y32, 0, sizeof(float) * (size_t)(plan->n * b.Rp)) != hipSuccess ||
+      hipMemset(b.zshift, 0, sizeof(float) * (size_t)b.Rp) != hipSuccess)
+    return RPCA_ERR_HIP;
   b.ready = true;
   return RPCA_OK;
 }
@@ -1566,7 +1580,9 @@ rpca_status backward_alloc(rpca_plan_s* plan) {
 
 // Reverse sweep of Steps 1-6 (reading: exact derivative of the computed
 // function with G fixed).  Small steps in float64, passes over A on the
-// float32 panel kernels, dA = P Y^T assembled in float64 with
+// float32 panel kernels, the rank-R factors of dA = P Y^T assembled in float64
+// and their product formed on the float32 matrix cores (the forward panel
+// kernel with K = R, one 64-column tile of dA per block column), with
 //   P = [Q | a_0 Z_0 .. a_i Z_i | H^(0) .. H^(i-1)],  Y = [T_bar | X_0 .. X_i | X_bar_1 .. X_bar_i]
 // where Z_i = H_bar_i, Z_j = H_bar_j + A~ X_bar_{j+1}, X_bar_j = a_j A~^T Z_j, and
 // a_j are the positive block scales of the forward (constants: Q does not depend on them).
@@ -1720,9 +1736,32 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   RPCA_TRY(launch_widen(plan->X, ldx, L, n, b.Yt + (int64_t)L * ldx, ldx, st));
   if (i > 0) RPCA_TRY(launch_widen(b.Xbar, ldx, i * l, n, b.Yt + (int64_t)2 * L * ldx, ldx, st));
   if (center) RPCA_TRY(launch_center_f64(b.Pm, ldp, m, R, plan->rps_cs, plan->ns_cs, b.ppart, st));
-  RPCA_TRY(launch_gemm64(true, b.Pm, ldp, b.Yt, ldx, m, (int)n, R, false, nullptr, nullptr, 0, dA, ldda, st));
+  // dA = P Y^T on the float32 matrix cores: P (m x R) and Y = (Y^T)^T (n x R) rounded to float32
+  RPCA_TRY(launch_to_f32(b.Pm, m, R, ldp, nullptr, b.P32, b.Rp, st));
+  RPCA_TRY(launch_transpose_out(b.Yt, ldx, R, (int)n, b.Y32, nullptr, b.Rp, st));
+  {
+    FwdArgs fa;
+    fa.A = b.P32;
+    fa.lda = b.Rp;
+    fa.m = m;
+    fa.n = b.Rp;
+    fa.shift = b.zshift;
+    fa.Xt = b.Y32;
+    fa.ldx = b.Rp;
+    fa.ncols = (int)n;
+    fa.Z = dA;
+    fa.ldz = ldda;
+    fa.vec = true;
+    RPCA_TRY(launch_fwd_f32(fa, st));
+  }
+  // a derivative that is not defined at this A (tied leading S~, or a Step 2 factor that is
+  // singular to working precision) shows as non-finite entries
+  RPCA_TRY(hipMemsetAsync(plan->flags + 4, 0, sizeof(int), st));
+  RPCA_TRY(launch_check_finite_f32(dA, m, n, ldda, plan->flags + 4, st));
+  int bad = 0;
+  RPCA_TRY(hipMemcpyAsync(&bad, plan->flags + 4, sizeof(int), hipMemcpyDeviceToHost, st));
   RPCA_TRY(hipStreamSynchronize(st));
-  return RPCA_OK;
+  return bad != 0 ? RPCA_ERR_NONFINITE : RPCA_OK;
 }
 
 // Appendix estimator p_{j,q}(D) of ||D||_2 for D = A~ - U S V^T: the q start
@@ -1851,31 +1890,23 @@ extern "C" rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t ld
   return RPCA_OK;
 }
 
-extern "C" rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out,
-                                     int64_t ldo, float* col_scale, float* shift, int32_t shift_mode,
-                                     void* hip_stream) {
-  if (storage != RPCA_A_BF16 && storage != RPCA_A_FP8_E4M3 && storage != RPCA_A_BF16_HILO)
-    return RPCA_ERR_INVALID_ARG;
-  if (m <= 0 || n <= 0 || A == nullptr || out == nullptr || lda < n || ldo < n || ldo % 16 != 0 ||
-      (reinterpret_cast<uintptr_t>(out) & 15) != 0)
-    return RPCA_ERR_INVALID_ARG;
-  if (storage == RPCA_A_FP8_E4M3 && col_scale == nullptr) return RPCA_ERR_INVALID_ARG;
-  if (shift_mode < 0 || shift_mode > 2 || (shift_mode != 0 && shift == nullptr)) return RPCA_ERR_INVALID_ARG;
-  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  int ns = 1;
-  int64_t rps = 0;
-  choose_rows(m, 4096, 256, &ns, &rps);
-  // scratch: column-sum partials (float64) and column maxima (float)
-  void* scratch = nullptr;
-  const size_t nbytes = (size_t)ns * (size_t)n * (sizeof(double) + sizeof(float)) + (size_t)n * sizeof(double);
-  hipError_t e = hipMalloc(&scratch, nbytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return e == hipErrorOutOfMemory ? RPCA_ERR_OUT_OF_MEMORY : RPCA_ERR_HIP;
-  }
+namespace rpca {
+// Row splits of the quantiser's column reductions and the bytes of its scratch:
+// column-sum partials [ns][n] float64 and the means [n] float64 (shift_mode 2),
+// column-maximum partials [ns][n] float (FP8).  Both quantise entry points use
+// this layout, so they reduce in the same split order and store the same bits.
+size_t quantize_scratch(int64_t m, int64_t n, int* ns, int64_t* rps) {
+  choose_rows(m, 4096, 256, ns, rps);
+  return (size_t)*ns * (size_t)n * (sizeof(double) + sizeof(float)) + (size_t)n * sizeof(double);
+}
+
+hipError_t quantize_run(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out, int64_t ldo,
+                        float* col_scale, float* shift, int32_t shift_mode, void* scratch, int ns, int64_t rps,
+                        hipStream_t st) {
   double* csp = reinterpret_cast<double*>(scratch);
   double* mu = csp + (size_t)ns * n;
   float* amax = reinterpret_cast<float*>(mu + n);
+  hipError_t e = hipSuccess;
   if (shift_mode == 2) {
     e = launch_colsum(ST_F32, A, lda, m, n, nullptr, 0, rps, ns, csp, st);
     if (e == hipSuccess) e = launch_colsum_reduce(csp, ns, n, 1.0 / (double)m, mu, shift, nullptr, st);
@@ -1883,6 +1914,38 @@ extern "C" rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, cons
   if (e == hipSuccess)
     e = launch_quantize(storage, m, n, A, lda, shift_mode != 0 ? shift : nullptr, out, ldo, col_scale, amax, ns, rps,
                         st);
+  return e;
+}
+
+int quantize_check(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, const void* out, int64_t ldo,
+                   const float* col_scale, const float* shift, int32_t shift_mode) {
+  if (storage != RPCA_A_BF16 && storage != RPCA_A_FP8_E4M3 && storage != RPCA_A_BF16_HILO)
+    return RPCA_ERR_INVALID_ARG;
+  if (m <= 0 || n <= 0 || A == nullptr || out == nullptr || lda < n || ldo < n || ldo % 16 != 0 ||
+      (reinterpret_cast<uintptr_t>(out) & 15) != 0)
+    return RPCA_ERR_INVALID_ARG;
+  if (storage == RPCA_A_FP8_E4M3 && col_scale == nullptr) return RPCA_ERR_INVALID_ARG;
+  if (shift_mode < 0 || shift_mode > 2 || (shift_mode != 0 && shift == nullptr)) return RPCA_ERR_INVALID_ARG;
+  return RPCA_OK;
+}
+}  // namespace rpca
+
+extern "C" rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda, void* out,
+                                     int64_t ldo, float* col_scale, float* shift, int32_t shift_mode,
+                                     void* hip_stream) {
+  const int vs = quantize_check(storage, m, n, A, lda, out, ldo, col_scale, shift, shift_mode);
+  if (vs != RPCA_OK) return static_cast<rpca_status>(vs);
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  int ns = 1;
+  int64_t rps = 0;
+  const size_t nbytes = quantize_scratch(m, n, &ns, &rps);
+  void* scratch = nullptr;
+  hipError_t e = hipMalloc(&scratch, nbytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? RPCA_ERR_OUT_OF_MEMORY : RPCA_ERR_HIP;
+  }
+  e = quantize_run(storage, m, n, A, lda, out, ldo, col_scale, shift, shift_mode, scratch, ns, rps, st);
   const hipError_t es = hipStreamSynchronize(st);
   if (e == hipSuccess) e = es;
   (void)hipFree(scratch);

@@ -174,13 +174,18 @@ __global__ __launch_bounds__(HH_THREADS) void hh_apply_kernel(const double* __re
 
 static size_t hh_lds(int L, int maxrows) { return sizeof(double) * (size_t)(maxrows + HH_WAVES * (L + 1)); }
 
+// LDS one workgroup may use on this device (160 KB on gfx950), set by the plan
+static size_t g_hh_lds_limit = 65536;
+void set_hh_lds_limit(size_t bytes) { g_hh_lds_limit = bytes; }
+bool hh_fits(int L, int64_t maxrows) { return maxrows <= (1 << 20) && hh_lds(L, (int)maxrows) <= g_hh_lds_limit; }
+
 hipError_t launch_hh_factor(double* X, int64_t rows_total, int64_t bu, int nb, int L, double* tau, double* Rout,
                             hipStream_t st) {
   if (nb <= 0 || L <= 0) return hipSuccess;
   if (rows_total - (int64_t)(nb - 1) * bu < L || (nb > 1 && bu < L)) return hipErrorInvalidValue;
   const int64_t maxrows = rows_total - (int64_t)(nb - 1) * bu > bu ? rows_total - (int64_t)(nb - 1) * bu : bu;
+  if (!hh_fits(L, maxrows)) return hipErrorInvalidValue;
   const size_t lds = hh_lds(L, (int)maxrows);
-  if (maxrows > (1 << 20) || lds > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hh_factor_kernel, dim3((unsigned)nb), dim3(HH_THREADS), lds, st, X, rows_total, bu, nb, L,
                      (int)maxrows, tau, Rout);
   return hipGetLastError();
@@ -191,8 +196,8 @@ hipError_t launch_hh_apply(const double* X, int64_t rows_total, int64_t bu, int 
   if (nb <= 0 || L <= 0) return hipSuccess;
   if (rows_total - (int64_t)(nb - 1) * bu < L || (nb > 1 && bu < L)) return hipErrorInvalidValue;
   const int64_t maxrows = rows_total - (int64_t)(nb - 1) * bu > bu ? rows_total - (int64_t)(nb - 1) * bu : bu;
+  if (!hh_fits(L, maxrows)) return hipErrorInvalidValue;
   const size_t lds = hh_lds(L, (int)maxrows);
-  if (maxrows > (1 << 20) || lds > 65536) return hipErrorInvalidValue;
   hipLaunchKernelGGL(hh_apply_kernel, dim3((unsigned)nb), dim3(HH_THREADS), lds, st, X, rows_total, bu, nb, L,
                      (int)maxrows, tau, Cin, Yout);
   return hipGetLastError();

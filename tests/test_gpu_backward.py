@@ -195,3 +195,32 @@ def test_backward_after_householder_step2():
     rel = np.linalg.norm(out[1][0] - out[0][0]) / np.linalg.norm(out[0][0])
     print(f"  householder vs cholesky QR gradient: {rel:.2e}")
     assert rel < 1e-6
+
+
+def test_backward_with_trailing_values_at_rounding_level():
+    """A spectrum that falls below float64 resolution inside the L columns (sigma_j = 0.5^j, n = 60,
+    L = 36): the trailing S~ of Step 4 are rounding noise (below sqrt(u) S~_1), some possibly zero
+    or tied.  The reverse sweep treats those directions as part of the complement and stays finite;
+    the gradient satisfies the homogeneity identity <dL/dA, A> = sum_j w_j sigma_j (the outputs U, V
+    are invariant and S scales linearly under A -> c A; exact for the method with G fixed)."""
+    _need_gpu()
+    m, n, k, l, i = 400, 60, 4, 12, 2
+    sigma = 0.5 ** np.arange(n, dtype=np.float64)
+    prob = F.svd_problem(6160, m, n, sigma)
+    A32 = prob["A"].astype(np.float32)
+    G = F.gaussian_G(6160, n, l)
+    gS, gU, gV = _cotangents(6161, m, n, k)
+    from paper_1007_5510_amd import rpca, _lib
+    Ad = torch.from_numpy(A32).cuda()
+    p = rpca.Plan(m, n, k, l, i, flags=_lib.FLAG_KEEP_STATE)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    U, S, V = p.factor(Ad, G=t(G))
+    sig_all = p.state("SIGMA").cpu().numpy()
+    print(f"  S~ trailing {sig_all[-4:]} (S~_1 {sig_all[0]:.3f}), Step 2 level {p.stats()['qr_fallback']}")
+    dA = p.backward(gS=t(gS)).cpu().double().numpy()
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(dA))
+    lhs = float(np.sum(dA * A32.astype(np.float64)))
+    rhs = float(np.dot(gS, S.cpu().double().numpy()))
+    print(f"  <dA, A> {lhs:.8e}  sum w_j s_j {rhs:.8e}  rel {abs(lhs - rhs) / abs(rhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-4 * abs(rhs)

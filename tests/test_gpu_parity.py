@@ -289,23 +289,24 @@ def test_block_rescale_keeps_large_matrices_finite():
     assert e.value.code == 6  # RPCA_ERR_NONFINITE
 
 
-def test_householder_step2_at_its_width_limit():
-    """L = 256 (the Householder path's limit): parity with the oracle; one column more is refused
-    with RPCA_ERR_QR_BREAKDOWN instead of running."""
+@pytest.mark.parametrize("m,n,k,l,i", [
+    (12000, 1500, 40, 64, 3),   # L = 256
+    (6000, 1200, 100, 120, 2),  # L = 360, the width of the streamed workload (k = 100, l = 120, i = 2)
+])
+def test_householder_step2_wide(m, n, k, l, i):
+    """Householder Step 2 forced at L = 256 and L = 360 (one workgroup per row block holds the
+    block's reflector and partial sums in LDS: up to L = 1024 on gfx950): parity with the oracle's
+    pivoted QR route and an orthonormal Q."""
     from paper_1007_5510_amd import _lib
-    m, n, k, l, i = 12000, 1500, 40, 64, 3
     sigma = 0.97 ** np.arange(n, dtype=np.float64)
-    p = F.svd_problem(7070, m, n, sigma)
-    G = F.gaussian_G(7070, n, l)
+    p = F.svd_problem(7070 + l, m, n, sigma)
+    G = F.gaussian_G(7070 + l, n, l)
     orc = O.rpca(p["A"], k, l, i, G)
     g = run_gpu(p["A"], k, l, i, G=G, flags=_lib.FLAG_FORCE_HOUSEHOLDER)
     assert g[3].stats()["qr_fallback"] == 3
     compare(g, orc, k, v_tol=2e-3)
     Q = g[3].state("Q").cpu().numpy()
     assert np.abs(Q.T @ Q - np.eye((i + 1) * l)).max() < 1e-13
-    with pytest.raises(_lib.RPCAError) as e:
-        run_gpu(p["A"], k, 65, i, G=F.gaussian_G(7070, n, 65), flags=_lib.FLAG_FORCE_HOUSEHOLDER)
-    assert e.value.code == 7  # RPCA_ERR_QR_BREAKDOWN: L = 260 > 256
 
 
 def test_wide_t_pass_matches_fallback_bitwise():
