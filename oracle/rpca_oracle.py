@@ -159,6 +159,13 @@ def rpca(A, k: int, l: int, i: int, G: np.ndarray, center: bool = False,
         F = apply_At(reader, H_blocks[-1])
         F_blocks.append(F)
         H_blocks.append(apply_A(reader, F))
+    r = steps_2_to_6(reader, H_blocks, k)
+    r.mu, r.F_blocks = mu, F_blocks
+    return r
+
+
+def steps_2_to_6(reader: PanelReader, H_blocks: list, k: int) -> RPCAResult:
+    """Steps 2-6 of Section 3 from the blocks H^(0..i) of Step 1, reading A through ``reader``."""
     H = np.hstack(H_blocks)
 
     # Step 2: pivoted QR of H; Q has (i+1) l orthonormal columns.
@@ -180,8 +187,8 @@ def rpca(A, k: int, l: int, i: int, G: np.ndarray, center: bool = False,
     Ut = Q @ W
 
     # Step 6: leftmost k columns and the leading k x k block.
-    return RPCAResult(U=Ut[:, :k].copy(), S=St[:k].copy(), V=Vt[:, :k].copy(), mu=mu,
-                      H_blocks=H_blocks, F_blocks=F_blocks, Q=Q, R=R, piv=piv, T=T,
+    return RPCAResult(U=Ut[:, :k].copy(), S=St[:k].copy(), V=Vt[:, :k].copy(),
+                      H_blocks=H_blocks, Q=Q, R=R, piv=piv, T=T,
                       Vtilde=Vt, Stilde=St, W=W, entries_read=reader.entries_read)
 
 

@@ -22,6 +22,16 @@ def _need_gpu():
         pytest.fail("librpca.so is not built (the GPU path has no fallback)")
 
 
+def _f32_block_tolerances(A, orc, k, center=False):
+    """Per-column vector bounds max(1e-4, 10 e_j): e_j is how far the oracle's own u_j (v_j) moves
+    when its Step 1 blocks are rounded to float32 and Steps 2-6 are redone in float64."""
+    reader = O.PanelReader(A, O.PANEL_ROWS, orc.mu if center else None)
+    r = O.steps_2_to_6(reader, [h.astype(np.float32).astype(np.float64) for h in orc.H_blocks], k)
+    eu = np.linalg.norm(r.U - orc.U, axis=0)
+    ev = np.linalg.norm(r.V - orc.V, axis=0)
+    return np.maximum(1e-4, 10.0 * eu), np.maximum(1e-4, 10.0 * ev)
+
+
 def _problem(seed, m, n, center):
     sigma = 0.9 ** np.arange(min(n, 300), dtype=np.float64)
     A = F.svd_problem(seed, m, n, sigma)["A"]
@@ -134,9 +144,13 @@ def test_device_callback_matches_host_pinned():
 def test_device_regenerated_rows_match_in_core():
     """Rows regenerated by the seeded device generator in every pass (the on-the-fly mode) and the
     same matrix generated once and factored in core, each against the float64 oracle run on that
-    matrix with the same G: singular values within 1e-5 relative (the float32 target), singular
-    vectors within 1e-4 in 2-norm (the float32 vector tolerance; sigma_j = exp(-j/10) leaves a gap
-    of 0.095 sigma_j between consecutive values, so all k = 20 vectors are compared).  The two
+    matrix with the same G: singular values within 1e-5 relative (the float32 target).  Singular
+    vectors: the float32 path keeps the Step 1 blocks H in float32, so its vectors cannot be closer
+    to the oracle's than the oracle's own vectors move when its H is rounded to float32; with
+    sigma_j = exp(-j/10) and i = 2 the last wanted columns of H^(2) carry (sigma_20/sigma_1)^5 ~ 1e-4
+    of the block's norm, and that rounding alone moves u_20 by ~4e-4.  Each column j is therefore
+    held to max(1e-4, 10 e_j), e_j the oracle's change under that rounding (the factor 10 covers
+    float32 accumulation in the products against a single rounding of the stored block).  The two
     device runs split the row sums differently (6000-row panels against the in-core row split);
     their singular values also agree with each other to 1e-6 relative."""
     _need_gpu()
@@ -164,15 +178,18 @@ def test_device_regenerated_rows_match_in_core():
     U1, S1, V1 = p1.factor(None, G=G, panel_fn=gen)
     torch.cuda.synchronize()
     assert len(calls) == (i + 2) * ((m + 5999) // 6000)  # every pass regenerates every panel
-    orc = O.rpca(A.cpu().numpy(), k, l, i, Gh)
+    Ah = A.cpu().numpy()
+    orc = O.rpca(Ah, k, l, i, Gh)
+    tol_u, tol_v = _f32_block_tolerances(Ah, orc, k)
     for name, (U_, S_, V_) in (("in core", (U0, S0, V0)), ("regenerated", (U1, S1, V1))):
         S_ = S_.cpu().double().numpy()
         U_, V_ = U_.cpu().double().numpy(), V_.cpu().double().numpy()
         es = (np.abs(S_ - orc.S) / orc.S).max()
-        eu = np.linalg.norm(U_ - orc.U, axis=0).max()
-        ev = np.linalg.norm(V_ - orc.V, axis=0).max()
-        print(f"  {name}: sigma rel err {es:.2e}, U err {eu:.2e}, V err {ev:.2e}")
-        assert es <= 1e-5 and eu <= 1e-4 and ev <= 1e-4
+        eu = np.linalg.norm(U_ - orc.U, axis=0)
+        ev = np.linalg.norm(V_ - orc.V, axis=0)
+        print(f"  {name}: sigma rel err {es:.2e}, U err {eu.max():.2e} (col {eu.argmax()}, bound "
+              f"{tol_u[eu.argmax()]:.2e}), V err {ev.max():.2e} (bound {tol_v[ev.argmax()]:.2e})")
+        assert es <= 1e-5 and np.all(eu <= tol_u) and np.all(ev <= tol_v)
     S0, S1 = S0.cpu().double().numpy(), S1.cpu().double().numpy()
     assert np.abs(S0 - S1).max() / S0[0] < 1e-6
 
