@@ -46,7 +46,8 @@ typedef enum {
   RPCA_ERR_CALLBACK = 5,      /* the panel callback returned non-zero */
   RPCA_ERR_NONFINITE = 6,     /* NaN or Inf met in the data or the iterates */
   RPCA_ERR_QR_BREAKDOWN = 7,  /* H (or T) numerically rank deficient beyond the fallback */
-  RPCA_ERR_NO_STATE = 8       /* rpca_backward / rpca_get_state without a kept forward */
+  RPCA_ERR_NO_STATE = 8,      /* rpca_backward / rpca_get_state without a kept forward */
+  RPCA_ERR_SCRATCH_LIMIT = 9  /* rpca_quantize_noalloc: the scratch would exceed its fixed size */
 } rpca_status;
 
 /* How A is stored.  Every format is row-major m x n with leading dimension lda.
@@ -289,6 +290,26 @@ rpca_status rpca_residual(rpca_plan_t plan, const void* A, int64_t lda, const fl
 rpca_status rpca_quantize(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda,
                           void* out, int64_t ldo, float* col_scale, float* shift, int32_t shift_mode,
                           void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * conversion as rpca_quantize, with the same arguments, rules and output
+ * bits, but no device allocation and no host-side wait.  Its scratch (per-row-
+ * split column sums and maxima: n * (12 * splits + 8) bytes, splits =
+ * ceil(m / 4096) up to 256) is taken from a fixed device array of
+ * RPCA_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; a request
+ * that needs more returns RPCA_ERR_SCRATCH_LIMIT (e.g. n above ~10900 once
+ * m >= 2^20, above ~1.67 million for m <= 4096).  The kernels are enqueued on
+ * hip_stream and the call returns without waiting.  Every call on one GPU
+ * uses that GPU's one array and nothing in it needs clearing between calls:
+ * calls on the same stream are ordered, but calls that overlap in time on one
+ * GPU (other streams or threads) race on the scratch.
+ * Errors: as rpca_quantize (INVALID_ARG, HIP for a failed launch or symbol
+ * lookup), plus SCRATCH_LIMIT; never OUT_OF_MEMORY.                         */
+#define RPCA_NOALLOC_SCRATCH_BYTES (32u << 20)
+rpca_status rpca_quantize_noalloc(int32_t storage, int64_t m, int64_t n, const float* A, int64_t lda,
+                                  void* out, int64_t ldo, float* col_scale, float* shift,
+                                  int32_t shift_mode, void* hip_stream);
 
 /* Intermediate results kept by KEEP_STATE (device copies into dst):
  *   RPCA_STATE_H      m x L floats, the blocks H^(j) each multiplied by a

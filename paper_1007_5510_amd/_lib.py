@@ -16,7 +16,7 @@ RPCA_OK = 0
 STATUS_NAMES = {
     0: "RPCA_OK", 1: "RPCA_ERR_INVALID_ARG", 2: "RPCA_ERR_UNSUPPORTED", 3: "RPCA_ERR_OUT_OF_MEMORY",
     4: "RPCA_ERR_HIP", 5: "RPCA_ERR_CALLBACK", 6: "RPCA_ERR_NONFINITE", 7: "RPCA_ERR_QR_BREAKDOWN",
-    8: "RPCA_ERR_NO_STATE",
+    8: "RPCA_ERR_NO_STATE", 9: "RPCA_ERR_SCRATCH_LIMIT",
 }
 STORAGE = {"f32": 0, "bf16": 1, "fp8_e4m3": 2, "bf16_hilo": 3}
 SOURCE = {"device": 0, "host_pinned": 1, "callback": 2, "device_callback": 3}
@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.rpca_residual.restype = i32
     lib.rpca_quantize.argtypes = [i32, i64, i64, vp, i64, vp, i64, vp, vp, i32, vp]
     lib.rpca_quantize.restype = i32
+    lib.rpca_quantize_noalloc.argtypes = [i32, i64, i64, vp, i64, vp, i64, vp, vp, i32, vp]
+    lib.rpca_quantize_noalloc.restype = i32
     lib.rpca_get_state.argtypes = [vp, i32, vp, i64]
     lib.rpca_get_state.restype = i32
     lib.rpca_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]

@@ -297,6 +297,7 @@ const char* rpca_status_str(rpca_status s) {
     case RPCA_ERR_NONFINITE: return "non-finite value in data or iterates";
     case RPCA_ERR_QR_BREAKDOWN: return "QR breakdown (numerically rank-deficient block)";
     case RPCA_ERR_NO_STATE: return "no kept forward state";
+    case RPCA_ERR_SCRATCH_LIMIT: return "request needs more scratch than the fixed no-allocation array holds";
   }
   return "unknown status";
 }

@@ -60,12 +60,29 @@ def test_parameter_validation_without_device():
     assert plan(l=1100, k=10, i=0, n=4000, m=8000) == 2  # (i+1) l > 1024 unsupported
     assert lib.rpca_plan(None, None, ctypes.byref(h)) == 1
     assert h.value is None
-    for code in range(9):
+    for code in range(10):
         assert lib.rpca_status_str(code)
     assert lib.rpca_status_str(99) == b"unknown status"
     lib.rpca_destroy(None)
     st = L.Stats()
     assert lib.rpca_get_stats(None, ctypes.byref(st)) == 1
+
+
+@needs_lib
+def test_noalloc_quantize_rejects_before_touching_a_device():
+    """Argument errors and requests beyond the fixed scratch array are refused on the host."""
+    from paper_1007_5510_amd import _lib as L
+    lib = L.load()
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below is refused first
+    q = lib.rpca_quantize_noalloc
+    assert q(0, 100, 100, fake, 100, fake, 112, None, None, 0, None) == 1        # F32 is not a stored format
+    assert q(1, 100, 100, fake, 100, fake, 100, None, None, 0, None) == 1        # ldo % 16 != 0
+    assert q(2, 100, 100, fake, 100, fake, 112, None, None, 0, None) == 1        # FP8 without col_scale
+    assert q(1, 100, 100, fake, 100, fake, 112, None, None, 2, None) == 1        # mean shift without a buffer
+    # m >= 2^20 rows split 256 ways: n * (12 * 256 + 8) bytes exceed 32 MiB from n = 10895 on
+    assert q(1, 1 << 20, 10895, fake, 10895, fake, 10896, None, None, 0, None) == 9
+    assert q(1, 4096, 1 << 21, fake, 1 << 21, fake, 1 << 21, None, None, 0, None) == 9
+    assert lib.rpca_status_str(9) == b"request needs more scratch than the fixed no-allocation array holds"
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
