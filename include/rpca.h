@@ -112,7 +112,7 @@ enum {
   RPCA_FLAG_FP64_STEP1 = 1u << 5,
   /* Step 2 by Householder QR (a TSQR reduction tree over row blocks, Q formed
    * from the reflectors) instead of Cholesky QR; it is otherwise the last
-   * fallback.  Needs L = (i+1) l <= 256 (QR_BREAKDOWN beyond).  The first
+   * fallback, for every L = (i+1) l <= 1024 the plan accepts.  The first
    * Householder Step 2 of a plan allocates the tree's workspace (about
    * 4 L^2 doubles per level-0 block, at most 2048 blocks), kept until
    * rpca_destroy; OUT_OF_MEMORY if that fails.                             */
