@@ -219,6 +219,51 @@ def exact_gate(A, U, S, V, k, chunk=8192):
     return resid, sigma_k1
 
 
+def host_link_probe(A, k, l, i, panels, dev, pr=16384, reps=2):
+    """The out-of-core schedule (Section 4) on the first panels*16384 rows of the in-core matrix,
+    copied once into pinned host memory: the plan moves every pass over the host link in 16384-row
+    panels, double-buffered against the panel kernels.  Reported: host-link bytes per second of
+    factorisation time against the measured host-to-device copy rate of the same panels."""
+    import torch
+    from paper_1007_5510_amd import rpca, _lib
+    m, n = A.shape
+    ms_rows = min(m, panels * pr)
+    Ah = torch.empty((ms_rows, n), dtype=torch.float32, pin_memory=True)
+    Ah.copy_(A[:ms_rows])
+    torch.cuda.synchronize()
+    pbuf = torch.empty((pr, n), dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    npan = ms_rows // pr
+    pbuf.copy_(Ah[:pr], non_blocking=True)
+    e0.record()
+    for b in range(npan):
+        pbuf.copy_(Ah[b * pr:(b + 1) * pr], non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    peak = npan * pr * n * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del pbuf
+    plan = rpca.Plan(ms_rows, n, k, l, i, center=True, source="host_pinned", panel_rows=pr, device=0)
+    U = torch.empty((ms_rows, k), dtype=torch.float32, device=dev)
+    S = torch.empty((k,), dtype=torch.float32, device=dev)
+    V = torch.empty((n, k), dtype=torch.float32, device=dev)
+    plan.factor(Ah, out=(U, S, V))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.factor(Ah, out=(U, S, V))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    st = plan.stats()
+    gbs = st["h2d_bytes"] / (ms * 1e-3) / 1e9
+    plan.close()
+    del Ah
+    return {"value": round(gbs, 2), "unit": "GB/s", "copy_peak": round(peak, 2), "frac": round(gbs / peak, 4),
+            "ms_per_factorisation": round(ms, 2), "rows": ms_rows, "panels": npan, "panel_rows": pr,
+            "passes": st["passes"], "h2d_bytes": st["h2d_bytes"],
+            "note": "first rows of the in-core matrix in pinned host memory, centred, same k, l, i; "
+                    "peak = host-to-device copy of the same panels without compute"}
+
+
 def cpu_baseline(A, k, l, i, rows, seed):
     """The float64 oracle, untuned, on the first `rows` rows of the same workload."""
     import numpy as np
@@ -532,6 +577,10 @@ def main():
     ap.add_argument("--no-peak-probe", action="store_true",
                     help="skip the measured GEMM / copy rates reported beside the roofline")
     ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--no-host-link", action="store_true",
+                    help="skip the streamed (pinned host memory) run on the first rows of the in-core matrix")
+    ap.add_argument("--link-panels", type=int, default=8,
+                    help="16384-row panels of the streamed run reported as host_link")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "fp8_e4m3", "bf16_hilo"],
                     help="stored format of A (low-precision copies are made from the float32 matrix with "
                          "its column means subtracted before conversion)")
@@ -547,6 +596,9 @@ def main():
                     help="float32 products on float32 matrix cores, or with each operand split into three bfloat16 "
                          "parts on the bfloat16 matrix cores (float32 storage only), or Step 1 in float64 on the "
                          "FP64 matrix cores (float32 storage only)")
+    ap.add_argument("--fused", action="store_true",
+                    help="single-read power steps (one fused kernel per step instead of a forward and an "
+                         "adjoint launch; float32 storage)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -587,7 +639,7 @@ def main():
         raise SystemExit(f"--compute {args.compute} applies to float32 storage only")
     plan = rpca.Plan(m, n, k, l, i, storage=storage, center=True, seed=args.seed,
                      flags=_lib.FLAG_PROFILE | (_lib.FLAG_SPLIT_BF16 if split else 0)
-                     | (_lib.FLAG_FP64_STEP1 if f64s1 else 0),
+                     | (_lib.FLAG_FP64_STEP1 if f64s1 else 0) | (_lib.FLAG_FUSED if args.fused else 0),
                      device=0)
     U = torch.empty((m, k), dtype=torch.float32, device=dev)
     S = torch.empty((k,), dtype=torch.float32, device=dev)
@@ -596,8 +648,8 @@ def main():
         plan.factor(Ain, out=(U, S, V))
         log(f"[bench] warmup {w} {plan.stats()['ms_total']:.2f} ms")
     torch.cuda.synchronize()
-    fwd_ms = adj_ms = tp_ms = 0.0
-    nf = na = ntp = 0
+    fwd_ms = adj_ms = tp_ms = fu_ms = 0.0
+    nf = na = ntp = nfu = 0
     stage = {"ms_power": 0.0, "ms_qr": 0.0, "ms_tpass": 0.0, "ms_small_svd": 0.0, "ms_assemble": 0.0}
     step_ms = []
     t0 = time.perf_counter()
@@ -611,6 +663,8 @@ def main():
         na += st["adj_launches"]
         tp_ms += st["ms_tpass_kernel"]
         ntp += st["tpass_launches"]
+        fu_ms += st["ms_fused_kernel"]
+        nfu += st["fused_launches"]
         for key in stage:
             stage[key] += st[key]
     torch.cuda.synchronize()
@@ -706,6 +760,9 @@ def main():
         # layout conditions hold, as they do for this workload), each timed by the plan's events
         tp_kernel = "adj_wide_kernel" if (L > 64 and L % 4 == 0 and n % 2 == 0) else "adj_f32_kernel"
         per = {"fwd32_kernel": [nf, fwd_ms, 2.0 * m * n * l]}
+        if nfu > 0:
+            # single-read power steps: the forward and the adjoint product of one step per launch
+            per["fused_power_f32_kernel"] = [nfu, fu_ms, 4.0 * m * n * l]
         if tp_kernel == "adj_wide_kernel":
             per["adj_f32_kernel"] = [na - ntp, adj_ms - tp_ms, 2.0 * m * n * l]
             per["adj_wide_kernel"] = [ntp, tp_ms, 2.0 * m * n * L]
@@ -723,7 +780,10 @@ def main():
             log(f"[bench] {name}: {cnt / args.steps:.0f} launches, avg {avg:.3f} ms, {tf:.1f} TF/s")
         dom_name = max(kern, key=lambda nm: kern[nm]["ms_per_step"])
         dom = kern[dom_name]
-        tr = measured_traffic(dom_name)
+        if dom_name == "fused_power_f32_kernel":
+            tr = measured_traffic(dom_name, "panel_fused.hip", "incore_fused_hbm_counters.md")
+        else:
+            tr = measured_traffic(dom_name)
         roof = {"bound": "mfma", "achieved": dom["achieved_tflops"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": dom["frac"],
                 "traffic": round(tr["fetch"] + tr["write"]) if tr else None,
@@ -768,6 +828,12 @@ def main():
         t = time.perf_counter()
         peaks = measured_peaks(dev)
         log(f"[bench] measured peaks {peaks} ({time.perf_counter() - t:.1f}s)")
+    link = None
+    if not args.no_host_link and storage == "f32" and not split and not f64s1:
+        t = time.perf_counter()
+        link = host_link_probe(A, k, l, i, args.link_panels, dev)
+        log(f"[bench] streamed from pinned host memory: {link['value']} GB/s over the host link, "
+            f"{link['frac']} of the measured copy rate ({time.perf_counter() - t:.1f}s)")
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
@@ -782,7 +848,8 @@ def main():
                   "f32 as 3 x bf16 parts (6 bf16 products, f32 accumulate)" if split else "f32")
         if storage == "f32" else "bf16-mfma/f32-acc", "data": "synthetic",
         "config": {"workload": f"in-core {storage} {m}x{n} low-rank+noise, centred, k={k} l={l} i={i}",
-                   "m": m, "n": n, "k": k, "l": l, "i": i, "storage": storage, "center": True},
+                   "m": m, "n": n, "k": k, "l": l, "i": i, "storage": storage, "center": True,
+                   "power_step": "one fused kernel (one read of A)" if args.fused else "forward + adjoint launches"},
         "frac_of_hbm_peak": round(value / PEAK_HBM_GBS, 4),
         "ms_per_step_median": round(float(sorted(step_ms)[len(step_ms) // 2]), 4),
         "paper_schedule_gbs": round(paper_gbs, 3),
@@ -792,6 +859,7 @@ def main():
         "a_reads_actual": st_last["a_reads"],
         "roofline": roof,
         "gate": gate,
+        "host_link": link,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

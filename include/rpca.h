@@ -116,7 +116,19 @@ enum {
    * Householder Step 2 of a plan allocates the tree's workspace (about
    * 4 L^2 doubles per level-0 block, at most 2048 blocks), kept until
    * rpca_destroy; OUT_OF_MEMORY if that fails.                             */
-  RPCA_FLAG_FORCE_HOUSEHOLDER = 1u << 6
+  RPCA_FLAG_FORCE_HOUSEHOLDER = 1u << 6,
+  /* Run each power step of Step 1 (eqs. second_prod .. last_prod) as one
+   * fused kernel that reads A once: H^(j) and the adjoint partial sums of
+   * A^T H^(j) come from the same read of each row block (Section 4.1), the
+   * columns split over the compute units of one or two XCDs, the partial
+   * sums of H^(j) combined between them through device-coherent atomics.
+   * Without the flag a power step is a forward launch and an adjoint launch
+   * (two reads of A).  Taken for float32 A in device memory (no SPLIT_BF16 /
+   * FP64_STEP1, m >= n, i >= 1, m >= 32768, l + 1 <= 64, n <= 20480) on a
+   * device of 256 compute units in 8 XCDs with cooperative launch; the plan
+   * checks the layout once with a launch without rows and otherwise keeps
+   * the two launches (rpca_stats.fused_launches stays 0).                   */
+  RPCA_FLAG_FUSED = 1u << 7
 };
 
 typedef struct {
@@ -191,6 +203,8 @@ typedef struct {
                             forward launch and an adjoint launch reads A twice, a
                             streamed panel or a fused power step once */
   int32_t reserved;
+  double ms_fused_kernel;  /* summed duration of the single-read power-step kernels (event timed) */
+  int64_t fused_launches;  /* number of those launches */
 } rpca_stats;
 
 /* Creates a plan for the problem in *desc, bound to hip_stream (a hipStream_t,

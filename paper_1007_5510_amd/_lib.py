@@ -27,6 +27,7 @@ FLAG_NO_RESCALE = 1 << 3
 FLAG_SPLIT_BF16 = 1 << 4
 FLAG_FP64_STEP1 = 1 << 5
 FLAG_FORCE_HOUSEHOLDER = 1 << 6
+FLAG_FUSED = 1 << 7
 STATE = {"H": 0, "HSCALE": 1, "Q": 2, "T": 3, "SIGMA": 4, "W": 5, "MU": 6, "H64": 7}
 
 
@@ -50,6 +51,7 @@ class Stats(ctypes.Structure):
         ("hip_error", ctypes.c_int32), ("passes", ctypes.c_int32),
         ("ms_tpass_kernel", ctypes.c_double), ("tpass_launches", ctypes.c_int64),
         ("a_reads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("ms_fused_kernel", ctypes.c_double), ("fused_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):

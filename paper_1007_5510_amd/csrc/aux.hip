@@ -409,4 +409,14 @@ hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = v;
+}
+
+hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, v);
+  return hipGetLastError();
+}
+
 }  // namespace rpca

@@ -66,6 +66,42 @@ struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
   int64_t ldzs3 = 0, zplane3 = 0;
 };
 
+// One power step of Step 1 on a single read of float32 A (panel_fused.hip): Z as the forward
+// product writes it and the adjoint partial sums of ngroups * nseg row segments as the adjoint
+// product writes them (P[split][ncols (+1 with ones)][ldp]).  Cooperative launch of
+// ngroups * gsize workgroups, one per CU, grouped by XCD.
+struct FusedArgs {
+  const void* A = nullptr;
+  int64_t lda = 0, m = 0, n = 0;
+  const float* shift = nullptr;
+  const float* Xt = nullptr;
+  int64_t ldx = 0;
+  int ncols = 0;
+  bool ones = false;
+  const float* corr = nullptr;
+  const double* alpha = nullptr;
+  float* Z = nullptr;
+  int64_t ldz = 0;
+  float* P = nullptr;
+  int64_t ldp = 0, split_stride = 0;
+  int ngroups = 0, gsize = 0;      // groups of compute units and their size (gsize = xcc_per_group * cu_per_xcc)
+  int xcc_per_group = 0, cu_per_xcc = 0;
+  int64_t rows_per_group = 0;      // multiple of 16, ngroups * rows_per_group >= m
+  int nseg = 1;                    // row segments per group (partial sums each)
+  int64_t seg_rows = 0;            // multiple of 16, nseg * seg_rows >= rows_per_group
+  bool vec = false;
+  unsigned* ws = nullptr;          // fused_ws_words() words
+  float* xpart = nullptr;          // fused_xpart_floats(gsize) floats
+  float* xred = nullptr;           // fused_xred_floats() floats
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+size_t fused_ws_words();
+size_t fused_xpart_floats(int gsize);
+size_t fused_xred_floats();
+bool fused_fits(int64_t n, int ncols, bool ones, int ngroups, int gsize);
+int fused_max_tiles_per_member();
+hipError_t launch_fused_f32(const FusedArgs& a, hipStream_t st);
+
 hipError_t launch_fwd_f32(const FwdArgs& a, hipStream_t st);
 // K split for the forward product over `slots` concurrent blocks
 void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk);
@@ -215,6 +251,7 @@ hipError_t launch_sub_cols(float* X, int64_t ldx, int64_t rows, int cols, const 
 hipError_t launch_check_finite_f32(const float* X, int64_t rows, int64_t cols, int64_t ld, int* flag,
                                    hipStream_t st);
 hipError_t launch_fill_f64(double* p, int64_t count, double v, hipStream_t st);
+hipError_t launch_fill_u32(unsigned* p, int64_t count, unsigned v, hipStream_t st);
 // out[r][c] = X[r][c] - colsum[c] * inv_rows, float64 (projects the column sums out)
 hipError_t launch_center_cols(const float* X, int64_t ldx, int64_t rows, int64_t cols, const double* colsum,
                               double inv_rows, double* out, int64_t ldo, hipStream_t st);

@@ -169,6 +169,17 @@ struct rpca_plan_s {
     int64_t rps_y = 0, fwd_kchunk = 0, ldpf = 0, rps_cs = 0, rps_cz = 0;
   } tr;
 
+  // single-read power steps (panel_fused.hip): groups of compute units (one or two XCDs each)
+  // split the columns; rows of a group in blocks of 16; adjoint partial sums per row segment
+  bool fused = false;
+  int fu_ngroups = 0, fu_xpg = 0, fu_cpx = 0, fu_nseg = 1;
+  int64_t fu_rpg = 0, fu_segrows = 0;
+  unsigned* fu_ws = nullptr;
+  float* fu_xpart = nullptr;
+  float* fu_xred = nullptr;
+  std::vector<EventPair> ev_fused;
+  int nev_fused = 0;
+
   bool have_state = false;
   bool Qfinal_is_Q1 = false;
   const void* A_last = nullptr;  // matrix of the last factorisation (for the backward passes)
@@ -228,6 +239,10 @@ struct rpca_plan_s {
       if (e.b) (void)hipEventDestroy(e.b);
     }
     for (auto& e : ev_adj) {
+      if (e.a) (void)hipEventDestroy(e.a);
+      if (e.b) (void)hipEventDestroy(e.b);
+    }
+    for (auto& e : ev_fused) {
       if (e.a) (void)hipEventDestroy(e.a);
       if (e.b) (void)hipEventDestroy(e.b);
     }
@@ -408,8 +423,30 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     choose_rows(plan->panel_rows, 1024, 64, &plan->ns_pcs, &plan->rps_pcs);
   }
 
+  // Single-read power steps (RPCA_FLAG_FUSED) on float32 A in device memory: a cooperative launch
+  // over every CU of a device laid out as 8 XCDs of 32 CUs (MI355X); groups of one XCD when the column
+  // slices fit, else of two.  The kernel checks the layout it finds (plan-time dry run below).
+  if (!lowp && !plan->x6 && !plan->f64s1 && !trans && !plan->streamed && i > 0 && m >= 32768 &&
+      (desc->flags & RPCA_FLAG_FUSED) != 0 && prop.cooperativeLaunch && prop.multiProcessorCount == 256 &&
+      plan->max_lds >= 160 * 1024) {
+    const int nx = 8, cpx = 32;
+    for (int xpg = 1; xpg <= 2 && !plan->fused; ++xpg) {
+      const int gs = xpg * cpx, ng = nx / xpg;
+      if (!fused_fits(n, l, true, ng, gs)) continue;
+      plan->fused = true;
+      plan->fu_ngroups = ng;
+      plan->fu_xpg = xpg;
+      plan->fu_cpx = cpx;
+      plan->fu_rpg = round_up((m + ng - 1) / ng, 16);
+      plan->fu_nseg = (int)((plan->fu_rpg + 8191) / 8192);
+      plan->fu_segrows = round_up((plan->fu_rpg + plan->fu_nseg - 1) / plan->fu_nseg, 16);
+    }
+  }
+
   const int64_t ldx = plan->ldx;
   int64_t pcount = std::max<int64_t>((int64_t)plan->ns_y * (l + 1), (int64_t)plan->ns_t * L) * plan->ldp;
+  if (plan->fused)
+    pcount = std::max<int64_t>(pcount, (int64_t)plan->fu_ngroups * plan->fu_nseg * (l + 1) * plan->ldp);
   if (plan->streamed)
     pcount = std::max<int64_t>(pcount, std::max<int64_t>((int64_t)plan->ns_py * l, (int64_t)plan->ns_pt * L) *
                                            plan->ldp);
@@ -525,6 +562,11 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
     ALLOC(Zh, (int64_t)plan->cpad_z * plan->ldzs);
     ALLOC(Zl, (int64_t)plan->cpad_z * plan->ldzs);
   }
+  if (plan->fused) {
+    ALLOC(fu_ws, (int64_t)fused_ws_words());
+    ALLOC(fu_xpart, (int64_t)fused_xpart_floats(plan->fu_xpg * plan->fu_cpx));
+    ALLOC(fu_xred, (int64_t)fused_xred_floats());
+  }
 #undef ALLOC
   // zero the padded transposed blocks and the shift once (padding must stay 0)
   if (hipMemset(plan->X, 0, sizeof(float) * (size_t)(i + 1) * l * ldx) != hipSuccess ||
@@ -532,9 +574,46 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
       hipMemset(plan->P, 0, sizeof(float) * (size_t)pcount) != hipSuccess)
     return fail(RPCA_ERR_HIP);
   if (hipDeviceSynchronize() != hipSuccess) return fail(RPCA_ERR_HIP);
+  if (plan->fused) {
+    // dry run without rows: the kernel's group set-up checks the XCD layout it meets; any
+    // mismatch (or a refused cooperative launch) leaves the plan on the two-launch power steps
+    FusedArgs fa;
+    fa.A = plan->X;
+    fa.lda = ldx;
+    fa.m = 0;
+    fa.n = n;
+    fa.shift = plan->shift;
+    fa.Xt = plan->X;
+    fa.ldx = ldx;
+    fa.ncols = l;
+    fa.ones = true;
+    fa.Z = plan->H;
+    fa.ldz = L;
+    fa.P = plan->P;
+    fa.ldp = plan->ldp;
+    fa.split_stride = (int64_t)(l + 1) * plan->ldp;
+    fa.ngroups = plan->fu_ngroups;
+    fa.xcc_per_group = plan->fu_xpg;
+    fa.cu_per_xcc = plan->fu_cpx;
+    fa.gsize = plan->fu_xpg * plan->fu_cpx;
+    fa.rows_per_group = plan->fu_rpg;
+    fa.nseg = plan->fu_nseg;
+    fa.seg_rows = plan->fu_segrows;
+    fa.ws = plan->fu_ws;
+    fa.xpart = plan->fu_xpart;
+    fa.xred = plan->fu_xred;
+    unsigned herr = 1u;
+    hipError_t le = launch_fused_f32(fa, nullptr);
+    if (le == hipSuccess) le = hipDeviceSynchronize();
+    if (le == hipSuccess) le = hipMemcpy(&herr, plan->fu_ws + 257, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (le != hipSuccess) (void)hipGetLastError();
+    if (le != hipSuccess || herr != 0u) plan->fused = false;
+    if (hipMemset(plan->P, 0, sizeof(float) * (size_t)pcount) != hipSuccess) return fail(RPCA_ERR_HIP);
+  }
   plan->ev_fwd.resize(16);
   plan->ev_adj.resize(16);
-  for (auto* vec : {&plan->ev_fwd, &plan->ev_adj})
+  plan->ev_fused.resize(plan->fused ? 8 : 0);
+  for (auto* vec : {&plan->ev_fwd, &plan->ev_adj, &plan->ev_fused})
     for (auto& ev : *vec)
       if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) return fail(RPCA_ERR_HIP);
   if (desc->flags & RPCA_FLAG_PROFILE)
@@ -573,6 +652,19 @@ EventPair* next_fwd_events(rpca_plan_s* plan) {
 hipError_t mark_stage(rpca_plan_s* plan, int q) {
   if (!(plan->d.flags & RPCA_FLAG_PROFILE) || plan->stage_ev[q] == nullptr) return hipSuccess;
   return hipEventRecord(plan->stage_ev[q], plan->stream);
+}
+
+// A bounded wait of the fused power step gave up: its output is not valid.  The plan
+// keeps to the two-launch power steps from now on; the call reports the failure.
+rpca_status fused_failed(rpca_plan_s* plan) {
+  plan->fused = false;
+  plan->stats.hip_error = (int32_t)hipErrorLaunchTimeOut;
+  return RPCA_ERR_HIP;
+}
+
+EventPair* next_fused_events(rpca_plan_s* plan) {
+  if (!(plan->d.flags & RPCA_FLAG_PROFILE) || plan->nev_fused >= (int)plan->ev_fused.size()) return nullptr;
+  return &plan->ev_fused[plan->nev_fused++];
 }
 
 EventPair* next_adj_events(rpca_plan_s* plan) {
@@ -811,7 +903,7 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
   rpca_stats& sx = plan->stats;
   sx = rpca_stats{};
   plan->have_state = false;
-  plan->nev_fwd = plan->nev_adj = 0;
+  plan->nev_fwd = plan->nev_adj = plan->nev_fused = 0;
   plan->tp_ev0 = plan->tp_ev1 = 0;
   plan->A_last = streamed ? nullptr : A;
   plan->lda_last = lda;
@@ -1123,11 +1215,76 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
   }
 
+  // single-read power steps: float32 A in device memory, not the split products
+  const bool fused = plan->fused && !lowp && !x6 && !streamed && !f64s1 && !trans;
   for (int j = 0; !streamed && !f64s1 && !trans && j <= i; ++j) {
     float* Xj = plan->X + (int64_t)j * l * ldx;
     // with fused centring, pass 0 writes the uncorrected product (A - 1 s0^T) G and corrects it below
     const bool p0 = fuse0 && j == 0;
     if (center && !p0) RPCA_TRY(launch_dot_rows(dres, Xj, ldx, n, l, plan->corr, st));
+    if (fused && j < i) {
+      // H^(j) = alpha_j ((A - 1 s^T) X_j - 1 corr^T) and the row-segment partial sums of
+      // (A - 1 s^T)^T H^(j) (plus the ones column in pass 0) from one read of A
+      FusedArgs fu;
+      fu.A = A;
+      fu.lda = lda;
+      fu.m = m;
+      fu.n = n;
+      fu.shift = shift;
+      fu.Xt = Xj;
+      fu.ldx = ldx;
+      fu.ncols = l;
+      fu.ones = p0;
+      fu.corr = (center && !p0) ? plan->corr : nullptr;
+      fu.alpha = plan->alpha + j;
+      fu.Z = plan->H + (int64_t)j * l;
+      fu.ldz = L;
+      fu.P = plan->P;
+      fu.ldp = plan->ldp;
+      fu.split_stride = (int64_t)(p0 ? l + 1 : l) * plan->ldp;
+      fu.ngroups = plan->fu_ngroups;
+      fu.xcc_per_group = plan->fu_xpg;
+      fu.cu_per_xcc = plan->fu_cpx;
+      fu.gsize = plan->fu_xpg * plan->fu_cpx;
+      fu.rows_per_group = plan->fu_rpg;
+      fu.nseg = plan->fu_nseg;
+      fu.seg_rows = plan->fu_segrows;
+      fu.vec = vec;
+      fu.ws = plan->fu_ws;
+      fu.xpart = plan->fu_xpart;
+      fu.xred = plan->fu_xred;
+      if (EventPair* ev = next_fused_events(plan)) {
+        fu.ev_begin = ev->a;
+        fu.ev_end = ev->b;
+      }
+      RPCA_TRY(launch_fused_f32(fu, st));
+      // a timeout of the kernel's bounded waits is reported through flags[5]
+      RPCA_TRY(hipMemcpyAsync(plan->flags + 5, plan->fu_ws + 257, sizeof(int), hipMemcpyDeviceToDevice, st));
+      sx.passes += 1;
+      sx.a_reads += 1;
+      sx.a_bytes_read += m * n * bpe;
+      const int nsp = plan->fu_ngroups * plan->fu_nseg;
+      if (center) {
+        RPCA_TRY(launch_colsum(ST_F32, plan->H + (int64_t)j * l, L, m, l, nullptr, 0, plan->rps_cn, plan->ns_cn,
+                               plan->csp, st));
+        RPCA_TRY(launch_colsum_reduce(plan->csp, plan->ns_cn, l, 1.0, plan->zsum, nullptr, nullptr, st));
+      }
+      if (p0) {
+        RPCA_TRY(launch_pass0_center(plan->P, nsp, fu.split_stride, plan->ldp, l, n, m, plan->shift, plan->d0,
+                                     plan->mu, plan->dres, st));
+        dres = plan->dres;
+      }
+      float* Xn = plan->X + (int64_t)(j + 1) * l * ldx;
+      int npart = 0;
+      RPCA_TRY(launch_reduce_y(plan->P, nsp, fu.split_stride, plan->ldp, l, n, nullptr, p0 ? plan->d0 : dres,
+                               center ? plan->zsum : nullptr, Xn, ldx, plan->sqp, &npart, st));
+      if (p0) {  // H^(0) = (A - 1 s0^T) G - 1 (d0^T G)  (block scale 1)
+        RPCA_TRY(launch_dot_rows(plan->d0, Xj, ldx, n, l, plan->corr, st));
+        RPCA_TRY(launch_sub_cols(plan->H, L, m, l, plan->corr, st));
+      }
+      RPCA_TRY(launch_finish_scale(plan->sqp, npart, rescale, plan->alpha + j + 1, plan->flags, st));
+      continue;
+    }
     FwdArgs fa;
     fa.A = A;
     fa.lda = lda;
@@ -1269,10 +1426,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
     if (level == 3) {
       s = householder_qr(plan, x_f64, Hqr, &Qfinal);
       if (s != RPCA_OK) return s;
-      int hf0 = 0;
-      RPCA_TRY(hipMemcpyAsync(&hf0, plan->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      int hf0[6] = {0, 0, 0, 0, 0, 0};
+      RPCA_TRY(hipMemcpyAsync(hf0, plan->flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
       RPCA_TRY(hipStreamSynchronize(st));
-      if (hf0 != 0) return RPCA_ERR_NONFINITE;
+      if (hf0[5] != 0) return fused_failed(plan);
+      if (hf0[0] != 0) return RPCA_ERR_NONFINITE;
       break;
     }
     if (level == 2) {
@@ -1282,10 +1440,11 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
         continue;
       }
       if (s != RPCA_OK) return s;
-      int hf0 = 0;
-      RPCA_TRY(hipMemcpyAsync(&hf0, plan->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      int hf0[6] = {0, 0, 0, 0, 0, 0};
+      RPCA_TRY(hipMemcpyAsync(hf0, plan->flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
       RPCA_TRY(hipStreamSynchronize(st));
-      if (hf0 != 0) return RPCA_ERR_NONFINITE;
+      if (hf0[5] != 0) return fused_failed(plan);
+      if (hf0[0] != 0) return RPCA_ERR_NONFINITE;
       break;
     }
     if (level == 0) {
@@ -1306,9 +1465,10 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       if (s != RPCA_OK) return s;
       Qfinal = plan->Q1;
     }
-    int hf[4] = {0, 0, 0, 0};
-    RPCA_TRY(hipMemcpyAsync(hf, plan->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    int hf[6] = {0, 0, 0, 0, 0, 0};
+    RPCA_TRY(hipMemcpyAsync(hf, plan->flags, 6 * sizeof(int), hipMemcpyDeviceToHost, st));
     RPCA_TRY(hipStreamSynchronize(st));
+    if (hf[5] != 0) return fused_failed(plan);
     if (hf[0] != 0) return RPCA_ERR_NONFINITE;
     const bool broke = hf[1] != 0 || hf[2] != 0 || hf[3] != 0;
     if (!broke) break;
@@ -1473,6 +1633,12 @@ extern "C" rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda,
       sx.ms_adj_kernel += t;
       if (q >= plan->tp_ev0 && q < plan->tp_ev1) sx.ms_tpass_kernel += t;
     }
+    for (int q = 0; q < plan->nev_fused; ++q) {
+      float t = 0.f;
+      RPCA_TRY(hipEventElapsedTime(&t, plan->ev_fused[q].a, plan->ev_fused[q].b));
+      sx.ms_fused_kernel += t;
+    }
+    sx.fused_launches = plan->nev_fused;
     sx.fwd_launches = plan->nev_fwd;
     sx.adj_launches = plan->nev_adj;
     sx.tpass_launches = plan->tp_ev1 - plan->tp_ev0;
