@@ -114,7 +114,8 @@ def test_incore_full_size_against_oracle():
     on the same stored A and G, panel by panel as Section 4.2 describes): every singular value within
     1e-5 relative (the float32 target), and sampled rows of the power blocks H^(1) and H^(2)
     (eqs. second_prod..last_prod, divided by the device's positive block scales) within 2e-6
-    relative, the float32 product bound used for the H blocks at the parity sizes.  Vectors are not
+    relative, the float32 product bound used for the H blocks at the parity sizes; both for the
+    power steps as forward + adjoint launches and as the single-read fused kernel.  Vectors are not
     compared: past the first few signal directions sigma_j sits in the noise bulk with no gap."""
     _need_gpu()
     import time
@@ -122,12 +123,19 @@ def test_incore_full_size_against_oracle():
     from paper_1007_5510_amd import rpca, _lib
     A = _workload()
     Gh = F.gaussian_G(SEED, N, L).astype(np.float32)
-    plan = rpca.Plan(M, N, K, L, I, center=True, flags=_lib.FLAG_PROFILE | _lib.FLAG_KEEP_STATE)
-    U, S, V = plan.factor(A, G=torch.from_numpy(Gh).cuda())
-    torch.cuda.synchronize()
-    S = S.cpu().double().numpy()
-    H = plan.state("H").cpu().double().numpy()
-    scale = np.cumprod(plan.state("HSCALE").cpu().numpy())
+    runs = {}
+    # the default power steps (forward + adjoint launches) and the single-read fused kernel
+    for name, flags in (("two-launch", 0), ("fused", _lib.FLAG_FUSED)):
+        plan = rpca.Plan(M, N, K, L, I, center=True, flags=flags | _lib.FLAG_PROFILE | _lib.FLAG_KEEP_STATE)
+        U, S, V = plan.factor(A, G=torch.from_numpy(Gh).cuda())
+        torch.cuda.synchronize()
+        st = plan.stats()
+        print(f"  {name}: fused launches {st['fused_launches']}, reads of A {st['a_reads']}", flush=True)
+        assert st["a_reads"] == (I + 2 if name == "fused" else 2 * I + 2)
+        runs[name] = (S.cpu().double().numpy(), plan.state("H").cpu().double().numpy(),
+                      np.cumprod(plan.state("HSCALE").cpu().numpy()))
+        plan.close()
+        del U, V
     Ah = A.cpu().numpy()
     del A
     torch.cuda.empty_cache()
@@ -135,17 +143,18 @@ def test_incore_full_size_against_oracle():
     t = time.perf_counter()
     orc = O.rpca(Ah, K, L, I, Gh, center=True)
     print(f"  oracle {time.perf_counter() - t:.1f} s", flush=True)
-    rel = np.abs(S - orc.S) / orc.S
-    print(f"  sigma rel err max {rel.max():.3e} (sigma_1 {orc.S[0]:.5f}, sigma_k {orc.S[-1]:.5f})")
-    assert rel.max() <= 1e-5
     rows = np.unique(np.concatenate([np.array([0, 1, 4095, 4096, 16383, 16384, M - 1]),
                                      np.random.default_rng(9).integers(0, M, 57)]))
-    for j in (1, 2):
-        got = H[rows, j * L:(j + 1) * L] / scale[j]
-        ref = orc.H_blocks[j][rows]
-        err = (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
-        print(f"  sampled H^({j}) rows: max rel err {err:.2e} over {len(rows)} rows")
-        assert err <= 2e-6
+    for name, (S, H, scale) in runs.items():
+        rel = np.abs(S - orc.S) / orc.S
+        print(f"  {name}: sigma rel err max {rel.max():.3e} (sigma_1 {orc.S[0]:.5f}, sigma_k {orc.S[-1]:.5f})")
+        assert rel.max() <= 1e-5
+        for j in (1, 2):
+            got = H[rows, j * L:(j + 1) * L] / scale[j]
+            ref = orc.H_blocks[j][rows]
+            err = (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+            print(f"  {name}: sampled H^({j}) rows: max rel err {err:.2e} over {len(rows)} rows")
+            assert err <= 2e-6
 
 
 def test_on_the_fly_full_size_sampled_and_invariants():
