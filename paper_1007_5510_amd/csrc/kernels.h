@@ -269,7 +269,7 @@ void set_max_lds(size_t bytes);
 hipError_t launch_cholesky(double* W, int L, double rel_tol, int* flag, hipStream_t st);
 // Rinv = R^-1 (upper)
 hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st);
-// Cholesky (as launch_cholesky) and R^-1 (as launch_triinv) in one launch, for L <= 180
+// Cholesky (as launch_cholesky) and R^-1 (as launch_triinv) in one launch, for L <= 1024
 bool cholinv_fits(int L);
 hipError_t launch_cholinv(double* W, int L, double rel_tol, int* flag, double* Rinv, hipStream_t st);
 // C = A B (A: M x K float or double, B: K x N double), optional upper-triangular B,

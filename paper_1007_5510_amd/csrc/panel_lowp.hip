@@ -172,20 +172,23 @@ __global__ __launch_bounds__(256) void split_zt_kernel(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Pipelining (both kernels).  Both streamed operands go from global memory
-// straight into LDS (global_load_lds_dwordx4: lane l's 16 bytes land at
-// M0 + 16 l), through a ring of NB stages: the loads of stage t + NB - 1 are
-// issued as soon as the workgroup has finished stage t - 1, so NB - 1 stages
-// are in flight without costing registers.  A is private to each wave (its
-// slot holds exactly the bytes each lane would have loaded, read back at
-// lane * 16, conflict-free); the float operand (X or Z hi/lo) is shared by
-// the workgroup and stored with the 16-byte chunk index XOR-swizzled by the
-// column (chunk c of column j at position c ^ (j & 7)), which makes the
-// column-strided 16-byte operand reads conflict-free.  Every wave issues the
-// same number of loads per stage (addresses clamped past the end), so a
-// counted s_waitcnt vmcnt(P (NB - 2)) means "this wave's loads of the
-// current stage have landed"; a plain s_barrier after it makes all waves'
-// loads visible.  No __syncthreads (its fence would wait for every load).
+// Pipelining (both kernels).  The A data a wave multiplies is its own: it
+// goes from global memory straight into VGPRs (buffer loads whose range ends
+// with the matrix) through a ring of DA stages held in registers, so DA - 1
+// stages are in flight per wave without LDS traffic.  The float operand (X,
+// or Z hi/lo in the adjoint) is shared by the workgroup: it goes from global
+// memory into LDS (global_load_lds_dwordx4: lane l's 16 bytes land at
+// M0 + 16 l) through a ring of DX stages, stored with the 16-byte chunk index
+// XOR-swizzled by the column (chunk c of column j at position c ^ (j & 7)),
+// which makes the column-strided 16-byte operand reads conflict-free.  Every
+// wave issues, per stage, its shared-operand loads and then its A loads (the
+// order pinned by scheduling barriers, every address clamped into range), so
+// a counted s_waitcnt vmcnt means "this wave's shared-operand loads of the
+// stage have landed"; a plain s_barrier after it makes all waves' loads
+// visible.  The loads are issued without branches (a branch around loads
+// makes the compiler wait for all of them where the paths join), and the
+// split sizes are whole rings, so only the last split has a partial ring.
+// No __syncthreads (its fence would wait for every load).
 // ---------------------------------------------------------------------------
 typedef __attribute__((address_space(3))) void* lds_ptr_t;
 typedef const __attribute__((address_space(1))) void* gbl_ptr_t;
@@ -199,26 +202,11 @@ constexpr int waitcnt_imm(int vm, int lgkm) {
   return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | ((lgkm & 15) << 8);
 }
 
-template <int ST>
-struct LpCfg {
-  static constexpr int ES = ST == ST_FP8 ? 1 : 2;  // bytes per stored element
-  static constexpr int W = ST == ST_HILO ? 4 : 8;  // waves per workgroup
-  static constexpr int NB = ST == ST_FP8 ? 4 : 3;  // ring stages
-  // A bytes per wave per stage: 32 rows x 64 K (forward) or 64 rows x 32 columns (adjoint)
-  static constexpr int SA = 2048 * ES * (ST == ST_HILO ? 2 : 1);
-  static constexpr int AQ = SA / 1024;         // 16-byte loads per lane per stage for A
-  static constexpr int XQ = 16 / W;            // loads per lane per stage for the shared operand
-  static constexpr int P = AQ + XQ;            // loads per lane per stage
-  static constexpr int SX = 16384;             // shared operand bytes per stage (2 planes x 64 x 64 bf16)
-  static constexpr int LDS = NB * (SX + W * SA);
-};
-
 // swizzled byte offset of 16-byte chunk c of column j (128-byte rows)
 RPCA_DEV int swz(int j, int c) { return j * 128 + 16 * (c ^ (j & 7)); }
 
 // ---------------------------------------------------------------------------
-// forward: a wave owns 32 rows x 64 columns (two tiles of 32); a workgroup of
-// W waves 32 W rows.  Stage = 64 K = 4 MFMA steps.
+// forward: stage = 64 K = 4 MFMA steps.
 // K offsets within a stage of the 8-entry group of MFMA step s, lane group g:
 //   bf16 / hi+lo: 16 s + 8 g;   fp8: 32 (s/2) + 16 g + 8 (s%2)  (16-byte loads)
 // ---------------------------------------------------------------------------
@@ -229,31 +217,70 @@ RPCA_DEV int lp_koff(int s, int g) {
   return ST == ST_FP8 ? 32 * (s >> 1) + 16 * g + 8 * (s & 1) : 16 * s + 8 * g;
 }
 
+// forward: a wave owns RT x 32 rows x 64 columns (RT row tiles share every X operand read);
+// a workgroup of W waves 32 RT W rows shares one X stage, so X traffic per byte of A falls
+// with RT.  A goes global -> VGPRs through a ring of DA stages (buffer loads, branch-free);
+// X goes global -> LDS (global_load_lds) through a ring of DX stages.  Per stage every wave
+// issues its XQ X loads and then its A loads, in that order (scheduling barriers pin it), so
+// "X of stage t has landed" is a counted wait.
 template <int ST>
-__global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void fwd_lp_kernel(
+struct LpFwdCfg {
+  static constexpr int ES = ST == ST_FP8 ? 1 : 2;
+  static constexpr int W = 8;
+  static constexpr int RT = ST == ST_HILO ? 1 : 2;
+  static constexpr int AQ1 = ST == ST_FP8 ? 2 : (ST == ST_HILO ? 8 : 4);  // 16-byte A loads per lane per row tile
+  static constexpr int AQ = RT * AQ1;
+  static constexpr int DA = ST == ST_FP8 ? 4 : (ST == ST_HILO ? 3 : 2);
+  static constexpr int DX = 3 < DA ? 3 : DA;
+  static constexpr int XQ = 16 / W;
+  static constexpr int P = AQ + XQ;
+  static constexpr int SX = 16384;
+  static constexpr int LDS = DX * SX;
+  static constexpr int ROWS = 32 * RT * W;
+  static constexpr int XWAIT = AQ + (DX - 2) * P;  // loads younger than X of the stage being computed
+  static_assert(XWAIT < 64, "vmcnt range");
+  static_assert(DA >= DX && DX >= 2, "the prologue issues X of stage 0 only when DA >= DX");
+};
+
+template <int ST>
+__global__ __launch_bounds__(512, 1) void fwd_lp_kernel(
     const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, int64_t plane,
     const uint16_t* __restrict__ Xh, const uint16_t* __restrict__ Xl, int64_t ldxs, int ncols, int64_t kchunk,
     const float* __restrict__ corr, const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz,
     int64_t split_stride, int direct) {
-  using C = LpCfg<ST>;
-  constexpr int ES = C::ES, W = C::W, NB = C::NB, SA = C::SA, AQ = C::AQ, XQ = C::XQ, P = C::P, SX = C::SX;
+  using C = LpFwdCfg<ST>;
+  constexpr int ES = C::ES, W = C::W, RT = C::RT, AQ1 = C::AQ1, AQ = C::AQ, DA = C::DA, DX = C::DX, XQ = C::XQ,
+                SX = C::SX;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 31, g = lane >> 5;
-  const int64_t r0 = (int64_t)blockIdx.x * (32 * W) + wave * 32;
+  const int64_t r0 = (int64_t)blockIdx.x * C::ROWS + wave * (32 * RT);
   const int sk = blockIdx.y;
   const int c0 = blockIdx.z * 64;
   const int64_t kbeg = (int64_t)sk * kchunk;
   const int64_t kend = kbeg + kchunk < n ? kbeg + kchunk : n;
-  const int64_t row = r0 + li;
-  const unsigned char* __restrict__ arow =
-      reinterpret_cast<const unsigned char*>(Av) + (row < m ? row : m - 1) * lda * ES;
   const int64_t plane_bytes = plane * ES;
-  unsigned char* const xring = lds;                                // NB x SX
-  unsigned char* const aring = lds + NB * SX + wave * (NB * SA);   // this wave's NB x SA
+  // A through buffer loads: the wave's first row (clamped) is the base; lane offsets hold the
+  // row (clamped to m - 1) and 16 g bytes; the stage's K offset is a scalar.  The range ends
+  // with the matrix, so loads past it return zeros.
+  const int64_t rb = r0 < m ? r0 : m - 1;
+  const unsigned char* abase = reinterpret_cast<const unsigned char*>(Av) + rb * lda * ES;
+  const int64_t arange = (m - rb) * lda * ES;
+  const int nrec = arange < 0x7FFFFFFF ? (int)arange : 0x7FFFFFFF;
+  const __amdgpu_buffer_rsrc_t rs_hi = __builtin_amdgcn_make_buffer_rsrc((void*)abase, (short)0, nrec, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_lo =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(abase + plane_bytes), (short)0, nrec, 0x00020000);
+  int voff[RT];
+  const unsigned char* arow[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = r0 + 32 * rt + li;
+    const int64_t rc = row < m ? row : m - 1;
+    voff[rt] = (int)((rc - rb) * lda * ES) + 16 * g;
+    arow[rt] = reinterpret_cast<const unsigned char*>(Av) + rc * lda * ES;
+  }
 
-  // shared-operand loads of this wave: instruction j covers plane j/8, columns 8 (j%8) .. +7
   const uint16_t* xsrc[XQ];
 #pragma unroll
   for (int q = 0; q < XQ; ++q) {
@@ -262,7 +289,6 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void fwd_lp_kernel(
     const int c = (lane & 7) ^ (col & 7);
     xsrc[q] = ((j >> 3) ? Xl : Xh) + (int64_t)(c0 + col) * ldxs + 8 * c;
   }
-  // byte offset (within the row) of A load q of the stage at K position kb
   auto aoff = [&](int q, int64_t kb) -> int64_t {
     if (ST == ST_FP8) return kb + 32 * q + 16 * g;
     if (ST == ST_HILO) return (q & 4 ? plane_bytes : 0) + 2 * (kb + 16 * (q & 3) + 8 * g);
@@ -276,42 +302,37 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void fwd_lp_kernel(
   const int64_t nfull = (kend - kbeg) / LP_KST;
   const int64_t kt = kbeg + nfull * LP_KST;
   const bool tail = kt < kend;
-  const int64_t nst = nfull + (tail ? 1 : 0);  // stages that need X
-  // issue the P loads of stage t into ring slot t % NB (A clamped to full stages, X to all stages)
-  auto issue = [&](int64_t t, int slot) {
+  const int64_t nst = nfull + (tail ? 1 : 0);
+  auto issue_x = [&](int64_t t) {
+    if (t < 0) return;
     const int64_t tx = t < nst ? t : nst - 1;
-    const int64_t ta = t < nfull ? t : (nfull > 0 ? nfull - 1 : 0);
+    unsigned char* xs = lds + (int)(t % DX) * SX;
     const int64_t kbx = kbeg + tx * LP_KST;
-    const int64_t kba = kbeg + ta * LP_KST;
-    unsigned char* xs = xring + slot * SX;
 #pragma unroll
     for (int q = 0; q < XQ; ++q) dma16(xsrc[q] + kbx, xs + 1024 * (wave * XQ + q));
-    unsigned char* as = aring + slot * SA;
-    if (nfull > 0) {
+  };
+  // branch-free (a branch around loads makes the compiler wait for every load at the join);
+  // with no full stage the loads read the split's first 64 K of the rows (never used)
+  auto issue_a = [&](int64_t t, u32x4 (&dst)[AQ]) {
+    const int64_t ta = t < nfull ? t : nfull - 1;
+    const int kbs = (int)((kbeg + (ta > 0 ? ta : 0) * LP_KST) * ES);
 #pragma unroll
-      for (int q = 0; q < AQ; ++q) dma16(arow + aoff(q, kba), as + 1024 * q);
-    } else {  // no full stage: keep the load count with an in-bounds dummy source (never used)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int q = 0; q < AQ; ++q) dma16(Xh + 8 * lane, as + 1024 * q);
-    }
+      for (int q = 0; q < AQ1; ++q)
+        dst[rt * AQ1 + q] = __builtin_bit_cast(
+            u32x4, __builtin_amdgcn_raw_buffer_load_b128((q & 4) && ST == ST_HILO ? rs_lo : rs_hi, voff[rt],
+                                                         kbs + 32 * (q & 3), 0));
   };
 
-  floatx16 acc[2], acc2[2];
+  // one float32 chain per output over the split (the MFMA sums 16 exact products per step)
+  floatx16 acc[RT][2];
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      acc[ct][v] = 0.f;
-      acc2[ct][v] = 0.f;
-    }
-  auto fold = [&]() {
+    for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      acc2[ct] += acc[ct];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[ct][v] = 0.f;
-    }
-  };
+      for (int v = 0; v < 16; ++v) acc[rt][ct][v] = 0.f;
   auto read_x = [&](u32x4 (&xo)[2][2], const unsigned char* xs, int s) {
     const int c = lp_koff<ST>(s, g) >> 3;
 #pragma unroll
@@ -319,18 +340,18 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void fwd_lp_kernel(
 #pragma unroll
       for (int hl = 0; hl < 2; ++hl) xo[ct][hl] = ld16(xs + hl * 8192 + swz(32 * ct + li, c));
   };
-  // A operands (hi, lo) of step s; `mask` >= 0 keeps only entries with K < kend (tail stage)
-  auto read_a = [&](const unsigned char* as, int s, int64_t kb, bool masked, u32x4& ah, u32x4& al) {
+  // A operands (hi, lo) of row tile rt, step s; `masked` keeps only entries with K < kend
+  auto a_op = [&](const u32x4 (&ar)[AQ], int rt, int s, int64_t kb, bool masked, u32x4& ah, u32x4& al) {
     if (ST == ST_FP8) {
-      u32x4 w = ld16(as + 1024 * (s >> 1) + 16 * lane);
+      u32x4 w = ar[rt * AQ1 + (s >> 1)];
       if (masked) {
         const int64_t valid = kend - aelem(s >> 1, kb);
         w = keep_u8(w, valid <= 0 ? 0 : (valid >= 16 ? 16 : (int)valid));
       }
       ah = (s & 1) ? fp8x8_to_bf16(w.z, w.w) : fp8x8_to_bf16(w.x, w.y);
     } else {
-      ah = ld16(as + 1024 * s + 16 * lane);
-      if (ST == ST_HILO) al = ld16(as + 1024 * (s + 4) + 16 * lane);
+      ah = ar[rt * AQ1 + s];
+      if (ST == ST_HILO) al = ar[rt * AQ1 + s + 4];
       if (masked) {
         const int64_t valid = kend - aelem(s, kb);
         const int v = valid <= 0 ? 0 : (valid >= 8 ? 8 : (int)valid);
@@ -339,97 +360,101 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void fwd_lp_kernel(
       }
     }
   };
-  auto compute = [&](int slot, int64_t kb, bool masked) {
-    const unsigned char* xs = xring + slot * SX;
-    const unsigned char* as = aring + slot * SA;
-    u32x4 xo[2][2], xn[2][2], ah, al, nh, nl;
+  auto compute = [&](const unsigned char* xs, const u32x4 (&ar)[AQ], int64_t kb, bool masked) {
+    u32x4 xo[2][2], xn[2][2];
     read_x(xo, xs, 0);
-    read_a(as, 0, kb, masked, ah, al);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      if (s < 3) {  // operands of the next step are read while this step runs
-        read_x(xn, xs, s + 1);
-        read_a(as, s + 1, kb, masked, nh, nl);
-      }
+      if (s < 3) read_x(xn, xs, s + 1);
 #pragma unroll
-      for (int hl = 0; hl < 2; ++hl)
+      for (int rt = 0; rt < RT; ++rt) {
+        u32x4 ah, al;
+        a_op(ar, rt, s, kb, masked, ah, al);
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma_bf16(ah, xo[ct][hl], acc[ct]);
-      if (ST == ST_HILO) {
+        for (int hl = 0; hl < 2; ++hl)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) acc[ct] = mfma_bf16(al, xo[ct][0], acc[ct]);
+          for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = mfma_bf16(ah, xo[ct][hl], acc[rt][ct]);
+        if (ST == ST_HILO) {
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) acc[rt][ct] = mfma_bf16(al, xo[ct][0], acc[rt][ct]);
+        }
       }
       if (s < 3) {
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
           for (int hl = 0; hl < 2; ++hl) xo[ct][hl] = xn[ct][hl];
-        ah = nh;
-        al = nl;
       }
     }
   };
-  // wait for this wave's loads of the current stage (NB - 2 younger stages may stay in flight)
-  // and its LDS reads, then meet the other waves
   auto stage_sync = [&]() {
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(P * (NB - 2), 0));
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(C::XWAIT, 0));
     __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto issue = [&](int64_t t_x, int64_t t_a, u32x4 (&dst)[AQ]) {
+    issue_x(t_x);
+    __builtin_amdgcn_sched_barrier(0);
+    issue_a(t_a, dst);
+    __builtin_amdgcn_sched_barrier(0);
   };
 
+  u32x4 ar[DA][AQ];
+  // prologue: virtual iterations v = -(DA-1) .. -1 issue X(v + DX - 1) (when >= 0) and A(v + DA - 1)
   if (nst > 0) {
 #pragma unroll
-    for (int u = 0; u < NB - 1; ++u) issue(u, u);
+    for (int v = -(DA - 1); v < 0; ++v) issue(v + DX - 1, v + DA - 1, ar[v + DA - 1]);
   }
   int64_t t = 0;
-  for (; t + NB <= nfull; t += NB) {
+  for (; t + DA <= nfull; t += DA) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
+    for (int u = 0; u < DA; ++u) {
       stage_sync();
-      issue(t + u + NB - 1, (u + NB - 1) % NB);  // into the slot stage t+u-1 used
-      compute(u, 0, false);
-    }
-    fold();  // NB stages per float32 chain before folding
-  }
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    if (t + u < nfull) {  // leftover full stages (same issue pattern keeps the counts uniform)
-      stage_sync();
-      issue(t + u + NB - 1, (u + NB - 1) % NB);
-      compute(u, 0, false);
+      issue(t + u + DX - 1, t + u + DA - 1, ar[(u + DA - 1) % DA]);
+      compute(lds + (int)((t + u) % DX) * SX, ar[u], 0, false);
     }
   }
-  fold();
+#pragma unroll
+  for (int u = 0; u < DA; ++u) {
+    if (t + u < nfull) {
+      stage_sync();
+      issue(t + u + DX - 1, t + u + DA - 1, ar[(u + DA - 1) % DA]);
+      compute(lds + (int)((t + u) % DX) * SX, ar[u], 0, false);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
   if (tail) {
-    // X of stage nfull is (or will be) in slot nfull % NB; A of the tail is reloaded masked
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
     __builtin_amdgcn_s_barrier();
-    const int slot = (int)(nfull % NB);
-    unsigned char* as = aring + slot * SA;
+    u32x4 at[AQ];
 #pragma unroll
-    for (int q = 0; q < AQ; ++q) {
-      const int64_t valid = kend - aelem(q, kt);
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (valid > 0) v = ld16(arow + aoff(q, kt));
-      *reinterpret_cast<u32x4*>(as + 1024 * q + 16 * lane) = v;
-    }
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));
-    compute(slot, kt, true);
-    fold();
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int q = 0; q < AQ1; ++q) {
+        const int64_t valid = kend - aelem(q, kt);
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (valid > 0) v = ld16(arow[rt] + aoff(q, kt));
+        at[rt * AQ1 + q] = v;
+      }
+    compute(lds + (int)(nfull % DX) * SX, at, kt, true);
   }
 
   const double alpha = (direct && alpha_ptr != nullptr) ? *alpha_ptr : 1.0;
   float* __restrict__ Zs = Z + (direct ? 0 : (int64_t)sk * split_stride);
 #pragma unroll
-  for (int ct = 0; ct < 2; ++ct) {
-    const int c = c0 + 32 * ct + li;
-    if (c >= ncols) continue;
-    const double cr = (direct && corr != nullptr) ? (double)corr[c] : 0.0;
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int64_t r = r0 + 8 * (v >> 2) + 4 * g + (v & 3);
-      if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * ((double)acc2[ct][v] - cr)) : acc2[ct][v];
+    for (int ct = 0; ct < 2; ++ct) {
+      const int c = c0 + 32 * ct + li;
+      if (c >= ncols) continue;
+      const double cr = (direct && corr != nullptr) ? (double)corr[c] : 0.0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t r = r0 + 32 * rt + 8 * (v >> 2) + 4 * g + (v & 3);
+        const float a2 = acc[rt][ct][v];
+        if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * ((double)a2 - cr)) : a2;
+      }
     }
-  }
 }
 
 // Z[r][c] = alpha (sum_s P[s][r][c] - corr[c]) in float64, s in split order
@@ -450,10 +475,12 @@ __global__ __launch_bounds__(256) void fwd_lp_reduce_kernel(const float* __restr
 }
 
 // ---------------------------------------------------------------------------
-// adjoint: a wave owns 32 columns of A and 32 ZT columns of Z (ZT tiles: 2 for
-// the power steps, 6 for a wide Z such as the T pass, so that A is read once
-// for up to 192 Z columns); a workgroup of W waves 32 W columns of A.  Stage = 64 rows (two 32-row
-// halves).  Lane i + 32 g loads columns 16 g .. 16 g + 15 of row i of a half;
+// adjoint: a wave owns 32 CT columns of A (CT tiles: 2 for the power steps,
+// where the two tiles share every Z operand read, 1 for a wide Z) and 32 ZT
+// columns of Z (ZT tiles: 2 for the power steps, 6 for a wide Z such as the T
+// pass, so that A is read once for up to 192 Z columns); a workgroup of W
+// waves 32 CT W columns of A.  Stage = 64 rows (two 32-row halves).  Lane
+// i + 32 g loads columns 16 g .. 16 g + 15 of row i of a half and tile;
 // after the transposing MFMAs lane j + 32 h holds tile column
 //   cmap(j) = 16 ((j % 16) / 8) + 8 (j / 16) + j % 8
 // at rows 8 (v/4) + 4 h + v%4 (register v) of the half.  The Z planes hold
@@ -462,33 +489,39 @@ __global__ __launch_bounds__(256) void fwd_lp_reduce_kernel(const float* __restr
 // ---------------------------------------------------------------------------
 constexpr int LA_RS = 64;
 
-// Z tiles per wave for a product with ncols columns of Z, and the ring depth:
-// six tiles leave LDS for two stages only (their loads then wait a full stage)
+// Z tiles per wave for a product with ncols columns of Z
 constexpr int lp_zt(int ncols) { return ncols > 64 ? 6 : 2; }
 template <int ST, int ZT>
 struct LpAdjCfg {
-  static constexpr int NB = ZT == 2 ? LpCfg<ST>::NB : 2;
-  static constexpr int SX = ZT * 8192;                        // Z bytes per stage (2 planes x 32 ZT x 64 rows)
-  static constexpr int XQ = 8 * ZT / LpCfg<ST>::W;            // Z loads per lane per stage
-  static constexpr int P = LpCfg<ST>::AQ + XQ;
-  static constexpr int LDS = NB * (SX + LpCfg<ST>::W * LpCfg<ST>::SA);
-  static constexpr bool FOLD = ZT == 2;                       // second float32 level (registers allow it)
-  static_assert((8 * ZT) % LpCfg<ST>::W == 0, "Z loads must divide evenly over the waves");
+  static constexpr int ES = ST == ST_FP8 ? 1 : 2;
+  static constexpr int W = 8;
+  static constexpr int CT = ZT == 2 && ST != ST_HILO ? 2 : 1;   // 32-column tiles of A per wave
+  static constexpr int HQ = ST == ST_FP8 ? 1 : (ST == ST_HILO ? 4 : 2);  // A loads per lane per 32-row half and tile
+  static constexpr int AQ = 2 * CT * HQ;
+  static constexpr int COLS = 32 * CT * W;
+  static constexpr int DA = ZT == 2 ? (ST == ST_HILO ? 2 : (ST == ST_FP8 ? 3 : 2))
+                                    : (ST == ST_HILO ? 2 : 4);
+  static constexpr int DZ0 = ZT == 2 ? 4 : 3;
+  static constexpr int DZ = DZ0 < DA ? DZ0 : DA;
+  static constexpr int SX = ZT * 8192;              // Z bytes per stage (2 planes x 32 ZT x 64 rows)
+  static constexpr int XQ = 8 * ZT / W;             // Z loads per lane per stage
+  static constexpr int P = AQ + XQ;
+  static constexpr int LDS = DZ * SX;
+  static constexpr int XWAIT = AQ + (DZ - 2) * P;
+  static_assert((8 * ZT) % W == 0, "Z loads must divide evenly over the waves");
   static_assert(LDS <= 163840, "ring exceeds the LDS of a workgroup");
+  static_assert(DZ >= 2 && XWAIT < 64, "ring depth");
 };
 
 template <int ST, int ZT>
-__global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
+__global__ __launch_bounds__(512, 1) void adj_lp_kernel(
     const void* __restrict__ Av, int64_t lda, int64_t m, int64_t n, int64_t plane,
     const uint16_t* __restrict__ Zh, const uint16_t* __restrict__ Zl, int64_t ldzs, int ncols,
     int64_t rows_per_split, int jtiles, int ctiles, int nsplit, float* __restrict__ P, int64_t ldp,
     int64_t split_stride) {
-  using C = LpCfg<ST>;
   using D = LpAdjCfg<ST, ZT>;
-  constexpr int ES = C::ES, W = C::W, SA = C::SA, AQ = C::AQ;
-  constexpr int NB = D::NB, XQ = D::XQ, PQ = D::P, SX = D::SX;
-  constexpr int ZPL = SX / 2;  // bytes of one Z plane in a stage
-  constexpr int HQ = AQ / 2;   // A loads per 32-row half
+  constexpr int ES = D::ES, W = D::W, CT = D::CT, HQ = D::HQ, AQ = D::AQ, DA = D::DA, DZ = D::DZ, XQ = D::XQ, SX = D::SX;
+  constexpr int ZPL = SX / 2;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const int64_t total = (int64_t)jtiles * ctiles * nsplit;
   const int64_t logical = xcd_remap_lp(blockIdx.x, total);
@@ -498,21 +531,21 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
   const int sp = (int)(rest / ctiles);
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 31, g = lane >> 5;
-  const int64_t cw = (int64_t)ct * (32 * W) + wave * 32;
+  const int64_t cw = (int64_t)ct * D::COLS + wave * (32 * CT);
   const int j0 = jt * 32 * ZT;
   const int64_t rbeg = (int64_t)sp * rows_per_split;
   const int64_t rend = rbeg + rows_per_split < m ? rbeg + rows_per_split : m;
   const int64_t plane_bytes = plane * ES;
-  unsigned char* const zring = lds;
-  unsigned char* const aring = lds + NB * SX + wave * (NB * SA);
 
-  // this lane's 16 columns: address (column 0 past n) and valid count
-  const int64_t cA = cw + 16 * g;
-  const int cvalid = n - cA <= 0 ? 0 : (n - cA >= 16 ? 16 : (int)(n - cA));
-  const int64_t coff = (cA < n ? cA : 0) * ES;
-  // routing matrices of the transpose (bf16 1.0 = 0x3F80)
+  int cvalid[CT], coff[CT];
+#pragma unroll
+  for (int c2 = 0; c2 < CT; ++c2) {
+    const int64_t cA = cw + 32 * c2 + 16 * g;
+    cvalid[c2] = n - cA <= 0 ? 0 : (n - cA >= 16 ? 16 : (int)(n - cA));
+    coff[c2] = (int)((cA < n ? cA : 0) * ES);
+  }
   u32x4 E1 = {0u, 0u, 0u, 0u}, E2 = {0u, 0u, 0u, 0u};
   {
     const int jj = li & 15, e = jj & 7;
@@ -524,8 +557,6 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
         E2[e >> 1] = one;
     }
   }
-  // shared Z loads of this wave: instruction j covers plane j / (4 ZT), Z columns
-  // 8 (j % (4 ZT)) .. +7
   const uint16_t* zsrc[XQ];
 #pragma unroll
   for (int q = 0; q < XQ; ++q) {
@@ -534,52 +565,48 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
     const int c = (lane & 7) ^ (col & 7);
     zsrc[q] = ((j / (4 * ZT)) ? Zl : Zh) + (int64_t)(j0 + col) * ldzs + 8 * c;
   }
-  // rows past m read row m-1 (finite) against zero Z rows
   const int64_t nfull = rend > rbeg ? (rend - rbeg + LA_RS - 1) / LA_RS : 0;
-  auto issue = [&](int64_t t, int slot) {
+  auto issue_z = [&](int64_t t) {
+    if (t < 0) return;
     const int64_t tc = t < nfull ? t : nfull - 1;
     const int64_t rb = rbeg + tc * LA_RS;
-    unsigned char* zs = zring + slot * SX;
+    unsigned char* zs = lds + (int)(t % DZ) * SX;
 #pragma unroll
     for (int q = 0; q < XQ; ++q) dma16(zsrc[q] + rb, zs + 1024 * (wave * XQ + q));
-    unsigned char* as = aring + slot * SA;
+  };
+  // rows past m read row m - 1 (finite) against zero Z rows
+  auto issue_a = [&](int64_t t, u32x4 (&dst)[AQ]) {
+    const int64_t tc = t < nfull ? t : nfull - 1;
+    const int64_t rb = rbeg + tc * LA_RS;
+    const unsigned char* base = reinterpret_cast<const unsigned char*>(Av) + rb * lda * ES;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsl =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(base + plane_bytes), (short)0, 0x7FFFFFFF, 0x00020000);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int64_t r = rb + 32 * h + li < m ? rb + 32 * h + li : m - 1;
-      const unsigned char* p = reinterpret_cast<const unsigned char*>(Av) + r * lda * ES + coff;
-      if (ST == ST_FP8) {
-        dma16(p, as + 1024 * h);
-      } else {
-        dma16(p, as + 1024 * (HQ * h));
-        dma16(p + 16, as + 1024 * (HQ * h + 1));
-        if (ST == ST_HILO) {
-          dma16(p + plane_bytes, as + 1024 * (HQ * h + 2));
-          dma16(p + plane_bytes + 16, as + 1024 * (HQ * h + 3));
-        }
-      }
+      const int64_t r = rb + 32 * h + li;
+      const int vr = (int)(((r < m ? r : m - 1) - rb) * lda * ES);
+#pragma unroll
+      for (int c2 = 0; c2 < CT; ++c2)
+#pragma unroll
+        for (int e = 0; e < HQ; ++e)
+          dst[(h * CT + c2) * HQ + e] = __builtin_bit_cast(
+              u32x4, __builtin_amdgcn_raw_buffer_load_b128(ST == ST_HILO && e >= 2 ? rsl : rs, vr + coff[c2],
+                                                           16 * (e & 1), 0));
     }
   };
 
-  floatx16 acc[ZT], acc2[D::FOLD ? ZT : 1];
+  // one float32 chain per output over the row split
+  floatx16 acc[CT][ZT];
 #pragma unroll
-  for (int zt = 0; zt < ZT; ++zt)
+  for (int c2 = 0; c2 < CT; ++c2)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      acc[zt][v] = 0.f;
-      if (D::FOLD) acc2[zt][v] = 0.f;
-    }
-  auto fold = [&]() {
-    if (!D::FOLD) return;
+    for (int zt = 0; zt < ZT; ++zt)
 #pragma unroll
-    for (int zt = 0; zt < ZT; ++zt) {
-      acc2[zt] += acc[zt];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[zt][v] = 0.f;
-    }
-  };
-  auto transpose = [&](u32x4 t1, u32x4 t2, u32x4& oa, u32x4& ob) {
-    t1 = keep_bf16(t1, cvalid < 8 ? cvalid : 8);
-    t2 = keep_bf16(t2, cvalid > 8 ? cvalid - 8 : 0);
+      for (int v = 0; v < 16; ++v) acc[c2][zt][v] = 0.f;
+  auto transpose = [&](u32x4 t1, u32x4 t2, int cv, u32x4& oa, u32x4& ob) {
+    t1 = keep_bf16(t1, cv < 8 ? cv : 8);
+    t2 = keep_bf16(t2, cv > 8 ? cv - 8 : 0);
     floatx16 d;
 #pragma unroll
     for (int v = 0; v < 16; ++v) d[v] = 0.f;
@@ -588,24 +615,22 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
     oa = u32x4{pack_bf16(d[0], d[1]), pack_bf16(d[2], d[3]), pack_bf16(d[4], d[5]), pack_bf16(d[6], d[7])};
     ob = u32x4{pack_bf16(d[8], d[9]), pack_bf16(d[10], d[11]), pack_bf16(d[12], d[13]), pack_bf16(d[14], d[15])};
   };
-  auto tr_half = [&](const unsigned char* as, int h, u32x4& oa, u32x4& ob, u32x4& la, u32x4& lb) {
+  auto tr_half = [&](const u32x4 (&ar)[AQ], int h, int c2, u32x4& oa, u32x4& ob, u32x4& la, u32x4& lb) {
+    const int b = (h * CT + c2) * HQ;
     if (ST == ST_FP8) {
-      const u32x4 w = ld16(as + 1024 * h + 16 * lane);
-      transpose(fp8x8_to_bf16(w.x, w.y), fp8x8_to_bf16(w.z, w.w), oa, ob);
+      const u32x4 w = ar[b];
+      transpose(fp8x8_to_bf16(w.x, w.y), fp8x8_to_bf16(w.z, w.w), cvalid[c2], oa, ob);
     } else {
-      transpose(ld16(as + 1024 * (HQ * h) + 16 * lane), ld16(as + 1024 * (HQ * h + 1) + 16 * lane), oa, ob);
-      if (ST == ST_HILO)
-        transpose(ld16(as + 1024 * (HQ * h + 2) + 16 * lane), ld16(as + 1024 * (HQ * h + 3) + 16 * lane), la, lb);
+      transpose(ar[b], ar[b + 1], cvalid[c2], oa, ob);
+      if (ST == ST_HILO) transpose(ar[b + 2], ar[b + 3], cvalid[c2], la, lb);
     }
   };
-  auto compute = [&](int slot) {
-    const unsigned char* zs = zring + slot * SX;
-    const unsigned char* as = aring + slot * SA;
-    u32x4 oa[2], ob[2], la[2], lb[2];
-    tr_half(as, 0, oa[0], ob[0], la[0], lb[0]);
-    tr_half(as, 1, oa[1], ob[1], la[1], lb[1]);
+  auto compute = [&](const unsigned char* zs, const u32x4 (&ar)[AQ]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      u32x4 oa[CT], ob[CT], la[CT], lb[CT];
+#pragma unroll
+      for (int c2 = 0; c2 < CT; ++c2) tr_half(ar, h, c2, oa[c2], ob[c2], la[c2], lb[c2]);
 #pragma unroll
       for (int zt = 0; zt < ZT; ++zt) {
         const int col = 32 * zt + li;
@@ -613,57 +638,69 @@ __global__ __launch_bounds__(64 * LpCfg<ST>::W, 1) void adj_lp_kernel(
         const u32x4 zbh = ld16(zs + swz(col, 4 * h + 2 + g));
         const u32x4 zal = ld16(zs + ZPL + swz(col, 4 * h + g));
         const u32x4 zbl = ld16(zs + ZPL + swz(col, 4 * h + 2 + g));
-        acc[zt] = mfma_bf16(oa[h], zah, acc[zt]);
-        acc[zt] = mfma_bf16(ob[h], zbh, acc[zt]);
-        acc[zt] = mfma_bf16(oa[h], zal, acc[zt]);
-        acc[zt] = mfma_bf16(ob[h], zbl, acc[zt]);
-        if (ST == ST_HILO) {
-          acc[zt] = mfma_bf16(la[h], zah, acc[zt]);
-          acc[zt] = mfma_bf16(lb[h], zbh, acc[zt]);
+#pragma unroll
+        for (int c2 = 0; c2 < CT; ++c2) {
+          acc[c2][zt] = mfma_bf16(oa[c2], zah, acc[c2][zt]);
+          acc[c2][zt] = mfma_bf16(ob[c2], zbh, acc[c2][zt]);
+          acc[c2][zt] = mfma_bf16(oa[c2], zal, acc[c2][zt]);
+          acc[c2][zt] = mfma_bf16(ob[c2], zbl, acc[c2][zt]);
+          if (ST == ST_HILO) {
+            acc[c2][zt] = mfma_bf16(la[c2], zah, acc[c2][zt]);
+            acc[c2][zt] = mfma_bf16(lb[c2], zbh, acc[c2][zt]);
+          }
         }
       }
     }
   };
   auto stage_sync = [&]() {
-    __builtin_amdgcn_s_waitcnt(waitcnt_imm(PQ * (NB - 2), 0));
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(D::XWAIT, 0));
     __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto issue = [&](int64_t tz, int64_t ta, u32x4 (&dst)[AQ]) {
+    issue_z(tz);
+    __builtin_amdgcn_sched_barrier(0);
+    issue_a(ta, dst);
+    __builtin_amdgcn_sched_barrier(0);
   };
 
+  u32x4 ar[DA][AQ];
   if (nfull > 0) {
 #pragma unroll
-    for (int u = 0; u < NB - 1; ++u) issue(u, u);
+    for (int v = -(DA - 1); v < 0; ++v) issue(v + DZ - 1, v + DA - 1, ar[v + DA - 1]);
   }
   int64_t t = 0;
-  for (; t + NB <= nfull; t += NB) {
+  for (; t + DA <= nfull; t += DA) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
+    for (int u = 0; u < DA; ++u) {
       stage_sync();
-      issue(t + u + NB - 1, (u + NB - 1) % NB);
-      compute(u);
+      issue(t + u + DZ - 1, t + u + DA - 1, ar[(u + DA - 1) % DA]);
+      compute(lds + (int)((t + u) % DZ) * SX, ar[u]);
     }
-    fold();
   }
 #pragma unroll
-  for (int u = 0; u < NB; ++u) {
+  for (int u = 0; u < DA; ++u) {
     if (t + u < nfull) {
       stage_sync();
-      issue(t + u + NB - 1, (u + NB - 1) % NB);
-      compute(u);
+      issue(t + u + DZ - 1, t + u + DA - 1, ar[(u + DA - 1) % DA]);
+      compute(lds + (int)((t + u) % DZ) * SX, ar[u]);
     }
   }
-  fold();
   __builtin_amdgcn_s_waitcnt(waitcnt_imm(0, 0));  // no load in flight at exit
 
   float* __restrict__ Ps = P + (int64_t)sp * split_stride;
+#pragma unroll
+  for (int c2 = 0; c2 < CT; ++c2)
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) {
     const int j = j0 + 32 * zt + li;
     if (j >= ncols) continue;
     float* __restrict__ prow = Ps + (int64_t)j * ldp;
-    const floatx16& r = D::FOLD ? acc2[D::FOLD ? zt : 0] : acc[zt];
+    const floatx16& r = acc[c2][zt];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t c = cw + 16 * (q & 1) + 8 * (q >> 1) + 4 * g;
+      const int64_t c = cw + 32 * c2 + 16 * (q & 1) + 8 * (q >> 1) + 4 * g;
       const floatx4 o = {r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]};
       if (c + 3 < n) {
         *reinterpret_cast<floatx4*>(prow + c) = o;
@@ -702,8 +739,8 @@ hipError_t launch_split_zt(const float* Z, int64_t ldz, int64_t m, int ncols, ui
 template <int ST>
 static void launch_fwd_lp_t(const FwdArgs& a, int ns, int ctiles, float* out, int64_t ldo, int64_t kchunk,
                             bool direct, hipStream_t st) {
-  using C = LpCfg<ST>;
-  dim3 grid((unsigned)((a.m + 32 * C::W - 1) / (32 * C::W)), (unsigned)ns, (unsigned)ctiles);
+  using C = LpFwdCfg<ST>;
+  dim3 grid((unsigned)((a.m + C::ROWS - 1) / C::ROWS), (unsigned)ns, (unsigned)ctiles);
   hipLaunchKernelGGL((fwd_lp_kernel<ST>), grid, dim3(64 * C::W), C::LDS, st, a.A, a.lda, a.m, a.n, a.plane, a.Xh,
                      a.Xl, a.ldxs, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
 }
@@ -740,12 +777,11 @@ hipError_t launch_fwd_lowp(int storage, const FwdArgs& a, hipStream_t st) {
 
 template <int ST, int ZT>
 static void launch_adj_lp_t(const AdjArgs& a, int jtiles, hipStream_t st) {
-  using C = LpCfg<ST>;
-  const int ctiles = (int)((a.n + 32 * C::W - 1) / (32 * C::W));
-  const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
   using D = LpAdjCfg<ST, ZT>;
+  const int ctiles = (int)((a.n + D::COLS - 1) / D::COLS);
+  const int64_t total = (int64_t)jtiles * ctiles * a.nsplit;
   constexpr size_t lds = D::LDS;
-  hipLaunchKernelGGL((adj_lp_kernel<ST, ZT>), dim3((unsigned)total), dim3(64 * C::W), lds, st,
+  hipLaunchKernelGGL((adj_lp_kernel<ST, ZT>), dim3((unsigned)total), dim3(64 * D::W), lds, st,
                      a.A, a.lda, a.m, a.n, a.plane, a.Zh, a.Zl, a.ldzs, a.ncols, a.rows_per_split, jtiles, ctiles,
                      a.nsplit, a.P, a.ldp, a.split_stride);
 }
@@ -777,17 +813,22 @@ hipError_t launch_adj_lowp(int storage, const AdjArgs& a, hipStream_t st) {
   return e;
 }
 
-static int lp_waves(int storage) { return storage == ST_HILO ? LpCfg<ST_HILO>::W : LpCfg<ST_BF16>::W; }
 
 // K split for the low-precision forward product (32 W-row workgroups, 64-K stages;
 // slots = workgroups resident at once, one per CU)
+static int64_t fwd_gran(int storage) {
+  const int da = storage == ST_FP8 ? LpFwdCfg<ST_FP8>::DA : (storage == ST_HILO ? LpFwdCfg<ST_HILO>::DA : LpFwdCfg<ST_BF16>::DA);
+  return (int64_t)LP_KST * da;
+}
+
 void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk) {
-  const int64_t rows = 32 * lp_waves(storage);
+  const int64_t rows = storage == ST_FP8 ? LpFwdCfg<ST_FP8>::ROWS : (storage == ST_HILO ? LpFwdCfg<ST_HILO>::ROWS : LpFwdCfg<ST_BF16>::ROWS);
   const int64_t rt = (m + rows - 1) / rows;
+  const int64_t gran = fwd_gran(storage);  // whole register rings per split
   int best = 1;
   double best_eff = 0.0;
   for (int s = 1; s <= 8; ++s) {
-    const int64_t chunk = ((n + s - 1) / s + LP_KST - 1) / LP_KST * LP_KST;
+    const int64_t chunk = ((n + s - 1) / s + gran - 1) / gran * gran;
     const int64_t ns = (n + chunk - 1) / chunk;
     const int64_t blocks = rt * ns;
     const int64_t rounds = (blocks + slots - 1) / slots;
@@ -798,7 +839,7 @@ void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit,
     }
     if (eff >= 0.94) break;
   }
-  const int64_t chunk = ((n + best - 1) / best + LP_KST - 1) / LP_KST * LP_KST;
+  const int64_t chunk = ((n + best - 1) / best + gran - 1) / gran * gran;
   *ksplit = (int)((n + chunk - 1) / chunk);
   *kchunk = chunk;
 }
@@ -806,8 +847,9 @@ void fwd_split_lp(int storage, int64_t m, int64_t n, int64_t slots, int* ksplit,
 // Row split of the low-precision adjoint (rows per split a multiple of 64)
 void adj_split_lp(int storage, int64_t m, int64_t n, int ncols, int64_t slots, int* nsplit,
                   int64_t* rows_per_split) {
-  const int64_t cols = 32 * lp_waves(storage);
   const int ztc = 32 * lp_zt(ncols);
+  const int64_t cols = lp_zt(ncols) == 2 ? (storage == ST_FP8 ? LpAdjCfg<ST_FP8, 2>::COLS : (storage == ST_HILO ? LpAdjCfg<ST_HILO, 2>::COLS : LpAdjCfg<ST_BF16, 2>::COLS))
+                                         : (storage == ST_FP8 ? LpAdjCfg<ST_FP8, 6>::COLS : (storage == ST_HILO ? LpAdjCfg<ST_HILO, 6>::COLS : LpAdjCfg<ST_BF16, 6>::COLS));
   const int64_t per = (int64_t)((ncols + ztc - 1) / ztc) * ((n + cols - 1) / cols);
   int64_t lo = (2 * slots + per - 1) / per;
   int64_t hi = lo * 4 + 8;
@@ -816,9 +858,13 @@ void adj_split_lp(int storage, int64_t m, int64_t n, int ncols, int64_t slots, i
   if (hi > maxs) hi = maxs;
   if (lo < 1) lo = 1;
   double best = -1.0;
-  int64_t bs = 1, br = ((m + LA_RS - 1) / LA_RS) * LA_RS;
+  const int zt = lp_zt(ncols);
+  const int da = zt == 2 ? (storage == ST_FP8 ? LpAdjCfg<ST_FP8, 2>::DA : (storage == ST_HILO ? LpAdjCfg<ST_HILO, 2>::DA : LpAdjCfg<ST_BF16, 2>::DA))
+                         : (storage == ST_FP8 ? LpAdjCfg<ST_FP8, 6>::DA : (storage == ST_HILO ? LpAdjCfg<ST_HILO, 6>::DA : LpAdjCfg<ST_BF16, 6>::DA));
+  const int64_t gran = (int64_t)LA_RS * da;  // whole register rings per split
+  int64_t bs = 1, br = ((m + gran - 1) / gran) * gran;
   for (int64_t s = lo; s <= hi; ++s) {
-    const int64_t r = ((m + s - 1) / s + LA_RS - 1) / LA_RS * LA_RS;
+    const int64_t r = ((m + s - 1) / s + gran - 1) / gran * gran;
     const int64_t ns = (m + r - 1) / r;
     const int64_t blocks = per * ns;
     const int64_t rounds = (blocks + slots - 1) / slots;

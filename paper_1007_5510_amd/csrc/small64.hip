@@ -668,13 +668,220 @@ __global__ __launch_bounds__(1024) void chol_blk_kernel(double* __restrict__ W, 
     for (int j = lane; j < L; j += 64) Rinv[(int64_t)i * L + j] = j >= i ? at(i, j) : 0.0;
 }
 
+// ---------------------------------------------------------------- blocked, in global memory
+// The same blocked Cholesky and inverse for 192 < L <= 1024, where the packed triangle no longer
+// fits in LDS: the matrix stays in global memory (at most 8 MiB, resident in L2) and one workgroup
+// of 16 waves walks it by 16 x 16 blocks exactly as above.  W is factored in place (lower
+// triangle zeroed); R is then copied to Rinv and inverted there.  Entries past L read as the
+// identity and are never written, which is the identity padding of the LDS version.  Block
+// results are held in registers (up to 4 block rows per wave) until every wave has read its
+// operands; barriers order the global-memory updates within the workgroup.
+constexpr int CBG_MAXNB = 64;
+
+bool chol_blkg_fits(int L) { return L >= 1 && L <= CB * CBG_MAXNB; }
+
+template <bool CHOL>
+__global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W, int L, double rel_tol,
+                                                         int* __restrict__ flag, double* __restrict__ Rinv) {
+  __shared__ double d0[CB * CBG_MAXNB];
+  __shared__ double Tm[CB * CB];  // R_kk (factor) or X_jj (inverse), row-major
+  __shared__ double rinv[CB];
+  const int Lp = (L + CB - 1) / CB * CB, NB = Lp / CB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  // 32-bit element offsets (L <= 1024) keep one address register per access
+  auto get = [&](const double* A, int i, int j) -> double {
+    return (i < L && j < L) ? A[(unsigned)(i * L + j)] : (i == j ? 1.0 : 0.0);
+  };
+  auto put = [&](double* A, int i, int j, double v) {
+    if (i < L && j < L) A[(unsigned)(i * L + j)] = v;
+  };
+
+  if (CHOL) {
+    for (int i = tid; i < L; i += 1024) d0[i] = W[(int64_t)i * L + i];
+    __syncthreads();
+    for (int kb = 0; kb < NB; ++kb) {
+      const int k0 = kb * CB;
+      if (wave == 0) {  // diagonal block: lane c holds column c
+        const int c = c16;
+        double w[CB];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) w[t] = t <= c ? get(W, k0 + t, k0 + c) : 0.0;
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          double p = __shfl(w[t], t, 64);
+          const int col = k0 + t;
+          const bool ok = col >= L || (isfinite(p) && p > 0.0 && p > rel_tol * d0[col]);
+          if (!ok) {
+            p = 1.0;
+            if (lane == 0) atomicCAS(flag, 0, col + 1);
+          }
+          const double r = sqrt(p), ir = 1.0 / r;
+          if (c == t) w[t] = r;
+          else if (c > t) w[t] *= ir;
+#pragma unroll
+          for (int u = t + 1; u < CB; ++u) {
+            const double rtu = __shfl(w[t], u, 64);
+            if (c >= u) w[u] -= rtu * w[t];
+          }
+        }
+        if (lane < CB) {
+#pragma unroll
+          for (int t = 0; t < CB; ++t) {
+            if (t <= c) put(W, k0 + t, k0 + c, w[t]);
+            Tm[t * CB + c] = t <= c ? w[t] : 0.0;
+            if (t == c) rinv[t] = 1.0 / w[t];
+          }
+        }
+      }
+      __syncthreads();
+      // block row: R_kj = R_kk^-T W_kj, one thread per column c < L (R_kk from LDS; padding
+      // columns are zero in R and are skipped; c < L puts every row k0 + t below L)
+      const int c = k0 + CB + tid;
+      if (c < L) {
+        double* wc = W + (unsigned)(k0 * L + c);
+        double x[CB];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) x[t] = wc[t * L];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          double sacc = x[t];
+#pragma unroll
+          for (int q = 0; q < t; ++q) sacc -= Tm[q * CB + t] * x[q];
+          x[t] = sacc * rinv[t];
+        }
+#pragma unroll
+        for (int t = 0; t < CB; ++t) wc[t * L] = x[t];
+      }
+      __syncthreads();
+      // trailing upper blocks (jb, lb), kb < jb <= lb
+      const int nrem = NB - kb - 1;
+      const int ntile = nrem * (nrem + 1) / 2;
+      for (int q = wave; q < ntile; q += 16) {
+        int rem = q, jb = kb + 1;
+        while (rem >= NB - jb) {
+          rem -= NB - jb;
+          ++jb;
+        }
+        const int lb = jb + rem;
+        const int j0 = jb * CB, l0 = lb * CB;
+        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double a = get(W, k0 + 4 * s + g, j0 + c16);
+          const double b = get(W, k0 + 4 * s + g, l0 + c16);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = j0 + 4 * v + g, col = l0 + c16;
+          if (jb < lb || col >= row) put(W, row, col, get(W, row, col) - acc[v]);
+        }
+      }
+      __syncthreads();
+    }
+    for (int i = wave; i < L; i += 16)
+      for (int j = lane; j < i; j += 64) W[(int64_t)i * L + j] = 0.0;
+  }
+  // Rinv = R (upper, zeros below), then inverted in place
+  for (int i = wave; i < L; i += 16)
+    for (int j = lane; j < L; j += 64) Rinv[(int64_t)i * L + j] = j >= i ? W[(int64_t)i * L + j] : 0.0;
+  __syncthreads();
+  double* X = Rinv;
+  for (int jb = 0; jb < NB; ++jb) {
+    const int j0 = jb * CB;
+    if (wave == 0) {  // X_jj = R_jj^-1, lane c computes column c
+      const int c = c16;
+      double x[CB];
+#pragma unroll
+      for (int i = CB - 1; i >= 0; --i) {
+        const double rii = get(X, j0 + i, j0 + i);
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = i + 1; q < CB; ++q) sacc += get(X, j0 + i, j0 + q) * x[q];
+        x[i] = i > c ? 0.0 : (i == c ? 1.0 / rii : -sacc / rii);
+      }
+      if (lane < CB) {
+#pragma unroll
+        for (int i = 0; i < CB; ++i) Tm[i * CB + c] = x[i];
+      }
+    }
+    __syncthreads();
+    // Y_w = R_wj X_jj for block rows w < jb (w = wave + 16 r)
+    doublex4 acc[CBG_MAXNB / 16];
+#pragma unroll
+    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+      acc[r] = doublex4{0.0, 0.0, 0.0, 0.0};
+      const int w = wave + 16 * r;
+      if (w < jb) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const double a = get(X, CB * w + c16, j0 + 4 * s + g);
+          const double b = Tm[(4 * s + g) * CB + c16];
+          acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+      const int w = wave + 16 * r;
+      if (w < jb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) put(X, CB * w + 4 * v + g, j0 + c16, acc[r][v]);
+      }
+    }
+    __syncthreads();
+    // X_ij = -sum_{k = i}^{jb-1} X_ik Y_k for block rows i < jb
+#pragma unroll
+    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+      acc[r] = doublex4{0.0, 0.0, 0.0, 0.0};
+      const int w = wave + 16 * r;
+      if (w < jb) {
+        const int row = CB * w + c16;
+        for (int kb = w; kb < jb; ++kb) {
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int col = CB * kb + 4 * s + g;
+            const double a = col >= row ? get(X, row, col) : 0.0;
+            const double b = get(X, CB * kb + 4 * s + g, j0 + c16);
+            acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[r], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+      const int w = wave + 16 * r;
+      if (w < jb) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) put(X, CB * w + 4 * v + g, j0 + c16, -acc[r][v]);
+      }
+    }
+    if (wave == 15) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = lane + 64 * q, r = e >> 4, cc = e & 15;
+        if (cc >= r) put(X, j0 + r, j0 + cc, Tm[e]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 bool cholinv_fits(int L) {
-  return chol_blk_fits(L) || ((int64_t)L * (L + 1) / 2 <= 16 * 1024 && cholinv_lds(L) <= g_max_lds);
+  return chol_blk_fits(L) || chol_blkg_fits(L) ||
+         ((int64_t)L * (L + 1) / 2 <= 16 * 1024 && cholinv_lds(L) <= g_max_lds);
 }
 
 hipError_t launch_cholinv(double* W, int L, double rel_tol, int* flag, double* Rinv, hipStream_t st) {
   if (chol_blk_fits(L)) {
     hipLaunchKernelGGL((chol_blk_kernel<true>), dim3(1), dim3(1024), chol_blk_lds(L), st, W, L, rel_tol, flag, Rinv);
+    return hipGetLastError();
+  }
+  if (chol_blkg_fits(L)) {
+    hipLaunchKernelGGL((chol_blkg_kernel<true>), dim3(1), dim3(1024), 0, st, W, L, rel_tol, flag, Rinv);
     return hipGetLastError();
   }
   if (!cholinv_fits(L)) return hipErrorInvalidValue;
@@ -689,6 +896,11 @@ hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st) {
   if (chol_blk_fits(L)) {
     hipLaunchKernelGGL((chol_blk_kernel<false>), dim3(1), dim3(1024), chol_blk_lds(L), st, const_cast<double*>(R), L,
                        0.0, nullptr, Rinv);
+    return hipGetLastError();
+  }
+  if (chol_blkg_fits(L)) {
+    hipLaunchKernelGGL((chol_blkg_kernel<false>), dim3(1), dim3(1024), 0, st, const_cast<double*>(R), L, 0.0, nullptr,
+                       Rinv);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(1024), (size_t)L * sizeof(double), st, R, L, Rinv);

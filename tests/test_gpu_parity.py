@@ -309,6 +309,31 @@ def test_householder_step2_wide(m, n, k, l, i):
     assert np.abs(Q.T @ Q - np.eye((i + 1) * l)).max() < 1e-13
 
 
+@pytest.mark.parametrize("m,n,k,l,i,decay,levels", [
+    (12000, 1500, 40, 64, 1, 0.998, (0,)),     # L = 128: Cholesky QR twice, LDS-resident factor
+    (12000, 1500, 40, 128, 1, 0.998, (0,)),    # L = 256: Cholesky QR twice, factor in global memory
+    (6000, 1200, 100, 120, 2, 0.995, (0,)),    # L = 360, the width of the streamed workload
+    (6000, 1200, 100, 120, 2, 0.97, (1, 2)),   # L = 360, ill-conditioned H: shifted rounds
+])
+def test_cholesky_qr_wide(m, n, k, l, i, decay, levels):
+    """Cholesky QR (Step 2, Section 3) up to L = 360, where the Gram factor and its inverse run
+    blocked in global memory (the packed triangle no longer fits in LDS): the plain rounds for a
+    well-conditioned H, the shifted rounds for an ill-conditioned one; parity with the oracle's
+    pivoted QR route and an orthonormal Q."""
+    sigma = decay ** np.arange(n, dtype=np.float64)
+    p = F.svd_problem(7170 + l, m, n, sigma)
+    G = F.gaussian_G(7170 + l, n, l)
+    orc = O.rpca(p["A"], k, l, i, G)
+    g = run_gpu(p["A"], k, l, i, G=G)
+    level = g[3].stats()["qr_fallback"]
+    print(f"  L = {(i + 1) * l}: Step 2 level {level}")
+    assert level in levels
+    compare(g, orc, k, v_tol=2e-3)
+    Q = g[3].state("Q").cpu().numpy()
+    L = (i + 1) * l
+    assert np.abs(Q.T @ Q - np.eye(L)).max() < 1e-13
+
+
 def test_wide_t_pass_matches_fallback_bitwise():
     """The T pass with L = 120 runs on the wide-Z adjoint when A's rows allow vector loads and on the
     64-column adjoint otherwise; both sum every output over the same rows in the same order, so the
