@@ -483,6 +483,72 @@ def run_on_the_fly(args):
     print(json.dumps(out), flush=True)
 
 
+def run_backward(args):
+    """Reverse sweep at the differentiation size: m=50000, n=8000 float32 A = U diag(sigma) V^T with
+    sigma_j = 2 * 0.95^(j-1) (distinct gaps), U, V orthonormal from seeded Gaussians, k=16, l=24, i=2;
+    each step is one forward factorisation with saved state and one rpca_backward for cotangents
+    (gS, gU, gV) drawn iid N(0,1), A and everything else resident in HBM."""
+    import numpy as np
+    import torch
+    from synth import fixtures as F
+    from paper_1007_5510_amd import rpca, _lib
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    m, n, k, l, i, seed = 50000, 8000, 16, 24, 2, 5000
+    t = time.perf_counter()
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    U0 = torch.linalg.qr(torch.randn((m, n), dtype=torch.float64, device=dev, generator=g))[0]
+    V0 = torch.linalg.qr(torch.randn((n, n), dtype=torch.float64, device=dev, generator=g))[0]
+    sigma = 2.0 * 0.95 ** torch.arange(n, dtype=torch.float64, device=dev)
+    A = ((U0 * sigma) @ V0.T).float().contiguous()
+    del U0, V0
+    gS = torch.randn((k,), dtype=torch.float32, device=dev, generator=g)
+    gU = torch.randn((m, k), dtype=torch.float32, device=dev, generator=g)
+    gV = torch.randn((n, k), dtype=torch.float32, device=dev, generator=g)
+    G = torch.from_numpy(F.gaussian_G(seed, n, l).astype(np.float32)).to(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] A = U diag(sigma) V^T built on the device {time.perf_counter() - t:.1f}s")
+    plan = rpca.Plan(m, n, k, l, i, flags=_lib.FLAG_KEEP_STATE | _lib.FLAG_PROFILE, device=0)
+    U = torch.empty((m, k), dtype=torch.float32, device=dev)
+    S = torch.empty((k,), dtype=torch.float32, device=dev)
+    V = torch.empty((n, k), dtype=torch.float32, device=dev)
+    dA = torch.empty((m, n), dtype=torch.float32, device=dev)
+    for _ in range(args.warmup):
+        plan.factor(A, G=G, out=(U, S, V))
+        plan.backward(gS, gU, gV, out=dA)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    fwd_ms, bwd_ms = 0.0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0.record()
+        plan.factor(A, G=G, out=(U, S, V))
+        e1.record()
+        plan.backward(gS, gU, gV, out=dA)
+        e2.record()
+        e2.synchronize()
+        fwd_ms += e0.elapsed_time(e1)
+        bwd_ms += e1.elapsed_time(e2)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    fwd_ms /= args.steps
+    bwd_ms /= args.steps
+    ok = bool(torch.isfinite(dA).all().item())
+    log(f"[bench] forward {fwd_ms:.2f} ms, backward {bwd_ms:.2f} ms per step; dA finite: {ok}")
+    out = {
+        "metric": "rank-k PCA forward factorisation + reverse sweep (dL/dA) time",
+        "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"reverse sweep float32 {m}x{n}, sigma_j = 2*0.95^(j-1), k={k} l={l} i={i}",
+                   "m": m, "n": n, "k": k, "l": l, "i": i},
+        "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3), "dA_finite": ok,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_stream(args):
     """Streamed workload: A (m x 25000 float32, rank 100, sigma_j = exp(-j/20), noise 1e-4) in pinned
     host memory, moved over the host link in 16384-row panels once per pass; k=100, l=120, i=2."""
@@ -586,7 +652,8 @@ def main():
                          "its column means subtracted before conversion)")
     ap.add_argument("--paper-row", type=int, default=-1,
                     help="paper-ex1/paper-ex2: the row of Table 1a/2a to run (0-based; -1: every row)")
-    ap.add_argument("--workload", default="incore", choices=["incore", "stream", "on-the-fly", "paper-ex1", "paper-ex2"],
+    ap.add_argument("--workload", default="incore",
+                    choices=["incore", "stream", "on-the-fly", "paper-ex1", "paper-ex2", "backward"],
                     help="incore: A resident in HBM (default); stream: A in pinned host memory, panels over the "
                          "host link; on-the-fly: the streamed structure with every panel generated on the device in "
                          "every pass; paper-ex1 / paper-ex2: the paper's first / second example at its table sizes")
@@ -614,6 +681,9 @@ def main():
         return
     if args.workload == "on-the-fly":
         run_on_the_fly(args)
+        return
+    if args.workload == "backward":
+        run_backward(args)
         return
     if args.workload in ("paper-ex1", "paper-ex2"):
         run_paper_example(args)
@@ -799,8 +869,10 @@ def main():
             dom = {"kernel": "fwd_lp_kernel", "avg_ms": fwd_avg}
         gbs = m * n * bpe / (dom["avg_ms"] * 1e-3) / 1e9
         log(f"[bench] {dom['kernel']} avg {dom['avg_ms']:.3f} ms = {gbs:.0f} GB/s of stored A")
+        tr = measured_traffic(f"{dom['kernel']}/{storage}", "panel_lowp.hip", "incore_lowp_counters.md")
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": round(tr["fetch"] + tr["write"]) if tr else None,
+                "traffic_unit": "HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
                 "algorithmic_bytes": m * n * bpe, "kernel": dom["kernel"], "avg_launch_ms": round(dom["avg_ms"], 4)}
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
