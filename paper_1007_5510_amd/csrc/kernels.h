@@ -37,6 +37,8 @@ struct FwdArgs {              // Z = alpha ((A - 1 s^T) Xt^T - 1 corr^T)
   // (cpad x ldxs3 each, xplane3 elements apart)
   const uint16_t* X3 = nullptr;
   int64_t ldxs3 = 0, xplane3 = 0;
+  // split products with a single K split: set to 1 when an output entry is not finite
+  int* nonfinite = nullptr;
 };
 
 struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1

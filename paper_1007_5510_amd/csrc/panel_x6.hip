@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
     const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
     const uint16_t* __restrict__ Xp, int64_t ldxs, int64_t xplane, int ncols, int64_t kchunk,
     const float* __restrict__ corr, const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz,
-    int64_t split_stride, int direct) {
+    int64_t split_stride, int direct, int* __restrict__ nonfinite) {
   constexpr int XP = KST + 8;  // padded LDS row (bfloat16)
   constexpr int NS = KST / 16;  // MFMA K-steps per stage
   constexpr int XQ = KST / 32;  // 16-byte X chunks per thread per plane
@@ -327,6 +327,7 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
 
   const double alpha = (direct && alpha_ptr != nullptr) ? *alpha_ptr : 1.0;
   float* __restrict__ Zs = Z + (direct ? 0 : (int64_t)sk * split_stride);
+  bool bad = false;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int c = c0 + 32 * t + li;
@@ -335,9 +336,15 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t r = r0 + 8 * (v >> 2) + 4 * g + (v & 3);
-      if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * ((double)acc2[t][v] - cr)) : acc2[t][v];
+      const float o = direct ? (float)(alpha * ((double)acc2[t][v] - cr)) : acc2[t][v];
+      if (r < m) {
+        Zs[r * ldz + c] = o;
+        bad = bad || !isfinite(o);
+      }
     }
   }
+  // optional check of the direct output: a non-finite entry sets *nonfinite
+  if (nonfinite != nullptr && bad) atomicOr(nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,13 +708,15 @@ hipError_t launch_fwd_x6(const FwdArgs& a, hipStream_t st) {
   float* out = direct ? a.Z : a.P;
   const int64_t ldo = direct ? a.ldz : a.ldp;
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
+  int* nf = direct ? a.nonfinite : nullptr;
   if (a.vec)
     hipLaunchKernelGGL((fwd_x6_kernel<true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift, a.X3,
-                       a.ldxs3, a.xplane3, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
+                       a.ldxs3, a.xplane3, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0,
+                       nf);
   else
     hipLaunchKernelGGL((fwd_x6_kernel<false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
                        a.X3, a.ldxs3, a.xplane3, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride,
-                       direct ? 1 : 0);
+                       direct ? 1 : 0, nf);
   hipError_t e = hipGetLastError();
   if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
   if (e != hipSuccess || direct) return e;

@@ -216,6 +216,9 @@ struct rpca_plan_s {
     int Rp = 0;                                      // R rounded up to 4 (zero padding)
     float *P32 = nullptr, *Y32 = nullptr;            // m x Rp, n x Rp: float32 factors of dA
     float* zshift = nullptr;                         // Rp zeros (no shift in the dA product)
+    uint16_t* Y3 = nullptr;                          // Y32 split into three bfloat16 planes
+    int64_t ldy3 = 0, yplane3 = 0;                   // (cpady x ldy3 each, yplane3 elements apart)
+    int cpady = 0;
   } bw;
   rpca_stats stats{};
   std::vector<EventPair> ev_fwd, ev_adj;
@@ -1733,6 +1736,10 @@ rpca_status backward_alloc(rpca_plan_s* plan) {
   BALLOC(P32, m * b.Rp);
   BALLOC(Y32, plan->n * b.Rp);
   BALLOC(zshift, b.Rp);
+  b.ldy3 = round_up(b.Rp + 64, 32);  // the split forward reads a tail stage of up to 64 K
+  b.cpady = (int)round_up(plan->n, 64);
+  b.yplane3 = (int64_t)b.cpady * b.ldy3;
+  BALLOC(Y3, 3 * b.yplane3);
 #undef BALLOC
   // the K padding of the float32 factors and the shift stay zero
   if (hipMemset(b.P32, 0, sizeof(float) * (size_t)(m * b.Rp)) != hipSuccess ||
@@ -1903,9 +1910,12 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   RPCA_TRY(launch_widen(plan->X, ldx, L, n, b.Yt + (int64_t)L * ldx, ldx, st));
   if (i > 0) RPCA_TRY(launch_widen(b.Xbar, ldx, i * l, n, b.Yt + (int64_t)2 * L * ldx, ldx, st));
   if (center) RPCA_TRY(launch_center_f64(b.Pm, ldp, m, R, plan->rps_cs, plan->ns_cs, b.ppart, st));
-  // dA = P Y^T on the float32 matrix cores: P (m x R) and Y = (Y^T)^T (n x R) rounded to float32
+  // dA = P Y^T: P (m x R) and Y = (Y^T)^T (n x R) rounded to float32, the product as the sum
+  // of the six bfloat16 products of order <= 2 of their three-part splits (float32-level
+  // products on the bfloat16 matrix cores, float32 accumulation over K = R)
   RPCA_TRY(launch_to_f32(b.Pm, m, R, ldp, nullptr, b.P32, b.Rp, st));
   RPCA_TRY(launch_transpose_out(b.Yt, ldx, R, (int)n, b.Y32, nullptr, b.Rp, st));
+  RPCA_TRY(launch_split3_x(b.Y32, b.Rp, b.Rp, (int)n, b.cpady, b.Y3, b.ldy3, b.yplane3, st));
   {
     FwdArgs fa;
     fa.A = b.P32;
@@ -1913,18 +1923,19 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
     fa.m = m;
     fa.n = b.Rp;
     fa.shift = b.zshift;
-    fa.Xt = b.Y32;
-    fa.ldx = b.Rp;
     fa.ncols = (int)n;
     fa.Z = dA;
     fa.ldz = ldda;
     fa.vec = true;
-    RPCA_TRY(launch_fwd_f32(fa, st));
+    fa.X3 = b.Y3;
+    fa.ldxs3 = b.ldy3;
+    fa.xplane3 = b.yplane3;
+    // a derivative that is not defined at this A (tied leading S~, or a Step 2 factor that is
+    // singular to working precision) shows as non-finite entries, flagged as they are written
+    RPCA_TRY(hipMemsetAsync(plan->flags + 4, 0, sizeof(int), st));
+    fa.nonfinite = plan->flags + 4;
+    RPCA_TRY(launch_fwd_x6(fa, st));
   }
-  // a derivative that is not defined at this A (tied leading S~, or a Step 2 factor that is
-  // singular to working precision) shows as non-finite entries
-  RPCA_TRY(hipMemsetAsync(plan->flags + 4, 0, sizeof(int), st));
-  RPCA_TRY(launch_check_finite_f32(dA, m, n, ldda, plan->flags + 4, st));
   int bad = 0;
   RPCA_TRY(hipMemcpyAsync(&bad, plan->flags + 4, sizeof(int), hipMemcpyDeviceToHost, st));
   RPCA_TRY(hipStreamSynchronize(st));

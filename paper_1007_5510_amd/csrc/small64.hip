@@ -680,7 +680,8 @@ constexpr int CBG_MAXNB = 64;
 
 bool chol_blkg_fits(int L) { return L >= 1 && L <= CB * CBG_MAXNB; }
 
-template <bool CHOL>
+// RB: block rows per wave in the inverse (NB <= 16 RB)
+template <bool CHOL, int RB>
 __global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W, int L, double rel_tol,
                                                          int* __restrict__ flag, double* __restrict__ Rinv) {
   __shared__ double d0[CB * CBG_MAXNB];
@@ -754,28 +755,50 @@ __global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W,
         for (int t = 0; t < CB; ++t) wc[t * L] = x[t];
       }
       __syncthreads();
-      // trailing upper blocks (jb, lb), kb < jb <= lb
+      // trailing upper blocks (jb, lb), kb < jb <= lb; two tiles per wave at a time, so
+      // their operand loads are in flight together
       const int nrem = NB - kb - 1;
       const int ntile = nrem * (nrem + 1) / 2;
-      for (int q = wave; q < ntile; q += 16) {
-        int rem = q, jb = kb + 1;
+      auto tile_of = [&](int q, int& jb, int& lb) {
+        int rem = q;
+        jb = kb + 1;
         while (rem >= NB - jb) {
           rem -= NB - jb;
           ++jb;
         }
-        const int lb = jb + rem;
-        const int j0 = jb * CB, l0 = lb * CB;
-        doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+        lb = jb + rem;
+      };
+      for (int q = wave; q < ntile; q += 32) {
+        const bool two = q + 16 < ntile;
+        int jb0, lb0, jb1 = kb + 1, lb1 = kb + 1;
+        tile_of(q, jb0, lb0);
+        if (two) tile_of(q + 16, jb1, lb1);
+        double a0[4], b0[4], a1[4], b1[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const double a = get(W, k0 + 4 * s + g, j0 + c16);
-          const double b = get(W, k0 + 4 * s + g, l0 + c16);
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          a0[s] = get(W, k0 + 4 * s + g, jb0 * CB + c16);
+          b0[s] = get(W, k0 + 4 * s + g, lb0 * CB + c16);
+          a1[s] = two ? get(W, k0 + 4 * s + g, jb1 * CB + c16) : 0.0;
+          b1[s] = two ? get(W, k0 + 4 * s + g, lb1 * CB + c16) : 0.0;
+        }
+        doublex4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], acc1, 0, 0, 0);
+        }
+        double c0[4], c1[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          c0[v] = get(W, jb0 * CB + 4 * v + g, lb0 * CB + c16);
+          c1[v] = two ? get(W, jb1 * CB + 4 * v + g, lb1 * CB + c16) : 0.0;
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = j0 + 4 * v + g, col = l0 + c16;
-          if (jb < lb || col >= row) put(W, row, col, get(W, row, col) - acc[v]);
+          const int row0 = jb0 * CB + 4 * v + g, col0 = lb0 * CB + c16;
+          if (jb0 < lb0 || col0 >= row0) put(W, row0, col0, c0[v] - acc0[v]);
+          const int row1 = jb1 * CB + 4 * v + g, col1 = lb1 * CB + c16;
+          if (two && (jb1 < lb1 || col1 >= row1)) put(W, row1, col1, c1[v] - acc1[v]);
         }
       }
       __syncthreads();
@@ -808,9 +831,9 @@ __global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W,
     }
     __syncthreads();
     // Y_w = R_wj X_jj for block rows w < jb (w = wave + 16 r)
-    doublex4 acc[CBG_MAXNB / 16];
+    doublex4 acc[RB];
 #pragma unroll
-    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+    for (int r = 0; r < RB; ++r) {
       acc[r] = doublex4{0.0, 0.0, 0.0, 0.0};
       const int w = wave + 16 * r;
       if (w < jb) {
@@ -824,7 +847,7 @@ __global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W,
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+    for (int r = 0; r < RB; ++r) {
       const int w = wave + 16 * r;
       if (w < jb) {
 #pragma unroll
@@ -834,12 +857,25 @@ __global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W,
     __syncthreads();
     // X_ij = -sum_{k = i}^{jb-1} X_ik Y_k for block rows i < jb
 #pragma unroll
-    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+    for (int r = 0; r < RB; ++r) {
       acc[r] = doublex4{0.0, 0.0, 0.0, 0.0};
       const int w = wave + 16 * r;
       if (w < jb) {
         const int row = CB * w + c16;
-        for (int kb = w; kb < jb; ++kb) {
+        // two block columns at a time (their loads in flight together), then the odd one
+        int kb = w;
+        for (; kb + 1 < jb; kb += 2) {
+          double a[8], b[8];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const int col = CB * kb + 4 * s + g;
+            a[s] = col >= row ? get(X, row, col) : 0.0;
+            b[s] = get(X, CB * kb + 4 * s + g, j0 + c16);
+          }
+#pragma unroll
+          for (int s = 0; s < 8; ++s) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc[r], 0, 0, 0);
+        }
+        if (kb < jb) {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const int col = CB * kb + 4 * s + g;
@@ -852,7 +888,7 @@ __global__ __launch_bounds__(1024) void chol_blkg_kernel(double* __restrict__ W,
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < CBG_MAXNB / 16; ++r) {
+    for (int r = 0; r < RB; ++r) {
       const int w = wave + 16 * r;
       if (w < jb) {
 #pragma unroll
@@ -881,7 +917,10 @@ hipError_t launch_cholinv(double* W, int L, double rel_tol, int* flag, double* R
     return hipGetLastError();
   }
   if (chol_blkg_fits(L)) {
-    hipLaunchKernelGGL((chol_blkg_kernel<true>), dim3(1), dim3(1024), 0, st, W, L, rel_tol, flag, Rinv);
+    if (L <= 32 * CB)
+      hipLaunchKernelGGL((chol_blkg_kernel<true, 2>), dim3(1), dim3(1024), 0, st, W, L, rel_tol, flag, Rinv);
+    else
+      hipLaunchKernelGGL((chol_blkg_kernel<true, 4>), dim3(1), dim3(1024), 0, st, W, L, rel_tol, flag, Rinv);
     return hipGetLastError();
   }
   if (!cholinv_fits(L)) return hipErrorInvalidValue;
@@ -899,8 +938,12 @@ hipError_t launch_triinv(const double* R, int L, double* Rinv, hipStream_t st) {
     return hipGetLastError();
   }
   if (chol_blkg_fits(L)) {
-    hipLaunchKernelGGL((chol_blkg_kernel<false>), dim3(1), dim3(1024), 0, st, const_cast<double*>(R), L, 0.0, nullptr,
-                       Rinv);
+    if (L <= 32 * CB)
+      hipLaunchKernelGGL((chol_blkg_kernel<false, 2>), dim3(1), dim3(1024), 0, st, const_cast<double*>(R), L, 0.0,
+                         nullptr, Rinv);
+    else
+      hipLaunchKernelGGL((chol_blkg_kernel<false, 4>), dim3(1), dim3(1024), 0, st, const_cast<double*>(R), L, 0.0,
+                         nullptr, Rinv);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(triinv_kernel, dim3(1), dim3(1024), (size_t)L * sizeof(double), st, R, L, Rinv);

@@ -159,8 +159,11 @@ EigWork eig_layout(double* work, int L, int kk) {
 }
 
 // ---- 1. Householder tridiagonalisation, one workgroup
-// NQ >= ceil(L / 64) rows per lane for a whole column.
-template <bool IN_LDS, int NQ>
+// NQ >= ceil(L / 64) rows per lane for a whole column.  With COLMV (matrix in global memory)
+// the symmetric product runs by columns: one wave per packed column, read once and
+// contiguously, feeding both the column's dot product with v and its axpy into a
+// wave-private partial p (TRD_WAVES x L doubles of LDS); the partials are then summed.
+template <bool IN_LDS, int NQ, bool COLMV = false>
 __global__ __launch_bounds__(TRD_THREADS) void tridiag_kernel(const double* __restrict__ M, int L,
                                                               double* __restrict__ gP, double* __restrict__ dg,
                                                               double* __restrict__ eg, double* __restrict__ taug) {
@@ -196,25 +199,53 @@ __global__ __launch_bounds__(TRD_THREADS) void tridiag_kernel(const double* __re
     const int r0 = j + 1, nr = L - r0;
     const bool next = j + 3 < L;  // reflector j+1 is still needed
     if (tj != 0.0) {
-      // p[t] = tj sum_c A(t, c) v[c] over c >= r0; 16 lanes per t
-      const int g = lane >> 4, u0 = lane & 15;
       double ptv = 0.0;
-      for (int tb = r0 + 4 * wave; tb < L; tb += 4 * TRD_WAVES) {
-        const int t = tb + g;
-        double s = 0.0;
-        if (t < L) {
-          const int ot = poff(t, L) - t;
-          for (int u = u0; u < nr; u += 16) {
-            const int c = r0 + u;
-            const double a = c <= t ? P[poff(c, L) + t - c] : P[ot + c];
-            s = fma(a, v[c], s);
+      if (COLMV) {
+        // column c (rows c .. L-1 contiguous) adds A(i, c) v[c] to yw[i], i >= c, and its dot
+        // with v below the diagonal to yw[c]; each wave owns its yw
+        double* yw = p + L + wave * L;
+        for (int i = r0 + lane; i < L; i += 64) yw[i] = 0.0;
+        for (int c = r0 + wave; c < L; c += TRD_WAVES) {
+          const int oc = poff(c, L) - c;
+          const double vc = v[c];
+          double d = 0.0;
+          for (int i = c + lane; i < L; i += 64) {
+            const double a = P[oc + i];
+            yw[i] = fma(a, vc, yw[i]);
+            if (i > c) d = fma(a, v[i], d);
           }
+          d = wave_sum64(d);
+          if (lane == 0) yw[c] += d;
         }
-        s = row_sum16(s);
-        if (u0 == 0 && t < L) {
+        __syncthreads();
+        for (int t = r0 + tid; t < L; t += TRD_THREADS) {
+          double s = 0.0;
+#pragma unroll
+          for (int w = 0; w < TRD_WAVES; ++w) s += p[L + w * L + t];
           const double pt = tj * s;
           p[t] = pt;
           ptv = fma(pt, v[t], ptv);
+        }
+      } else {
+        // p[t] = tj sum_c A(t, c) v[c] over c >= r0; 16 lanes per t
+        const int g = lane >> 4, u0 = lane & 15;
+        for (int tb = r0 + 4 * wave; tb < L; tb += 4 * TRD_WAVES) {
+          const int t = tb + g;
+          double s = 0.0;
+          if (t < L) {
+            const int ot = poff(t, L) - t;
+            for (int u = u0; u < nr; u += 16) {
+              const int c = r0 + u;
+              const double a = c <= t ? P[poff(c, L) + t - c] : P[ot + c];
+              s = fma(a, v[c], s);
+            }
+          }
+          s = row_sum16(s);
+          if (u0 == 0 && t < L) {
+            const double pt = tj * s;
+            p[t] = pt;
+            ptv = fma(pt, v[t], ptv);
+          }
         }
       }
       ptv = wave_sum64(ptv);
@@ -501,6 +532,9 @@ hipError_t launch_syev_small(const double* M, int L, int kk, double* work, doubl
   if (L <= 256 && trd_lds <= max_lds)
     hipLaunchKernelGGL((tridiag_kernel<true, 4>), dim3(1), dim3(TRD_THREADS), trd_lds, st, M, L, w.P, w.d, w.e,
                        w.tau);
+  else if ((32 + (3 + (size_t)TRD_WAVES) * L) * sizeof(double) <= max_lds)
+    hipLaunchKernelGGL((tridiag_kernel<false, 16, true>), dim3(1), dim3(TRD_THREADS),
+                       (32 + (3 + (size_t)TRD_WAVES) * L) * sizeof(double), st, M, L, w.P, w.d, w.e, w.tau);
   else
     hipLaunchKernelGGL((tridiag_kernel<false, 16>), dim3(1), dim3(TRD_THREADS), (32 + 3 * (size_t)L) * sizeof(double),
                        st, M, L, w.P, w.d, w.e, w.tau);

@@ -131,6 +131,31 @@ def test_backward_requires_state():
     assert rc == 8  # RPCA_ERR_NO_STATE
 
 
+def test_backward_flags_a_nonfinite_derivative():
+    """A cotangent with a NaN makes dA non-finite: rpca_backward reports NONFINITE (the check
+    runs in the epilogue of the dense dA product), and the same plan then gives the finite
+    dA of clean cotangents again."""
+    _need_gpu()
+    from paper_1007_5510_amd import rpca, _lib
+    m, n, k, l, i = 3000, 500, 6, 10, 1
+    sigma = 0.9 ** np.arange(n, dtype=np.float64)
+    A = F.svd_problem(8100, m, n, sigma)["A"]
+    G = F.gaussian_G(8100, n, l)
+    gS, gU, gV = _cotangents(8100, m, n, k)
+    p = rpca.Plan(m, n, k, l, i, flags=_lib.FLAG_KEEP_STATE)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    Ad = t(A)  # the reverse sweep reads A again: it must stay allocated
+    p.factor(Ad, G=t(G))
+    bad = gS.copy()
+    bad[1] = np.nan
+    with pytest.raises(_lib.RPCAError) as e:
+        p.backward(gS=t(bad), gU=t(gU), gV=t(gV))
+    assert e.value.code == 6  # RPCA_ERR_NONFINITE
+    dA = p.backward(gS=t(gS), gU=t(gU), gV=t(gV))
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(dA).all())
+
+
 def test_backward_full_size_fd():
     """The differentiation workload at full size: 50000 x 8000, sigma_j = 2 * 0.95^(j-1), k=16, l=24,
     i=2; loss = sum w_j sigma_j + <G_U, U> + <G_V, V>.  The spectrum is built to rank 400

@@ -314,9 +314,10 @@ def test_householder_step2_wide(m, n, k, l, i):
     (12000, 1500, 40, 128, 1, 0.998, (0,)),    # L = 256: Cholesky QR twice, factor in global memory
     (6000, 1200, 100, 120, 2, 0.995, (0,)),    # L = 360, the width of the streamed workload
     (6000, 1200, 100, 120, 2, 0.97, (1, 2)),   # L = 360, ill-conditioned H: shifted rounds
+    (8000, 2000, 100, 200, 2, 0.999, (0,)),    # L = 600: four block rows per wave in the inverse
 ])
 def test_cholesky_qr_wide(m, n, k, l, i, decay, levels):
-    """Cholesky QR (Step 2, Section 3) up to L = 360, where the Gram factor and its inverse run
+    """Cholesky QR (Step 2, Section 3) up to L = 600, where the Gram factor and its inverse run
     blocked in global memory (the packed triangle no longer fits in LDS): the plain rounds for a
     well-conditioned H, the shifted rounds for an ill-conditioned one; parity with the oracle's
     pivoted QR route and an orthonormal Q."""
