@@ -17,13 +17,15 @@
 namespace rpca {
 
 // ---------------------------------------------------------------- X^T Y over a row split
-// part[s][a][b] = sum_{r in split s} X[r][a] Y[r][b],  a < na, b < nb (64 x 64 tiles)
+// part[s][a][b] = sum_{r in split s} X[r][a] Y[r][b],  a < na, b < nb (64 x 64 tiles).  Rows are
+// staged 16 at a time in LDS (two buffers); the next 16 rows are loaded to registers (from
+// clamped addresses, zeroed when stored) while the current ones are multiplied.
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void xty_kernel(const TX* __restrict__ X, int64_t ldx, int na,
                                                   const TY* __restrict__ Y, int64_t ldy, int nb, int64_t rows,
                                                   int64_t rps, int tb, double* __restrict__ part) {
-  __shared__ double XI[16][65];
-  __shared__ double YJ[16][65];
+  __shared__ double XI[2][16][65];
+  __shared__ double YJ[2][16][65];
   const int ti = blockIdx.x / tb, tj = blockIdx.x % tb;
   const int s = blockIdx.y;
   const int I0 = ti * 64, J0 = tj * 64;
@@ -35,28 +37,52 @@ __global__ __launch_bounds__(256) void xty_kernel(const TX* __restrict__ X, int6
     for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
   const int64_t rb = (int64_t)s * rps;
   const int64_t re = rb + rps < rows ? rb + rps : rows;
-  for (int64_t r0 = rb; r0 < re; r0 += 16) {
-    for (int e = threadIdx.x; e < 1024; e += 256) {
-      const int rr = e >> 6, cc = e & 63;
-      const int64_t r = r0 + rr;
-      const bool rok = r < re;
-      XI[rr][cc] = (rok && I0 + cc < na) ? (double)X[r * ldx + I0 + cc] : 0.0;
-      YJ[rr][cc] = (rok && J0 + cc < nb) ? (double)Y[r * ldy + J0 + cc] : 0.0;
+  // staging: element q of this thread is row (tid + 256 q) / 64, column (tid + 256 q) % 64
+  const int cc = threadIdx.x & 63, rq = threadIdx.x >> 6;
+  const int xc = I0 + cc < na ? I0 + cc : na - 1, yc = J0 + cc < nb ? J0 + cc : nb - 1;
+  TX px[4];
+  TY py[4];
+  auto load = [&](int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + rq + 4 * q < re ? r0 + rq + 4 * q : re - 1;
+      px[q] = X[r * ldx + xc];
+      py[q] = Y[r * ldy + yc];
     }
-    __syncthreads();
+  };
+  auto store = [&](int buf, int64_t r0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool rok = r0 + rq + 4 * q < re;
+      XI[buf][rq + 4 * q][cc] = (rok && I0 + cc < na) ? (double)px[q] : 0.0;
+      YJ[buf][rq + 4 * q][cc] = (rok && J0 + cc < nb) ? (double)py[q] : 0.0;
+    }
+  };
+  if (rb < re) {
+    load(rb);
+    store(0, rb);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t r0 = rb; r0 < re; r0 += 16) {
+    const bool more = r0 + 16 < re;
+    if (more) load(r0 + 16);
 #pragma unroll 4
     for (int rr = 0; rr < 16; ++rr) {
       double xi[4], yj[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) xi[a] = XI[rr][ty + 16 * a];
+      for (int a = 0; a < 4; ++a) xi[a] = XI[buf][rr][ty + 16 * a];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) yj[b] = YJ[rr][tx + 16 * b];
+      for (int b = 0; b < 4; ++b) yj[b] = YJ[buf][rr][tx + 16 * b];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = fma(xi[a], yj[b], acc[a][b]);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store(buf ^ 1, r0 + 16);
     __syncthreads();
+    buf ^= 1;
   }
   double* out = part + (int64_t)s * na * nb;
 #pragma unroll
@@ -68,16 +94,26 @@ __global__ __launch_bounds__(256) void xty_kernel(const TX* __restrict__ X, int6
     }
 }
 
-// out[a][b] = colscale[b] * sum_s part[s][a][b]
-__global__ void xty_reduce_kernel(const double* __restrict__ part, int nsplit, int na, int nb,
-                                  const double* __restrict__ colscale, double* __restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// out[a][b] = colscale[b] * sum_s part[s][a][b]: a block takes 16 entries, its 16 groups of 16
+// threads sum every 16th split, and the group sums are combined in a fixed order
+__global__ __launch_bounds__(256) void xty_reduce_kernel(const double* __restrict__ part, int nsplit, int na, int nb,
+                                                         const double* __restrict__ colscale,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[16][16];
+  const int t = threadIdx.x & 15, grp = threadIdx.x >> 4;
   const int64_t cnt = (int64_t)na * nb;
-  if (e >= cnt) return;
+  const int64_t e = (int64_t)blockIdx.x * 16 + t;
   double v = 0.0;
-  for (int s = 0; s < nsplit; ++s) v += part[(int64_t)s * cnt + e];
-  if (colscale != nullptr) v *= colscale[e % nb];
-  out[e] = v;
+  if (e < cnt)
+    for (int s = grp; s < nsplit; s += 16) v += part[(int64_t)s * cnt + e];
+  sh[grp][t] = v;
+  __syncthreads();
+  if (grp != 0 || e >= cnt) return;
+  double tot = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tot += sh[q][t];
+  if (colscale != nullptr) tot *= colscale[e % nb];
+  out[e] = tot;
 }
 
 hipError_t launch_xty(bool x64, const void* X, int64_t ldx, int na, bool y64, const void* Y, int64_t ldy, int nb,
@@ -101,7 +137,7 @@ hipError_t launch_xty(bool x64, const void* X, int64_t ldx, int na, bool y64, co
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t cnt = (int64_t)na * nb;
-  hipLaunchKernelGGL(xty_reduce_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, part, nsplit, na, nb,
+  hipLaunchKernelGGL(xty_reduce_kernel, dim3((unsigned)((cnt + 15) / 16)), dim3(256), 0, st, part, nsplit, na, nb,
                      colscale, out);
   return hipGetLastError();
 }

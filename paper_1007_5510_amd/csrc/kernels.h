@@ -37,8 +37,6 @@ struct FwdArgs {              // Z = alpha ((A - 1 s^T) Xt^T - 1 corr^T)
   // (cpad x ldxs3 each, xplane3 elements apart)
   const uint16_t* X3 = nullptr;
   int64_t ldxs3 = 0, xplane3 = 0;
-  // split products with a single K split: set to 1 when an output entry is not finite
-  int* nonfinite = nullptr;
 };
 
 struct AdjArgs {              // P_s = ((A_s - 1 s^T)^T Z_s)^T, s = 0..nsplit-1
@@ -118,6 +116,16 @@ hipError_t launch_split3_x(const float* Xt, int64_t ldx, int64_t n, int ncols, i
 hipError_t launch_split3_zt(const float* Z, int64_t ldz, int64_t m, int ncols, bool ones, int cpad, uint16_t* Zp,
                             int64_t ldzs, int64_t plane, hipStream_t st);
 hipError_t launch_fwd_x6(const FwdArgs& a, hipStream_t st);
+// three-part bfloat16 split of X (rows x cols) in the K-step-major layout of the rank-K product:
+// part q of X[r][k] at ((3 (k / 16) + q) rows_pad + r) 16 + k % 16, zero for r < rows_pad, k < kp
+// outside X; Xp holds 3 rows_pad kp entries
+hipError_t launch_split3_rows(const float* X, int64_t ldx, int64_t rows, int cols, int64_t rows_pad, int kp,
+                              uint16_t* Xp, hipStream_t st);
+// O = P Y^T (m x n, ld ldo) from the split of P (rows_pad = mpad, m rounded up to 256) and of Y
+// (rows_pad = npad >= n rounded up to 256), kp a multiple of 32; *nonfinite |= 1 when an entry of
+// O is not finite
+hipError_t launch_outer_x6(const uint16_t* Pp, int64_t mpad, const uint16_t* Yp, int64_t npad, int kp, int64_t m,
+                           int64_t n, float* O, int64_t ldo, int* nonfinite, hipStream_t st);
 // 65 to 192 output columns (with rows_per_split % 32 == 0 and planes at least that wide) go to the
 // one-read wide kernel, others to 64-column tiles
 hipError_t launch_adj_x6(const AdjArgs& a, hipStream_t st);

@@ -24,6 +24,8 @@
 // In the adjoint the roles are swapped (A operand = Z^T, B operand = A), so the
 // output lanes run along the columns of A and its partial-sum rows are written
 // with consecutive lanes at consecutive addresses.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
     const float* __restrict__ A, int64_t lda, int64_t m, int64_t n, const float* __restrict__ shift,
     const uint16_t* __restrict__ Xp, int64_t ldxs, int64_t xplane, int ncols, int64_t kchunk,
     const float* __restrict__ corr, const double* __restrict__ alpha_ptr, float* __restrict__ Z, int64_t ldz,
-    int64_t split_stride, int direct, int* __restrict__ nonfinite) {
+    int64_t split_stride, int direct) {
   constexpr int XP = KST + 8;  // padded LDS row (bfloat16)
   constexpr int NS = KST / 16;  // MFMA K-steps per stage
   constexpr int XQ = KST / 32;  // 16-byte X chunks per thread per plane
@@ -327,7 +329,6 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
 
   const double alpha = (direct && alpha_ptr != nullptr) ? *alpha_ptr : 1.0;
   float* __restrict__ Zs = Z + (direct ? 0 : (int64_t)sk * split_stride);
-  bool bad = false;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int c = c0 + 32 * t + li;
@@ -336,15 +337,9 @@ __global__ __launch_bounds__(256, MINB) void fwd_x6_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t r = r0 + 8 * (v >> 2) + 4 * g + (v & 3);
-      const float o = direct ? (float)(alpha * ((double)acc2[t][v] - cr)) : acc2[t][v];
-      if (r < m) {
-        Zs[r * ldz + c] = o;
-        bad = bad || !isfinite(o);
-      }
+      if (r < m) Zs[r * ldz + c] = direct ? (float)(alpha * ((double)acc2[t][v] - cr)) : acc2[t][v];
     }
   }
-  // optional check of the direct output: a non-finite entry sets *nonfinite
-  if (nonfinite != nullptr && bad) atomicOr(nonfinite, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,6 +670,204 @@ __global__ __launch_bounds__(512, 1) void adj_x6w_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// rank-K product with a wide output, O = P Y^T (the dense derivative of the
+// reverse sweep): O[r][c] = sum over k < kp of P[r][k] Y[c][k], from the three
+// bfloat16 parts of P and of Y, each held K-step-major: the 16 entries of K-step
+// s, part q of row r are contiguous at ((3 s + q) rows_pad + r) 16, so the rows of
+// a tile for one K-step and part are one contiguous run.  Both are padded with
+// zeros to whole 256-row tiles and to kp, a multiple of 32.  A block of 8 waves
+// computes 256 x 256 tiles of O, a wave 64 x 128 (two by four 32 x 32 tiles, six
+// products each per K-step of 16).  The parts of a K-step go from global memory
+// straight into LDS (no registers) through a ring of three stages, so two
+// K-steps are in flight while one is multiplied.  The blocks are persistent,
+// one per compute unit: each XCD takes one eighth of the column tiles and its
+// blocks walk them row tile by row tile, so its slice of Y stays in its L2 while
+// P streams through, and the copies of a block's next tile overlap the last
+// K-steps and the stores of the one before.  O is written with non-temporal
+// stores, and any non-finite entry sets the flag.
+// ---------------------------------------------------------------------------
+constexpr int OX_T = 256;  // tile rows and columns
+
+// Xp in the K-step-major layout above: part q of X[r][k] for r < rows, k < cols; zero for
+// r < rows_pad, k < kp otherwise.  Thread: one pair of entries (row r, K-step s, pair j).
+__global__ __launch_bounds__(256) void split3_rows_kernel(const float* __restrict__ X, int64_t ldx, int64_t rows,
+                                                          int cols, int64_t rows_pad, int kp,
+                                                          uint16_t* __restrict__ Xp) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j = (int)(e & 7);
+  const int64_t sr = e >> 3;  // s * rows_pad + r
+  const int64_t s = sr / rows_pad, r = sr - s * rows_pad;
+  if (s >= kp / 16) return;
+  const int k = 16 * (int)s + 2 * j;
+  float a = 0.f, b = 0.f;
+  if (r < rows) {
+    const float* __restrict__ x = X + r * ldx;
+    if (k < cols) a = x[k];
+    if (k + 1 < cols) b = x[k + 1];
+  }
+  const X6Parts q = x6_split(a, b);
+  const int64_t panel = rows_pad * 16;
+  uint32_t* o = reinterpret_cast<uint32_t*>(Xp + 3 * s * panel + r * 16 + 2 * j);
+  o[0] = q.h;
+  o[panel / 2] = q.m;
+  o[panel] = q.l;
+}
+
+typedef __attribute__((address_space(3))) void* ox_lds_ptr_t;
+typedef const __attribute__((address_space(1))) void* ox_gbl_ptr_t;
+
+// s_waitcnt immediate (gfx9 encoding): vmcnt <= vm, lgkmcnt and expcnt not waited
+constexpr int ox_vmcnt(int vm) { return (vm & 15) | ((vm >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+constexpr int OX_CHUNK = 8192;             // one K-step, one part of a 256-row tile (bytes)
+constexpr int OX_STAGE = 6 * OX_CHUNK;     // P parts 0..2, then Y parts 0..2
+constexpr int OX_DX = 3;                   // ring stages (two K-steps in flight)
+constexpr int OX_BPX = 32;                 // persistent blocks per XCD (one per compute unit)
+
+// LDS slot of the 16-byte half h of tile row r (32-byte rows): the halves of rows r and
+// r + 4 (which share banks modulo 128 bytes) and of rows r and r + 8 (modulo 256 bytes)
+// are swapped relative to each other, so the 16-byte reads of 8 or 16 consecutive rows
+// by consecutive lanes hit distinct banks
+RPCA_DEV int ox_slot(int r, int h) { return 2 * r + (h ^ (((r >> 2) ^ (r >> 3)) & 1)); }
+
+__global__ __launch_bounds__(512, 1) void outer_x6_kernel(const uint16_t* __restrict__ Pp, int64_t mpad,
+                                                          const uint16_t* __restrict__ Yp, int64_t npad, int kp,
+                                                          int64_t m, int64_t n, int nbr, int nbc, int cg,
+                                                          float* __restrict__ O, int64_t ldo,
+                                                          int* __restrict__ nonfinite) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[OX_DX * OX_STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 31, g = lane >> 5;
+  // tiles of this block: XCD x owns the column tiles [x cg, x cg + cnt) of every row tile,
+  // numbered row-major; the B blocks on it take every B-th of them
+  const int x = (int)(blockIdx.x & 7), lb = (int)(blockIdx.x >> 3), B = (int)(gridDim.x >> 3);
+  const int cnt = nbc - x * cg < cg ? nbc - x * cg : cg;
+  if (cnt <= 0 || (int64_t)lb >= (int64_t)nbr * cnt) return;
+  const int nmine = (int)(((int64_t)nbr * cnt - lb + B - 1) / B);
+  const int nst = kp / 16;
+  const int F = nmine * nst;  // K-steps of all this block's tiles, in order
+  auto origin = [&](int j, int64_t& r0, int64_t& c0) {
+    const int64_t idx = lb + (int64_t)j * B;
+    r0 = (idx / cnt) * OX_T;
+    c0 = ((int64_t)x * cg + idx % cnt) * OX_T;
+  };
+  // global -> LDS copies (global_load_lds_dwordx4: lane l's 16 bytes land at the wave's
+  // base + 16 l): thread tid fills slot tid of each chunk, i.e. row dr, half dh
+  const int dr = tid >> 1, dh = (tid & 1) ^ (((dr >> 2) ^ (dr >> 3)) & 1);
+  const unsigned char* __restrict__ pbase = reinterpret_cast<const unsigned char*>(Pp + dr * 16 + 8 * dh);
+  const unsigned char* __restrict__ ybase = reinterpret_cast<const unsigned char*>(Yp + dr * 16 + 8 * dh);
+  const int64_t pkb = mpad * 32, ykb = npad * 32;  // bytes per K-step and part
+  auto issue = [&](int f) {
+    f = f < F ? f : F - 1;  // past the last K-step: re-read it into a slot no longer read
+    const int j = f / nst, ks = f - j * nst;
+    int64_t r0, c0;
+    origin(j, r0, c0);
+    const unsigned char* ps = pbase + r0 * 32 + (int64_t)(3 * ks) * pkb;
+    const unsigned char* ys = ybase + c0 * 32 + (int64_t)(3 * ks) * ykb;
+    unsigned char* st = lds + (f % OX_DX) * OX_STAGE + wave * 1024;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      __builtin_amdgcn_global_load_lds((ox_gbl_ptr_t)(ps + q * pkb), (ox_lds_ptr_t)(st + q * OX_CHUNK), 16, 0, 0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      __builtin_amdgcn_global_load_lds((ox_gbl_ptr_t)(ys + q * ykb), (ox_lds_ptr_t)(st + (3 + q) * OX_CHUNK), 16, 0,
+                                       0);
+  };
+  // wave w: rows 64 (w >> 1) .. + 63 (two 32-row tiles) x columns 128 (w & 1) .. + 127 (four)
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 128;
+  const int ao0 = 16 * ox_slot(wr + li, g), ao1 = 16 * ox_slot(wr + 32 + li, g);
+  floatx16 acc[2][4];
+  auto zero = [&]() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+  };
+  zero();
+  auto compute = [&](const unsigned char* st) {
+    x6_u32x4 a0[3], a1[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      a0[q] = *reinterpret_cast<const x6_u32x4*>(st + q * OX_CHUNK + ao0);
+      a1[q] = *reinterpret_cast<const x6_u32x4*>(st + q * OX_CHUNK + ao1);
+    }
+#pragma unroll
+    for (int tc = 0; tc < 4; ++tc) {
+      const int bo = (3 * OX_CHUNK) + 16 * ox_slot(wc + 32 * tc + li, g);
+      x6_u32x4 b[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) b[q] = *reinterpret_cast<const x6_u32x4*>(st + q * OX_CHUNK + bo);
+      // the six products of order <= 2, small terms first, the two row tiles interleaved
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const int i = e < 3 ? 2 - e : (e < 5 ? 4 - e : 0), k = e < 3 ? e : (e < 5 ? e - 3 : 0);
+        acc[0][tc] = x6_mfma(a0[i], b[k], acc[0][tc]);
+        acc[1][tc] = x6_mfma(a1[i], b[k], acc[1][tc]);
+      }
+    }
+  };
+  bool bad = false;
+  auto put = [&](int j) {
+    int64_t r0, c0;
+    origin(j, r0, c0);
+    auto body = [&](auto checked) {
+#pragma unroll
+      for (int tc = 0; tc < 4; ++tc) {
+        const int64_t c = c0 + wc + 32 * tc + li;
+#pragma unroll
+        for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t r = r0 + wr + 32 * tr + 8 * (v >> 2) + 4 * g + (v & 3);
+            const float o = acc[tr][tc][v];
+            if (!decltype(checked)::value || (r < m && c < n)) {
+              __builtin_nontemporal_store(o, O + r * ldo + c);
+              bad = bad || !isfinite(o);
+            }
+          }
+      }
+    };
+    if (r0 + OX_T <= m && c0 + OX_T <= n)
+      body(std::false_type{});
+    else
+      body(std::true_type{});
+  };
+
+  // ring of OX_DX stages over the block's K-steps f = 0 .. F - 1: K-step f is multiplied
+  // from slot f % OX_DX while K-steps f + 1 .. f + OX_DX - 1 are in flight.  Every iteration
+  // issues exactly 6 copies per wave, so "K-step f has landed" is a counted wait (the
+  // stores of a finished tile are issued before the copies of that iteration, so they are
+  // older than every copy the wait may leave in flight); the barrier after the wait makes
+  // every wave's copies visible and tells that every wave is done with the slot the next
+  // copies overwrite.  No __syncthreads (its fence would wait for every copy in flight).
+#pragma unroll
+  for (int v = 0; v < OX_DX - 1; ++v) issue(v);
+  int ks = 0, j = 0;
+  for (int f = 0; f < F; ++f) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(ox_vmcnt(6 * (OX_DX - 2)));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    if (ks == nst) {  // tile j is complete: write it, start tile j + 1
+      put(j);
+      zero();
+      ks = 0;
+      ++j;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    issue(f + OX_DX - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(lds + (f % OX_DX) * OX_STAGE);
+    ++ks;
+  }
+  put(j);
+  __builtin_amdgcn_s_waitcnt(ox_vmcnt(0));  // no copy in flight at exit
+  if (bad) atomicOr(nonfinite, 1);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_split3_x(const float* Xt, int64_t ldx, int64_t n, int ncols, int cpad, uint16_t* Xp, int64_t ldxs,
@@ -708,15 +901,13 @@ hipError_t launch_fwd_x6(const FwdArgs& a, hipStream_t st) {
   float* out = direct ? a.Z : a.P;
   const int64_t ldo = direct ? a.ldz : a.ldp;
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
-  int* nf = direct ? a.nonfinite : nullptr;
   if (a.vec)
     hipLaunchKernelGGL((fwd_x6_kernel<true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift, a.X3,
-                       a.ldxs3, a.xplane3, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0,
-                       nf);
+                       a.ldxs3, a.xplane3, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
   else
     hipLaunchKernelGGL((fwd_x6_kernel<false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
                        a.X3, a.ldxs3, a.xplane3, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride,
-                       direct ? 1 : 0, nf);
+                       direct ? 1 : 0);
   hipError_t e = hipGetLastError();
   if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
   if (e != hipSuccess || direct) return e;
@@ -759,6 +950,33 @@ hipError_t launch_adj_x6(const AdjArgs& a, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
   return e;
+}
+
+hipError_t launch_split3_rows(const float* X, int64_t ldx, int64_t rows, int cols, int64_t rows_pad, int kp,
+                              uint16_t* Xp, hipStream_t st) {
+  if (rows_pad <= 0) return hipSuccess;
+  if (X == nullptr || Xp == nullptr || kp <= 0 || kp % 16 != 0 || cols > kp || ldx < cols || rows > rows_pad)
+    return hipErrorInvalidValue;
+  const int64_t blocks = (rows_pad * (kp / 16) * 8 + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(split3_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, ldx, rows, cols, rows_pad, kp,
+                     Xp);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer_x6(const uint16_t* Pp, int64_t mpad, const uint16_t* Yp, int64_t npad, int kp, int64_t m,
+                           int64_t n, float* O, int64_t ldo, int* nonfinite, hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (Pp == nullptr || Yp == nullptr || O == nullptr || nonfinite == nullptr || kp < 32 || kp % 32 != 0 || ldo < n)
+    return hipErrorInvalidValue;
+  const int64_t nbr = (m + OX_T - 1) / OX_T, nbc = (n + OX_T - 1) / OX_T;
+  if (mpad != nbr * OX_T || npad < nbc * OX_T) return hipErrorInvalidValue;
+  const int64_t cg = (nbc + 7) / 8;
+  if (nbr * cg * (kp / 16) > 0x7fffffff) return hipErrorInvalidValue;
+  // persistent blocks, one per compute unit (eight XCDs of 32), each walking its XCD's tiles
+  hipLaunchKernelGGL(outer_x6_kernel, dim3(8 * OX_BPX), dim3(512), 0, st, Pp, mpad, Yp, npad, kp, m, n, (int)nbr,
+                     (int)nbc, (int)cg, O, ldo, nonfinite);
+  return hipGetLastError();
 }
 
 }  // namespace rpca

@@ -215,10 +215,12 @@ struct rpca_plan_s {
     double* ppart = nullptr;                         // column-sum partials of P
     int Rp = 0;                                      // R rounded up to 4 (zero padding)
     float *P32 = nullptr, *Y32 = nullptr;            // m x Rp, n x Rp: float32 factors of dA
-    float* zshift = nullptr;                         // Rp zeros (no shift in the dA product)
-    uint16_t* Y3 = nullptr;                          // Y32 split into three bfloat16 planes
-    int64_t ldy3 = 0, yplane3 = 0;                   // (cpady x ldy3 each, yplane3 elements apart)
-    int cpady = 0;
+    uint16_t *P3 = nullptr, *Y3 = nullptr;           // their three-part bfloat16 splits (K-step-major,
+    int kp3 = 0;                                     // kp3 = R rounded up to 32, rows padded to 256:
+    int64_t mpad3 = 0, npad3 = 0;                    // mpad3 and npad3)
+    int ns_x = 1;                                    // row splits of the m-row X^T Y products
+    int64_t rps_x = 0;                               // (short splits: they are latency bound)
+    double* xpart = nullptr;                         // their partials, ns_x x L x L
   } bw;
   rpca_stats stats{};
   std::vector<EventPair> ev_fwd, ev_adj;
@@ -385,7 +387,12 @@ rpca_status rpca_plan(const rpca_desc* desc, void* hip_stream, rpca_plan_t* out)
   }
   choose_rows(m, 4096, 256, &plan->ns_cs, &plan->rps_cs);
   choose_rows(m, 512, 1024, &plan->ns_cn, &plan->rps_cn);
-  choose_rows(m, 512, 256, &plan->ns_g, &plan->rps_g);
+  {
+    // Gram / X^T Y row splits over H and Q: short splits (the products are latency bound), as
+    // many as keep the float64 partial matrices within 64 MB
+    const int64_t cap = std::max<int64_t>(64, std::min<int64_t>(1024, ((int64_t)64 << 20) / (8 * (int64_t)L * L)));
+    choose_rows(m, 128, (int)cap, &plan->ns_g, &plan->rps_g);
+  }
   choose_rows(n, 80, 256, &plan->ns_gt, &plan->rps_gt);
   if (desc->flags & RPCA_FLAG_SPLIT_BF16) {
     // the split products read A in float pairs from device memory
@@ -1735,16 +1742,17 @@ rpca_status backward_alloc(rpca_plan_s* plan) {
   b.Rp = (b.R + 3) / 4 * 4;
   BALLOC(P32, m * b.Rp);
   BALLOC(Y32, plan->n * b.Rp);
-  BALLOC(zshift, b.Rp);
-  b.ldy3 = round_up(b.Rp + 64, 32);  // the split forward reads a tail stage of up to 64 K
-  b.cpady = (int)round_up(plan->n, 64);
-  b.yplane3 = (int64_t)b.cpady * b.ldy3;
-  BALLOC(Y3, 3 * b.yplane3);
+  b.kp3 = (int)round_up(b.R, 32);
+  choose_rows(m, 128, 1024, &b.ns_x, &b.rps_x);
+  BALLOC(xpart, (int64_t)b.ns_x * LL);
+  b.mpad3 = round_up(m, 256);
+  b.npad3 = round_up(plan->n, 256);
+  BALLOC(P3, 3 * b.mpad3 * b.kp3);
+  BALLOC(Y3, 3 * b.npad3 * b.kp3);
 #undef BALLOC
-  // the K padding of the float32 factors and the shift stay zero
+  // the K padding of the float32 factors stays zero
   if (hipMemset(b.P32, 0, sizeof(float) * (size_t)(m * b.Rp)) != hipSuccess ||
-      hipMemset(b.Y32, 0, sizeof(float) * (size_t)(plan->n * b.Rp)) != hipSuccess ||
-      hipMemset(b.zshift, 0, sizeof(float) * (size_t)b.Rp) != hipSuccess)
+      hipMemset(b.Y32, 0, sizeof(float) * (size_t)(plan->n * b.Rp)) != hipSuccess)
     return RPCA_ERR_HIP;
   b.ready = true;
   return RPCA_OK;
@@ -1755,8 +1763,9 @@ rpca_status backward_alloc(rpca_plan_s* plan) {
 // Reverse sweep of Steps 1-6 (reading: exact derivative of the computed
 // function with G fixed).  Small steps in float64, passes over A on the
 // float32 panel kernels, the rank-R factors of dA = P Y^T assembled in float64
-// and their product formed on the float32 matrix cores (the forward panel
-// kernel with K = R, one 64-column tile of dA per block column), with
+// and their product formed from three-part bfloat16 splits of the float32
+// factors (six products per K-step on the bfloat16 matrix cores, one 128 x 128
+// tile of dA per block, the finiteness check in its epilogue), with
 //   P = [Q | a_0 Z_0 .. a_i Z_i | H^(0) .. H^(i-1)],  Y = [T_bar | X_0 .. X_i | X_bar_1 .. X_bar_i]
 // where Z_i = H_bar_i, Z_j = H_bar_j + A~ X_bar_{j+1}, X_bar_j = a_j A~^T Z_j, and
 // a_j are the positive block scales of the forward (constants: Q does not depend on them).
@@ -1786,8 +1795,7 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
 
   // ---- small SVD adjoint: T_bar = T B + V_bar S~^-1 W^T
   if (gU != nullptr)
-    RPCA_TRY(launch_xty(true, Q, L, L, false, gU, ldgu, k, m, plan->rps_g, plan->ns_g, plan->sgn, plan->gp, b.Wbar,
-                        st));
+    RPCA_TRY(launch_xty(true, Q, L, L, false, gU, ldgu, k, m, b.rps_x, b.ns_x, plan->sgn, b.xpart, b.Wbar, st));
   else
     RPCA_TRY(hipMemsetAsync(b.Wbar, 0, sizeof(double) * (size_t)L * k, st));
   if (gV != nullptr)
@@ -1810,20 +1818,29 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   // ---- T = A~^T Q:  Q_bar = G_U' W_k^T + A~ T_bar
   {
     if (center) RPCA_TRY(launch_dot_rows(dres, b.TbarT, ldx, n, L, plan->corr, st));
-    FwdArgs fa;
-    fa.A = A;
-    fa.lda = lda;
-    fa.m = m;
-    fa.n = n;
-    fa.shift = plan->shift;
-    fa.Xt = b.TbarT;
-    fa.ldx = ldx;
-    fa.ncols = L;
-    fa.corr = center ? plan->corr : nullptr;
-    fa.Z = b.Zf;
-    fa.ldz = L;
-    fa.vec = vec;
-    RPCA_TRY(launch_fwd_f32(fa, st));
+    // L columns as launches of at most 64 (the last one narrower: 32 columns of matrix-core
+    // work for a remainder of up to 32), each with the K split of the l-column products
+    for (int c0 = 0; c0 < L; c0 += 64) {
+      FwdArgs fa;
+      fa.A = A;
+      fa.lda = lda;
+      fa.m = m;
+      fa.n = n;
+      fa.shift = plan->shift;
+      fa.Xt = b.TbarT + (int64_t)c0 * ldx;
+      fa.ldx = ldx;
+      fa.ncols = L - c0 < 64 ? L - c0 : 64;
+      fa.corr = center ? plan->corr + c0 : nullptr;
+      fa.Z = b.Zf + c0;
+      fa.ldz = L;
+      fa.vec = vec;
+      fa.ksplit = plan->fwd_ks;
+      fa.kchunk = plan->fwd_kchunk;
+      fa.P = plan->Pf;
+      fa.ldp = plan->ldpf;
+      fa.split_stride = m * plan->ldpf;
+      RPCA_TRY(launch_fwd_f32(fa, st));
+    }
   }
   if (gU != nullptr) {
     RPCA_TRY(launch_gemm64(false, gU, ldgu, b.Bp, L, m, L, k, false, nullptr, b.Qbar, L, nullptr, 0, st));
@@ -1833,7 +1850,7 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   }
 
   // ---- QR adjoint: H_bar = (Q_bar + Q copyltu(-Q_bar^T Q)) R^-T, R = R2 R1 (R3 R2 R1 after the fallback)
-  RPCA_TRY(launch_xty(true, b.Qbar, L, L, true, Q, L, L, m, plan->rps_g, plan->ns_g, nullptr, plan->gp, b.M2, st));
+  RPCA_TRY(launch_xty(true, b.Qbar, L, L, true, Q, L, L, m, b.rps_x, b.ns_x, nullptr, b.xpart, b.M2, st));
   RPCA_TRY(launch_copyltu_neg(b.M2, L, b.Smat, st));
   RPCA_TRY(launch_gemm64(true, Q, L, b.Smat, L, m, L, L, false, nullptr, b.Qbar, L, nullptr, 0, st, b.Qbar, L));
   if (plan->stats.qr_fallback >= 2) {
@@ -1915,27 +1932,12 @@ extern "C" rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const fl
   // products on the bfloat16 matrix cores, float32 accumulation over K = R)
   RPCA_TRY(launch_to_f32(b.Pm, m, R, ldp, nullptr, b.P32, b.Rp, st));
   RPCA_TRY(launch_transpose_out(b.Yt, ldx, R, (int)n, b.Y32, nullptr, b.Rp, st));
-  RPCA_TRY(launch_split3_x(b.Y32, b.Rp, b.Rp, (int)n, b.cpady, b.Y3, b.ldy3, b.yplane3, st));
-  {
-    FwdArgs fa;
-    fa.A = b.P32;
-    fa.lda = b.Rp;
-    fa.m = m;
-    fa.n = b.Rp;
-    fa.shift = b.zshift;
-    fa.ncols = (int)n;
-    fa.Z = dA;
-    fa.ldz = ldda;
-    fa.vec = true;
-    fa.X3 = b.Y3;
-    fa.ldxs3 = b.ldy3;
-    fa.xplane3 = b.yplane3;
-    // a derivative that is not defined at this A (tied leading S~, or a Step 2 factor that is
-    // singular to working precision) shows as non-finite entries, flagged as they are written
-    RPCA_TRY(hipMemsetAsync(plan->flags + 4, 0, sizeof(int), st));
-    fa.nonfinite = plan->flags + 4;
-    RPCA_TRY(launch_fwd_x6(fa, st));
-  }
+  RPCA_TRY(launch_split3_rows(b.P32, b.Rp, m, R, b.mpad3, b.kp3, b.P3, st));
+  RPCA_TRY(launch_split3_rows(b.Y32, b.Rp, n, R, b.npad3, b.kp3, b.Y3, st));
+  // a derivative that is not defined at this A (tied leading S~, or a Step 2 factor that is
+  // singular to working precision) shows as non-finite entries, flagged as they are written
+  RPCA_TRY(hipMemsetAsync(plan->flags + 4, 0, sizeof(int), st));
+  RPCA_TRY(launch_outer_x6(b.P3, b.mpad3, b.Y3, b.npad3, b.kp3, m, n, dA, ldda, plan->flags + 4, st));
   int bad = 0;
   RPCA_TRY(hipMemcpyAsync(&bad, plan->flags + 4, sizeof(int), hipMemcpyDeviceToHost, st));
   RPCA_TRY(hipStreamSynchronize(st));

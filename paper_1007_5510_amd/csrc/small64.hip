@@ -222,19 +222,23 @@ hipError_t launch_gram(bool x_is_f64, const void* X, int64_t ldx, int64_t rows, 
   return hipGetLastError();
 }
 
-// 64 elements per block, 4 groups of threads each summing every 4th split, combined in a fixed order
+// 16 elements per block, 16 groups of threads each summing every 16th split, combined in a fixed order
 __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ part, int nsplit, int L,
                                                           double* __restrict__ W) {
-  __shared__ double sh[4][64];
-  const int t = threadIdx.x & 63, g = threadIdx.x >> 6;
+  __shared__ double sh[16][16];
+  const int t = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t LL = (int64_t)L * L;
-  const int64_t e = (int64_t)blockIdx.x * 64 + t;
+  const int64_t e = (int64_t)blockIdx.x * 16 + t;
   double s = 0.0;
   if (e < LL)
-    for (int k = g; k < nsplit; k += 4) s += part[(int64_t)k * LL + e];
+    for (int k = g; k < nsplit; k += 16) s += part[(int64_t)k * LL + e];
   sh[g][t] = s;
   __syncthreads();
-  if (g == 0 && e < LL) W[e] = (sh[0][t] + sh[1][t]) + (sh[2][t] + sh[3][t]);
+  if (g != 0 || e >= LL) return;
+  double tot = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) tot += sh[q][t];
+  W[e] = tot;
 }
 
 // diag += coef * trace(W)  (shift of the shifted Cholesky QR)
@@ -255,7 +259,7 @@ __global__ __launch_bounds__(256) void add_trace_shift_kernel(double* __restrict
 hipError_t launch_gram_reduce(const double* part, int nsplit, int L, double* W, double shift_coef,
                               hipStream_t st) {
   const int64_t LL = (int64_t)L * L;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((LL + 63) / 64)), dim3(256), 0, st, part, nsplit, L, W);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((LL + 15) / 16)), dim3(256), 0, st, part, nsplit, L, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || shift_coef == 0.0) return e;
   hipLaunchKernelGGL(add_trace_shift_kernel, dim3(1), dim3(256), 0, st, W, L, shift_coef);
