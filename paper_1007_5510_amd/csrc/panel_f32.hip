@@ -170,32 +170,51 @@ __global__ __launch_bounds__(256, MINB) void fwd32_kernel(
     }
   };
 
-  // whole stages: straight-line body, the prefetch after the last one re-reads it.
-  // The prologue's loads are waited for before the loop, so the loop header
-  // carries no wait on loads issued inside the loop.
+  // whole stages on two register stages of A used alternately (no copy between
+  // them, so a load has the whole next stage to arrive; the X loads of a stage
+  // are issued before its A loads, so storing X waits for X only).  The
+  // prologue's loads are waited for before the loop, so the loop header carries
+  // no wait on loads issued inside the loop; past the last whole stage the
+  // prefetch re-reads it.
   const int64_t nfull = (kend - kbeg) / KST;
   int it = 0;
+  auto step_done = [&]() {
+    if (++it == 128 / KST) {  // fold every 64 MFMA K-steps
+      it = 0;
+      fold();
+    }
+  };
   if (nfull > 0) {
-    AStage ac, an;
+    AStage a0, a1;
     XStage xr;
     load_x(xr, kbeg);
-    load_a(ac, kbeg);
+    load_a(a0, kbeg);
     store_x(xr, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    for (int64_t st = 0; st < nfull; ++st) {
-      const int64_t kn = kbeg + (st + 1 < nfull ? st + 1 : st) * KST;
-      load_x(xr, kn);
-      load_a(an, kn);
+    int64_t st = 0;
+    for (; st + 2 <= nfull; st += 2) {
+      const int64_t k1 = kbeg + (st + 1) * KST;
+      load_x(xr, k1);
+      load_a(a1, k1);
       __builtin_amdgcn_sched_barrier(0);
-      compute(ac, (int)(st & 1));
-      store_x(xr, (int)((st + 1) & 1));
+      compute(a0, 0);
+      store_x(xr, 1);
       __syncthreads();
-      ac = an;
-      if (++it == 128 / KST) {  // fold every 64 MFMA K-steps
-        it = 0;
-        fold();
-      }
+      step_done();
+      const int64_t k2 = kbeg + (st + 2 < nfull ? st + 2 : st + 1) * KST;
+      load_x(xr, k2);
+      load_a(a0, k2);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, 1);
+      store_x(xr, 0);
+      __syncthreads();
+      step_done();
+    }
+    if (st < nfull) {  // odd stage count: the last stage is in a0, X in buffer 0
+      compute(a0, 0);
+      __syncthreads();
+      step_done();
     }
   }
   // tail stage (fewer than KST columns left): masked loads
