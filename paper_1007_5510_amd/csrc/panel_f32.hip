@@ -25,8 +25,8 @@
 // Accuracy: the long sums are split (over K in the forward product, over
 // rows in the adjoint) and the split partial sums reduced in float64.  In the
 // forward product each float32 chain is limited to 64 MFMA K-steps and folded
-// into a second float32 level (a float outer level keeps the kernel within
-// 128 registers, four workgroups per CU); the adjoint keeps one float32 chain
+// into a second float32 level (a float outer level keeps the one-tile kernel
+// within 128 registers, four workgroups per CU); the adjoint keeps one float32 chain
 // per split (a few thousand rows), which frees the registers of a second
 // level and measured about 5% faster.
 //
@@ -78,6 +78,11 @@ RPCA_DEV floatx16 mfma32(float a, float b, floatx16 c) {
 }
 
 constexpr int F3_KST = 32;  // K per LDS stage of the launched configuration
+// workgroups per CU the launched forward kernels are sized for: one 32-column tile
+// fits four within 128 registers; two tiles at three (158 registers, no spills)
+// measured 2.8% faster than at four (128 registers, 19 spilled)
+template <int NT2>
+constexpr int FWD32_MINB = NT2 == 1 ? 4 : 3;
 
 // KST: K per LDS stage (32 or 64); NCH: independent accumulation chains per
 // output tile (consecutive MFMAs of one tile alternate between them); OT:
@@ -687,10 +692,10 @@ static hipError_t launch_fwd32(const FwdArgs& a, hipStream_t st) {
   const int64_t ldo = direct ? a.ldz : a.ldp;
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
   if (a.vec)
-    hipLaunchKernelGGL((fwd32_kernel<NT2, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
+    hipLaunchKernelGGL((fwd32_kernel<NT2, true, F3_KST, 1, float, FWD32_MINB<NT2>>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
                        a.Xt, a.ldx, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
   else
-    hipLaunchKernelGGL((fwd32_kernel<NT2, false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+    hipLaunchKernelGGL((fwd32_kernel<NT2, false, F3_KST, 1, float, FWD32_MINB<NT2>>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
                        a.shift, a.Xt, a.ldx, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride,
                        direct ? 1 : 0);
   hipError_t e = hipGetLastError();
