@@ -816,14 +816,26 @@ hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
   dim3 grid((unsigned)total);
   const bool vec = a.vec && (a.n % 4 == 0);
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
-  if (vec)
-    hipLaunchKernelGGL((adj_f32_kernel<4, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
-                       a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P, a.ldp,
-                       a.split_stride, a.ones ? 1 : 0);
-  else
-    hipLaunchKernelGGL((adj_f32_kernel<4, false>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
-                       a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jtiles, ctiles, a.P, a.ldp,
-                       a.split_stride, a.ones ? 1 : 0);
+  // up to 32 output columns (with the ones column): two 16-column tiles per wave instead of four,
+  // half the matrix-core work of the padded 64 (the narrow blocks of a small l are bound by the
+  // read of A, not by the matrix cores); identical sums, since every output column has its own chain
+  const bool narrow = a.ncols + (a.ones ? 1 : 0) <= 32;
+#define RPCA_ADJ(NT_, VEC_)                                                                               \
+  hipLaunchKernelGGL((adj_f32_kernel<NT_, VEC_, ADJ_RS, NT_ == 2 ? 3 : 2>), grid, dim3(256), 0, st,      \
+                     (const float*)a.A, a.lda, a.m, a.n, a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split,  \
+                     a.nsplit, jtiles, ctiles, a.P, a.ldp, a.split_stride, a.ones ? 1 : 0)
+  if (narrow) {
+    if (vec)
+      RPCA_ADJ(2, true);
+    else
+      RPCA_ADJ(2, false);
+  } else {
+    if (vec)
+      RPCA_ADJ(4, true);
+    else
+      RPCA_ADJ(4, false);
+  }
+#undef RPCA_ADJ
   hipError_t e = hipGetLastError();
   if (a.ev_end != nullptr) (void)hipEventRecord(a.ev_end, st);
   return e;
