@@ -78,11 +78,17 @@ RPCA_DEV floatx16 mfma32(float a, float b, floatx16 c) {
 }
 
 constexpr int F3_KST = 32;  // K per LDS stage of the launched configuration
-// workgroups per CU the launched forward kernels are sized for: one 32-column tile
-// fits four within 128 registers; two tiles at three (158 registers, no spills)
-// measured 2.8% faster than at four (128 registers, 19 spilled)
+// launched forward configurations, three workgroups per CU: two 32-column tiles
+// with 32 K per stage (158 registers, no spills; 2.8% faster than four workgroups
+// per CU at 128 registers with 19 spilled), one tile with 64 K per stage (161
+// registers: twice the bytes of A in flight per wave for the narrow, read-bound
+// products; 2-3% faster than 32 K at four workgroups per CU).  K chunks of the
+// split are multiples of 64 so that every stage of either is whole.
 template <int NT2>
-constexpr int FWD32_MINB = NT2 == 1 ? 4 : 3;
+constexpr int FWD32_MINB = 3;
+template <int NT2>
+constexpr int FWD32_KST = NT2 == 1 ? 64 : 32;
+constexpr int F3_KCHUNK = 64;
 
 // KST: K per LDS stage (32 or 64); NCH: independent accumulation chains per
 // output tile (consecutive MFMAs of one tile alternate between them); OT:
@@ -692,10 +698,10 @@ static hipError_t launch_fwd32(const FwdArgs& a, hipStream_t st) {
   const int64_t ldo = direct ? a.ldz : a.ldp;
   if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
   if (a.vec)
-    hipLaunchKernelGGL((fwd32_kernel<NT2, true, F3_KST, 1, float, FWD32_MINB<NT2>>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
+    hipLaunchKernelGGL((fwd32_kernel<NT2, true, FWD32_KST<NT2>, 1, float, FWD32_MINB<NT2>>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n, a.shift,
                        a.Xt, a.ldx, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride, direct ? 1 : 0);
   else
-    hipLaunchKernelGGL((fwd32_kernel<NT2, false, F3_KST, 1, float, FWD32_MINB<NT2>>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+    hipLaunchKernelGGL((fwd32_kernel<NT2, false, FWD32_KST<NT2>, 1, float, FWD32_MINB<NT2>>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
                        a.shift, a.Xt, a.ldx, a.ncols, kchunk, a.corr, a.alpha, out, ldo, a.split_stride,
                        direct ? 1 : 0);
   hipError_t e = hipGetLastError();
@@ -732,7 +738,7 @@ void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk
   int best = 1;
   double best_eff = 0.0;
   for (int s = 1; s <= 8; ++s) {
-    const int64_t chunk = ((n + s - 1) / s + F3_KST - 1) / F3_KST * F3_KST;
+    const int64_t chunk = ((n + s - 1) / s + F3_KCHUNK - 1) / F3_KCHUNK * F3_KCHUNK;
     const int64_t ns = (n + chunk - 1) / chunk;
     const int64_t blocks = rt * ns;
     const int64_t rounds = (blocks + slots - 1) / slots;
@@ -743,7 +749,7 @@ void fwd_split(int64_t m, int64_t n, int64_t slots, int* ksplit, int64_t* kchunk
     }
     if (eff >= 0.94) break;
   }
-  const int64_t chunk = ((n + best - 1) / best + F3_KST - 1) / F3_KST * F3_KST;
+  const int64_t chunk = ((n + best - 1) / best + F3_KCHUNK - 1) / F3_KCHUNK * F3_KCHUNK;
   *ksplit = (int)((n + chunk - 1) / chunk);
   *kchunk = chunk;
 }
