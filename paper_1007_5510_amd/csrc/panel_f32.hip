@@ -510,7 +510,7 @@ typedef float adjw_f2 __attribute__((ext_vector_type(2)));
 constexpr int ADJW_ACOLS = 128;  // A columns per block
 
 // Z tiles per block of the wide-Z adjoint for ncols columns (host side: launcher and split rule)
-static inline int adjw_tiles(int ncols) { return ncols <= 128 ? 8 : 12; }
+static inline int adjw_tiles(int ncols) { return ncols <= 96 ? 6 : (ncols <= 128 ? 8 : 12); }
 
 template <int NT, bool VEC>
 __global__ __launch_bounds__(256, 2) void adj_wide_kernel(
@@ -518,8 +518,11 @@ __global__ __launch_bounds__(256, 2) void adj_wide_kernel(
     const float* __restrict__ Z, int64_t ldz, int ncols, int64_t rows_per_split, int nsplit, int jtiles,
     int ctiles, float* __restrict__ P, int64_t ldp, int64_t split_stride) {
   constexpr int RS = ADJ_RS;
-  constexpr int ZCOLS = 16 * NT;  // Z columns per block
-  constexpr int ZH = NT / 4;      // 4-column Z pieces per thread per stage (16 threads per row)
+  constexpr int ZCOLS = 16 * NT;            // Z columns per block
+  constexpr int PW = NT % 4 == 0 ? 4 : 2;   // columns per Z piece (16 or 8 bytes)
+  constexpr int ZH = NT / PW;               // Z pieces per thread per stage (16 threads per row)
+  typedef float zpiece_t __attribute__((ext_vector_type(PW)));
+  static_assert(NT % 2 == 0, "Z pieces of 2 or 4 columns");
   __shared__ __attribute__((aligned(16))) float Zs[2][RS][16][NT];
   const int64_t total = (int64_t)jtiles * ctiles * nsplit;
   const int64_t logical = xcd_remap(blockIdx.x, total);
@@ -547,16 +550,16 @@ __global__ __launch_bounds__(256, 2) void adj_wide_kernel(
     return v;
   };
   const adjw_f2 sh = ld2(shift);
-  // cooperative Z loader: thread -> row zr of the stage, ZH 4-column pieces at columns
-  // 4 (ZH (tid % 16) + h); a piece past the last real column re-reads the last piece (its
-  // products land in columns that are never stored).  Element cc of the stage row goes to
-  // LDS slot [zr][cc % 16][cc / 16].
+  // cooperative Z loader: thread -> row zr of the stage, ZH PW-column pieces at columns
+  // PW (ZH (tid % 16) + h); a piece past the last real column re-reads the last piece (its
+  // products land in columns that are never stored; ncols is a multiple of 4, so no piece
+  // straddles it).  Element cc of the stage row goes to LDS slot [zr][cc % 16][cc / 16].
   const int zr = tid >> 4;
   int zcol[ZH], zslot[ZH];
 #pragma unroll
   for (int h = 0; h < ZH; ++h) {
-    const int cc = 4 * (ZH * (tid & 15) + h);
-    zcol[h] = j0 + cc + 4 <= ncols ? j0 + cc : ncols - 4;
+    const int cc = PW * (ZH * (tid & 15) + h);
+    zcol[h] = j0 + cc + PW <= ncols ? j0 + cc : ncols - PW;
     zslot[h] = zr * (16 * NT) + (cc & 15) * NT + (cc >> 4);
   }
 
@@ -569,7 +572,7 @@ __global__ __launch_bounds__(256, 2) void adj_wide_kernel(
     adjw_f2 a[RS / 4];
   };
   struct ZStage {
-    floatx4 z[ZH];
+    zpiece_t z[ZH];
   };
   auto load_a = [&](AStage& b, int64_t rb) {
 #pragma unroll
@@ -578,28 +581,28 @@ __global__ __launch_bounds__(256, 2) void adj_wide_kernel(
   auto load_z = [&](ZStage& b, int64_t rb) {
     const float* zrow = Z + (rb + zr) * ldz;
 #pragma unroll
-    for (int h = 0; h < ZH; ++h) b.z[h] = *reinterpret_cast<const floatx4*>(zrow + zcol[h]);
+    for (int h = 0; h < ZH; ++h) b.z[h] = *reinterpret_cast<const zpiece_t*>(zrow + zcol[h]);
   };
-  // columns cc .. cc + 3 of a piece share the tile cc / 16 and take slots p = cc % 16 .. + 3
+  // columns cc .. cc + PW - 1 of a piece share the tile cc / 16 and take slots p = cc % 16 ..
   auto store_z = [&](const ZStage& b, int buf) {
     float* base = &Zs[buf][0][0][0];
 #pragma unroll
     for (int h = 0; h < ZH; ++h)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) base[zslot[h] + e * NT] = b.z[h][e];
+      for (int e = 0; e < PW; ++e) base[zslot[h] + e * NT] = b.z[h][e];
   };
   auto compute = [&](const AStage& b, int buf) {
 #pragma unroll
     for (int q = 0; q < RS / 4; ++q) {
-      const floatx4* zp = reinterpret_cast<const floatx4*>(&Zs[buf][4 * q + kk][p][0]);
-      floatx4 z[ZH];
+      const zpiece_t* zp = reinterpret_cast<const zpiece_t*>(&Zs[buf][4 * q + kk][p][0]);
+      zpiece_t z[ZH];
 #pragma unroll
       for (int h = 0; h < ZH; ++h) z[h] = zp[h];
       const adjw_f2 a = b.a[q] - sh;
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[v][t] = mfma4(a[v], z[t >> 2][t & 3], acc[v][t]);
+        for (int t = 0; t < NT; ++t) acc[v][t] = mfma4(a[v], z[t / PW][t % PW], acc[v][t]);
       }
     }
   };
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(256, 2) void adj_wide_kernel(
       load_z(zt, rt);
     } else {
 #pragma unroll
-      for (int h = 0; h < ZH; ++h) zt.z[h] = floatx4{0.f, 0.f, 0.f, 0.f};
+      for (int h = 0; h < ZH; ++h) zt.z[h] = zpiece_t(0.f);
     }
     store_z(zt, buf);
     AStage at;
@@ -806,7 +809,10 @@ hipError_t launch_adj_f32(const AdjArgs& a, hipStream_t st) {
     const int ct = (int)((a.n + ADJW_ACOLS - 1) / ADJW_ACOLS);
     const dim3 grid((unsigned)((int64_t)jt * ct * a.nsplit));
     if (a.ev_begin != nullptr) (void)hipEventRecord(a.ev_begin, st);
-    if (nt == 8)
+    if (nt == 6)
+      hipLaunchKernelGGL((adj_wide_kernel<6, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
+                         a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jt, ct, a.P, a.ldp, a.split_stride);
+    else if (nt == 8)
       hipLaunchKernelGGL((adj_wide_kernel<8, true>), grid, dim3(256), 0, st, (const float*)a.A, a.lda, a.m, a.n,
                          a.shift, a.Z, a.ldz, a.ncols, a.rows_per_split, a.nsplit, jt, ct, a.P, a.ldp, a.split_stride);
     else
