@@ -256,11 +256,16 @@ rpca_status rpca_factor(rpca_plan_t plan, const void* A, int64_t lda, const floa
  * preceding rpca_factor with RPCA_FLAG_KEEP_STATE and the same A still valid.
  *   gS  (k), gU (m x k, ldgu), gV (n x k, ldgv): device cotangents of S, U, V
  *       (any may be NULL = zero).
- *   dA  (m x n, ldda): device floats receiving dL/dA.
+ *   dA  (m x n, ldda): device floats receiving dL/dA, formed as P Y^T from
+ *       rank-(3i+2)l float64 factors rounded to float32, with float32-level
+ *       products (three-part bfloat16 splits, six products per term).
  * The first call allocates the reverse-sweep workspace, kept until
  * rpca_destroy.  Blocks the calling thread until dA is written.
  * Errors: NO_STATE, INVALID_ARG, UNSUPPORTED (storage other than F32,
- * streamed sources), OUT_OF_MEMORY, HIP.                                   */
+ * streamed sources), OUT_OF_MEMORY, NONFINITE (an entry of dA is not finite:
+ * the derivative is not defined at this A, e.g. tied leading singular values
+ * or a Step 2 factor singular to working precision; dA is still written),
+ * HIP.                                                                     */
 rpca_status rpca_backward(rpca_plan_t plan, const float* gS, const float* gU, int64_t ldgu,
                           const float* gV, int64_t ldgv, float* dA, int64_t ldda);
 
