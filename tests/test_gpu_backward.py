@@ -78,6 +78,29 @@ def test_backward_matches_oracle(center, i):
         assert abs(fd - an) <= 1e-4 * abs(fd)
 
 
+@pytest.mark.parametrize("m,n,k,l,i,center", [(257, 129, 3, 5, 1, False), (700, 300, 6, 10, 2, True),
+                                              (1500, 700, 10, 36, 1, False)])
+def test_backward_ragged_tiles(m, n, k, l, i, center):
+    """Shapes that end the dense dA product in ragged 256-row and 256-column tiles (one row of the
+    second row tile at 257; n below one column tile), with K = (3i + 2) l padded to a multiple of 32
+    (25 -> 32, 80 -> 96, 180 -> 192), and a 72-column T pass on the six-tile wide adjoint: dA against
+    the float64 oracle gradient."""
+    _need_gpu()
+    sigma = 2.0 * 0.95 ** np.arange(n, dtype=np.float64)
+    prob = F.svd_problem(5160 + m, m, n, sigma)
+    A32 = prob["A"].astype(np.float32)
+    if center:
+        A32 = (A32 + np.linspace(0, 1, n, dtype=np.float32)[None, :]).astype(np.float32)
+    G = F.gaussian_G(5161 + m, n, l)
+    gS, gU, gV = _cotangents(5162 + m, m, n, k)
+    ref = B.gradient(A32.astype(np.float64), k, l, i, G.astype(np.float64), center, gS, gU, gV)
+    got, _ = _gpu_grad(A32, k, l, i, G, center, gS, gU, gV)
+    assert np.isfinite(got).all()
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  {m} x {n}, k={k} l={l} i={i} center={center}: rel {rel:.3e}")
+    assert rel < 1e-4
+
+
 def test_backward_partial_cotangents():
     """Any of gS, gU, gV may be absent (zero)."""
     _need_gpu()
