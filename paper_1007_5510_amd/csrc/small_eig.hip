@@ -255,8 +255,12 @@ __global__ __launch_bounds__(TRD_THREADS) void tridiag_kernel(const double* __re
 #pragma unroll
       for (int q = 0; q < TRD_WAVES; ++q) tot += red[q];
       const double kdot = 0.5 * tj * tot;
-      // A22 -= v w^T + w v^T with w = p - kdot v; one wave per column
-      for (int k = r0 + wave; k < L; k += TRD_WAVES) {
+      // A22 -= v w^T + w v^T with w = p - kdot v; one wave per column.  The wave that
+      // builds reflector j+1 from column r0 takes no other column, so the reflector (on the
+      // critical path of the next step) overlaps the other waves' column updates
+      const int kfirst = next ? (wave == 0 ? r0 : r0 + wave) : r0 + wave;
+      const int kstep = next ? (wave == 0 ? L : TRD_WAVES - 1) : TRD_WAVES;
+      for (int k = kfirst; k < L; k += kstep) {
         const int ok = poff(k, L) - k;
         const double vk = v[k], wk = p[k] - kdot * vk;
         if (next && k == r0) {  // first trailing column: keep it and build reflector j+1
