@@ -72,20 +72,23 @@ hipError_t launch_colsum(int storage, const void* X, int64_t ld, int64_t rows, i
   return hipGetLastError();
 }
 
-// 64 columns per block, 4 groups of threads each summing every 4th split, combined in a fixed order
+// 16 columns per block, 16 groups of threads each summing every 16th split (a split count of
+// several hundred leaves each thread a short chain), combined in a fixed order
 __global__ __launch_bounds__(256) void colsum_reduce_kernel(const double* __restrict__ part, int nsplit,
                                                             int64_t cols, double scale, double* __restrict__ out,
                                                             float* __restrict__ out32, double* __restrict__ resid) {
-  __shared__ double sh[4][64];
-  const int t = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int64_t c = (int64_t)blockIdx.x * 64 + t;
+  __shared__ double sh[16][16];
+  const int t = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t c = (int64_t)blockIdx.x * 16 + t;
   double s = 0.0;
   if (c < cols)
-    for (int k = g; k < nsplit; k += 4) s += part[(int64_t)k * cols + c];
+    for (int k = g; k < nsplit; k += 16) s += part[(int64_t)k * cols + c];
   sh[g][t] = s;
   __syncthreads();
   if (g != 0 || c >= cols) return;
-  s = ((sh[0][t] + sh[1][t]) + sh[2][t]) + sh[3][t];
+  s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s += sh[q][t];
   s *= scale;
   out[c] = s;
   if (out32 != nullptr) {
@@ -97,7 +100,7 @@ __global__ __launch_bounds__(256) void colsum_reduce_kernel(const double* __rest
 
 hipError_t launch_colsum_reduce(const double* part, int nsplit, int64_t cols, double scale, double* out,
                                 float* out_f32, double* resid, hipStream_t st) {
-  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((unsigned)((cols + 63) / 64)), dim3(256), 0, st, part, nsplit, cols,
+  hipLaunchKernelGGL(colsum_reduce_kernel, dim3((unsigned)((cols + 15) / 16)), dim3(256), 0, st, part, nsplit, cols,
                      scale, out, out_f32, resid);
   return hipGetLastError();
 }
