@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void reduce_y_kernel(const TP* __restrict__ P,
   if (c < n) {
     double v = 0.0;
     const TP* p = P + (int64_t)j * ldp + c;
-    for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+    v += sum_strided(p, nsplit, split_stride);
     if (cs != nullptr) v *= (double)cs[c];
     if (d != nullptr) v -= d[c] * zsum[j];
     const float f = (float)v;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void reduce_t_kernel(const TP* __restrict__ P,
   if (c >= n) return;
   double v = 0.0;
   const TP* p = P + (int64_t)j * ldp + c;
-  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  v += sum_strided(p, nsplit, split_stride);
   if (cs != nullptr) v *= (double)cs[c];
   if (d != nullptr) v -= d[c] * qsum[j];
   T[c * ldt + j] = v;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void pass0_center_kernel(const float* __restri
   if (c >= n) return;
   double v = 0.0;
   const float* p = P + (int64_t)row * ldp + c;
-  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  v += sum_strided(p, nsplit, split_stride);
   const double d = v * inv_m;
   const double u = (double)shift[c] + d;
   const float s1 = (float)u;
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void pass0_mean_lp_kernel(const float* __restr
   if (c >= n) return;
   double v = 0.0;
   const float* p = P + (int64_t)row * ldp + c;
-  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  v += sum_strided(p, nsplit, split_stride);
   if (cs != nullptr) v *= (double)cs[c];
   mu[c] = v * inv_m;
 }
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void accumulate_parts_kernel(const TP* __restr
   if (c >= cols || r >= rows) return;
   double v = 0.0;
   const TP* p = part + r * ld + c;
-  for (int s = 0; s < nsplit; ++s) v += (double)p[(int64_t)s * split_stride];
+  v += sum_strided(p, nsplit, split_stride);
   acc[r * ld + c] += v;
 }
 

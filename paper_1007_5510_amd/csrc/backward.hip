@@ -376,8 +376,7 @@ __global__ void sub_colmean_kernel(double* __restrict__ X, int64_t ldx, int64_t 
   const int c0 = blockIdx.y * 256;
   const int c = c0 + threadIdx.x;
   if (c < cols) {
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * cols + c];
+    const double s = sum_strided(part + c, nsplit, (int64_t)cols);
     mean[threadIdx.x] = s * inv_rows;
   }
   __syncthreads();

@@ -61,6 +61,24 @@ RPCA_DEV double normal_elem(uint64_t seed, uint32_t stream, uint64_t e) {
 // ---------------------------------------------------------------------------
 // wave64 reductions (DPP/permute via __shfl_xor)
 // ---------------------------------------------------------------------------
+// sum_{s < ns} p[s * stride] in float64, in order of s; the loads go out eight at a time
+// (a plain loop waits for each load before the next add)
+template <typename T>
+RPCA_DEV double sum_strided(const T* __restrict__ p, int ns, int64_t stride) {
+  double v = 0.0;
+  for (int s = 0; s < ns; s += 8) {
+    // the last batch re-reads entry ns - 1 in its unused slots (no branch around the
+    // loads, which would make them wait one by one) and adds only the real entries
+    T x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = p[(int64_t)(s + u < ns ? s + u : ns - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s + u < ns) v += (double)x[u];
+  }
+  return v;
+}
+
 RPCA_DEV double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void fwd64_reduce_kernel(const double* __restr
   const int64_t r = e / ncols;
   const int c = (int)(e % ncols);
   double v = 0.0;
-  for (int s = 0; s < nsplit; ++s) v += P[(int64_t)s * split_stride + r * ldp + c];
+  v += sum_strided(P + r * ldp + c, nsplit, split_stride);
   if (corr != nullptr) v -= corr[c];
   Z[r * ldz + c] = (alpha_ptr != nullptr ? *alpha_ptr : 1.0) * v;
 }
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(256) void reduce_x64_kernel(const double* __restric
   if (c < n) {
     const double* p = P + (int64_t)j * ldp + c;
     double v = 0.0;
-    for (int s = 0; s < nsplit; ++s) v += p[(int64_t)s * split_stride];
+    v += sum_strided(p, nsplit, split_stride);
     if (d != nullptr) v -= d[c] * zsum[j];
     Xt[(int64_t)j * ldx + c] = v;
     sq = v * v;

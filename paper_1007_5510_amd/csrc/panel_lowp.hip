@@ -468,7 +468,7 @@ __global__ __launch_bounds__(256) void fwd_lp_reduce_kernel(const float* __restr
   const int64_t r = e / ncols;
   const int c = (int)(e % ncols);
   double v = 0.0;
-  for (int s = 0; s < nsplit; ++s) v += (double)P[(int64_t)s * split_stride + r * ldp + c];
+  v += sum_strided(P + r * ldp + c, nsplit, split_stride);
   const double alpha = alpha_ptr != nullptr ? *alpha_ptr : 1.0;
   const double cr = corr != nullptr ? (double)corr[c] : 0.0;
   Z[r * ldz + c] = (float)(alpha * (v - cr));
