@@ -156,8 +156,21 @@ __global__ __launch_bounds__(256) void dot_rows_kernel(const double* __restrict_
   __shared__ double sh[4];
   const int j = blockIdx.x;
   const float* x = Xt + (int64_t)j * ldx;
+  // the loads of four strides go out together; the products are added in the same order
   double s = 0.0;
-  for (int64_t c = threadIdx.x; c < n; c += 256) s += d[c] * (double)x[c];
+  int64_t c = threadIdx.x;
+  for (; c + 768 < n; c += 1024) {
+    double dv[4];
+    float xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      dv[u] = d[c + 256 * u];
+      xv[u] = x[c + 256 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += dv[u] * (double)xv[u];
+  }
+  for (; c < n; c += 256) s += d[c] * (double)x[c];
   s = block_sum_256(s, sh);
   if (threadIdx.x == 0) corr[j] = (float)s;
 }
