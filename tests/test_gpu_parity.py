@@ -335,12 +335,12 @@ def test_cholesky_qr_wide(m, n, k, l, i, decay, levels):
     assert np.abs(Q.T @ Q - np.eye(L)).max() < 1e-13
 
 
-@pytest.mark.parametrize("k,l,i", [(20, 40, 2), (16, 24, 2), (20, 44, 1)])
+@pytest.mark.parametrize("k,l,i", [(20, 40, 2), (16, 24, 2), (20, 44, 1), (50, 60, 2)])
 def test_wide_t_pass_matches_fallback_bitwise(k, l, i):
-    """The T pass with L = 120 (8 tiles of 16 columns), 72 or 88 (6 tiles, 8-byte Z pieces) runs on
-    the wide-Z adjoint when A's rows allow vector loads and on the 64-column adjoint otherwise; both
-    sum every output over the same rows in the same order, so the same matrix with an aligned and
-    with an odd leading dimension factors to identical bits."""
+    """The T pass with L = 120 (8 tiles of 16 columns), 180 (12 tiles), 72 or 88 (6 tiles, 8-byte Z
+    pieces) runs on the wide-Z adjoint when A's rows allow vector loads and on the 64-column adjoint
+    otherwise; both sum every output over the same rows in the same order, so the same matrix with an
+    aligned and with an odd leading dimension factors to identical bits."""
     m, n = 6000, 1000
     sigma = 0.9 ** np.arange(n, dtype=np.float64)
     p = F.svd_problem(6100, m, n, sigma)
